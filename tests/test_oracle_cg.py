@@ -1,0 +1,112 @@
+"""Pins of the oracle's CG (Algorithm 1) and right-hand side.
+
+Closed form: one N=2 element gives u_centre = pi^2/8 in one iteration
+(tests/golden/single_element_N2.txt).  Brute force: CG equals a dense
+Cholesky solve of the assembled, Dirichlet-restricted system.  Convergence:
+the manufactured solution u = sin(pi x) sin(pi y) sin(pi z) is approached
+spectrally as N grows.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from dense_reference import assemble
+from seminputs import box_mesh, random_global_rhs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_single():
+    vals = {}
+    with open(os.path.join(GOLDEN, "single_element_N2.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, v = [s.strip() for s in line.split("=")]
+            vals[k] = eval(v, {"pi": math.pi, "__builtins__": {}})
+    return vals
+
+
+def test_single_element_pi_squared_over_8():
+    g = _golden_single()
+    mesh = box_mesh(1, 1, 1, 2)
+    pr = oracle.Problem(mesh)
+    b, _ = pr.rhs_manufactured()
+    x, it, hist = pr.cg(b, tol=1e-14, max_iter=10)
+    centre = 1 + 3 * (1 + 3 * 1)
+    assert it == g["iterations"]
+    assert abs(x[centre] - g["u_centre"]) < 1e-14
+    others = np.delete(x, centre)
+    assert np.all(others == 0.0)
+
+
+@pytest.mark.parametrize("N,shape,perturb", [(2, (2, 2, 2), 0.1), (3, (2, 2, 1), 0.1),
+                                             (4, (2, 1, 2), 0.1), (3, (3, 2, 2), 0.0)])
+def test_cg_equals_dense_cholesky(N, shape, perturb):
+    mesh = box_mesh(*shape, N, perturb=perturb, seed=13, reorient=True, permute=True)
+    pr = oracle.Problem(mesh)
+    b, _ = pr.rhs_manufactured()
+    x, it, hist = pr.cg(b, tol=1e-13, max_iter=2000)
+    A, Bg, Xg, Xl, Bl = assemble(mesh.vert, mesh.glob_id, mesh.n_glob, N)
+    fg = 3 * math.pi ** 2 * np.prod(np.sin(math.pi * Xg), axis=1)
+    bg = Bg * fg
+    free = np.ones(mesh.n_glob, dtype=bool)
+    free[mesh.glob_id.ravel()[mesh.dirichlet.ravel() != 0]] = False
+    Aff = A[np.ix_(free, free)]
+    L = np.linalg.cholesky(Aff)
+    xf = np.linalg.solve(L.T, np.linalg.solve(L, bg[free]))
+    xg = np.zeros(mesh.n_glob)
+    xg[free] = xf
+    ref = xg[mesh.glob_id.ravel()]
+    assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
+    # CG converges within the number of free unknowns (exact arithmetic bound)
+    assert it <= int(free.sum()) + 5
+    # the recursive residual estimate matches the true residual
+    assert pr.true_rel_residual(b, x) < 1e-11
+
+
+def test_cg_recurrences_are_consistent():
+    # rho_i = <r_i, r_i, c>, beta_i = rho_i / rho_{i-1}; alpha_i > 0 (SPD)
+    mesh = box_mesh(2, 2, 2, 4, perturb=0.1, seed=2)
+    pr = oracle.Problem(mesh)
+    b = random_global_rhs(mesh, seed=3)
+    x, it, h = pr.cg(b, fixed=12)
+    assert it == 12
+    rho, alpha, beta = h["rho"], h["alpha"], h["beta"]
+    np.testing.assert_allclose(beta[1:], rho[1:] / rho[:-1], rtol=1e-14)
+    assert np.all(alpha[1:] > 0)
+    # x solves A x = b - r: check the recursive residual is the true one
+    r_true = b - pr.apply_A(x)
+    assert abs(pr.dot(r_true, r_true) - rho[-1]) <= 1e-8 * rho[0]
+
+
+def test_cg_zero_rhs_returns_zero():
+    mesh = box_mesh(2, 1, 1, 3)
+    pr = oracle.Problem(mesh)
+    x, it, _ = pr.cg(np.zeros(mesh.n_local), tol=1e-8)
+    assert it == 0 and np.all(x == 0)
+
+
+def test_manufactured_solution_spectral_convergence():
+    errs = []
+    for N in (3, 5, 7):
+        mesh = box_mesh(4, 4, 4, N)
+        pr = oracle.Problem(mesh)
+        b, u = pr.rhs_manufactured()
+        x, it, _ = pr.cg(b, tol=1e-12, max_iter=5000)
+        errs.append(np.max(np.abs(x - u)))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-5
+    # spectral: each step of 2 in N gains more than a factor 10
+    assert errs[1] < errs[0] / 10 and errs[2] < errs[1] / 10
+
+
+def test_manufactured_solution_deformed_mesh():
+    mesh = box_mesh(3, 3, 3, 6, perturb=0.1, seed=2108, reorient=True)
+    pr = oracle.Problem(mesh)
+    b, u = pr.rhs_manufactured()
+    x, it, _ = pr.cg(b, tol=1e-12, max_iter=5000)
+    assert np.max(np.abs(x - u)) < 1e-4
