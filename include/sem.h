@@ -1,0 +1,216 @@
+/*
+ * sem.h -- C ABI of the MI355X (gfx950) spectral-element Poisson CG library.
+ *
+ * The library implements the per-iteration hot path of the unpreconditioned
+ * SEM conjugate-gradient solver of Karp et al., "A High-Fidelity Flow Solver
+ * for Unstructured Meshes on Field-Programmable Gate Arrays" (HPC Asia 2022,
+ * arXiv 2108.12188): the matrix-free local operator A_L (Sec. 3, Eq. 4-5),
+ * gather-scatter QQ^T with Dirichlet masking (Sec. 3.1, Sec. 4.3) and the
+ * CG vector updates and weighted reductions of Algorithm 1, with the
+ * geometric factors either precomputed or recomputed on the fly from the
+ * element vertices (Sec. 5.1, Eq. 13-14).
+ *
+ * General conventions
+ *   - Order N, P = N + 1, P3 = P^3 local points per element; N in [1, 11].
+ *   - Local (replicated) vectors have n_local = E * P3 entries, element-major,
+ *     local point l = i + P*(j + P*k) inside an element (i fastest).  This is
+ *     the "local representation u_L = Q u" of Sec. 3.1.
+ *   - Vectors passed as `void*` are caller-owned DEVICE buffers of n_local
+ *     entries of the precision named by the call (double for SEM_FP64 and
+ *     SEM_MIXED, float for SEM_FP32), at least 16-byte aligned.  The mesh
+ *     handle owns every other device array and frees it in
+ *     sem_mesh_destroy.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Every call
+ *     except sem_mesh_create, sem_cg_solve and the batch solve is
+ *     stream-ordered and returns before the work finishes.
+ *   - No C++ exception crosses this boundary.  On an error the call returns
+ *     a negative sem_status, leaves its outputs untouched, and
+ *     sem_last_error() returns a message for the calling thread.
+ *   - Calls that use the same mesh handle on overlapping streams race on the
+ *     handle's internal work vectors; serialise them.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_mesh_s *sem_mesh_t;
+typedef struct sem_batch_s *sem_batch_t;
+
+typedef enum {
+    SEM_OK = 0,
+    SEM_EINVAL = -1,       /* bad argument (NULL pointer, size, inconsistent mesh) */
+    SEM_ENOMEM = -2,       /* device allocation failed */
+    SEM_EDEVICE = -3,      /* a HIP runtime call failed */
+    SEM_EJACOBIAN = -4,    /* |J| <= 0 at some GLL point; message names the element */
+    SEM_EBREAKDOWN = -5,   /* CG breakdown: <p,w,c> <= 0 or a non-finite scalar */
+    SEM_EUNSUPPORTED = -6  /* order, precision/geometry form or size not built */
+} sem_status;
+
+typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_MIXED = 2 } sem_precision;
+typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
+
+/* sem_mesh_create flags: which precomputed geometric-factor arrays to keep.
+ * The on-the-fly form needs none of them (it reads the vertices). */
+#define SEM_MESH_G_FP32 0x1u   /* G as float [E][6][P3]  (24 B per point)  */
+#define SEM_MESH_G_FP64 0x2u   /* G as double [E][6][P3] (48 B per point)  */
+
+/*
+ * Build a mesh on the current HIP device (Sec. 3: decomposition into E
+ * hexahedra with a tensor GLL basis of order N; Sec. 3.1: the scatter map Q).
+ *   n_elem     E > 0.
+ *   order_N    N in [1, 11].
+ *   vert_xyz   HOST double [E][8][3]: element vertices; vertex a + 2b + 4c sits
+ *              at reference corner (xi, eta, gamma) = (2a-1, 2b-1, 2c-1).
+ *              Elements are trilinear ("linearly deformed", Sec. 5.1).
+ *   glob_id    HOST int64 [E][P3]: global point of every local point (this is
+ *              Q).  Ids are >= 0; points with equal id are summed by the
+ *              gather-scatter.  Every id in [0, max id] need not be used.
+ *   dirichlet  HOST uint8 [E][P3]: 1 on the Dirichlet boundary; must be equal
+ *              on all copies of a global point.  May be NULL (no boundary).
+ *   flags      bit set of SEM_MESH_G_FP32 / SEM_MESH_G_FP64.
+ *   out        receives the handle.
+ * Copies what it needs; the host arrays may be freed on return.  Blocks until
+ * the device-side setup (geometric factors, Jacobian check) has finished.
+ * Errors: SEM_EINVAL (NULL, E <= 0, bad ids, inconsistent Dirichlet flags,
+ * more than 255 copies of a point, n_local >= 2^31), SEM_EUNSUPPORTED (N out
+ * of range), SEM_EJACOBIAN, SEM_ENOMEM, SEM_EDEVICE.
+ */
+sem_status sem_mesh_create(int64_t n_elem, int order_N, const double *vert_xyz,
+                           const int64_t *glob_id, const uint8_t *dirichlet,
+                           uint32_t flags, void *hip_stream, sem_mesh_t *out);
+
+/* Free every device array of the mesh (synchronises the device). NULL is a no-op. */
+void sem_mesh_destroy(sem_mesh_t mesh);
+
+typedef struct {
+    int64_t n_elem;        /* E */
+    int32_t order_N;       /* N */
+    int64_t n_local;       /* E * P3 (the paper's n, Eq. 7) */
+    int64_t n_glob;        /* distinct global points */
+    int64_t n_shared;      /* local points with multiplicity > 1 */
+    int64_t n_groups;      /* global points with multiplicity > 1 */
+    int64_t n_dirichlet;   /* local points on the Dirichlet boundary */
+    size_t device_bytes;   /* device memory held by the handle */
+} sem_mesh_info_t;
+
+sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);
+
+/*
+ * Local operator, no gather-scatter, no mask (Eq. 4-5: w_e = D^T G^e D u_e
+ * for every element e).  prec: SEM_FP32 or SEM_FP64 (buffers of that type).
+ * geom: SEM_G_PRECOMPUTED reads the G array of that precision (it must have
+ * been requested at mesh creation, else SEM_EUNSUPPORTED); SEM_G_ON_THE_FLY
+ * recomputes G at every point from the 8 vertices ("rematerialization",
+ * Sec. 5.1).  u and w must not overlap.
+ */
+sem_status sem_ax(sem_mesh_t mesh, sem_precision prec, sem_geom geom,
+                  const void *u_dev, void *w_dev, void *hip_stream);
+
+/*
+ * In-place gather-scatter w <- QQ^T w (Sec. 3.1 and 4.3): every copy of a
+ * global point receives the sum of all copies, summed in ascending local
+ * index.  apply_mask = 1 then zeroes the Dirichlet points (Algorithm 1, mask
+ * step).  prec: SEM_FP32 or SEM_FP64.
+ */
+sem_status sem_gs(sem_mesh_t mesh, sem_precision prec, void *w_dev, int apply_mask,
+                  void *hip_stream);
+
+/*
+ * Weighted inner product <a, b, c> = sum_l a_l b_l c_l with c_l = 1/m_l, m_l
+ * the multiplicity of local point l (Algorithm 1; c removes the replicated
+ * copies).  Accumulates in FP64 in a fixed order (deterministic).  Writes one
+ * double to the DEVICE pointer out_dev.  prec: SEM_FP32 or SEM_FP64.
+ */
+sem_status sem_dot(sem_mesh_t mesh, sem_precision prec, const void *a_dev,
+                   const void *b_dev, double *out_dev, void *hip_stream);
+
+/*
+ * Physical coordinates of every local GLL point: xyz_dev is a DEVICE double
+ * buffer [3][n_local] (x block, then y, then z).
+ */
+sem_status sem_coords(sem_mesh_t mesh, double *xyz_dev, void *hip_stream);
+
+/*
+ * Right-hand side of the weak form, Eq. 2: b = mask(QQ^T (B f)) with B the
+ * diagonal GLL mass (w_q |J_q|) and f DEVICE double [n_local] the source at
+ * every local point.  b: n_local entries of prec (SEM_FP32 or SEM_FP64;
+ * SEM_MIXED writes double).  f and b may alias only if both are double.
+ */
+sem_status sem_rhs(sem_mesh_t mesh, sem_precision prec, const double *f_dev, void *b_dev,
+                   void *hip_stream);
+
+typedef struct {
+    sem_precision prec;   /* SEM_FP64, SEM_FP32, or SEM_MIXED (FP32 inner CG + FP64 outer) */
+    sem_geom geom;        /* form of the local operator in the (inner) CG */
+    double tol;           /* stop when ||r||_c / ||r0||_c <= tol (MIXED: true FP64 residual / ||b||_c) */
+    int max_iter;         /* iteration cap (MIXED: cap on inner iterations per outer step) */
+    int fixed_iters;      /* > 0: run exactly this many iterations, no convergence test */
+    double inner_tol;     /* MIXED: relative tolerance of each inner FP32 solve (0 -> 1e-5) */
+    int max_outer;        /* MIXED: cap on outer refinement steps (0 -> 20) */
+    int poll_every;       /* iterations per graph launch between host checks (0 -> auto) */
+    int use_graph;        /* 1: replay captured HIP graphs; 0: plain launches */
+    int true_residual;    /* 1: also compute ||b - A x||_c / ||b||_c in FP64 at the end */
+    double *hist_rho;     /* optional HOST buffer: rho_0..rho_iters (length hist_len) */
+    double *hist_alpha;   /* optional HOST buffer: alpha_1..alpha_iters at [1..] */
+    int hist_len;
+} sem_cg_opts;
+
+typedef struct {
+    int iters;                /* CG iterations done (MIXED: total inner iterations) */
+    int outer;                /* MIXED: outer refinement steps; else 0 */
+    int converged;            /* 1 if the tolerance was met */
+    int status;               /* 0 running/ok, 1 converged, 2 iteration cap, 3 breakdown */
+    double rel_res_recursive; /* sqrt(rho_i / rho_0) of the last (inner) solve */
+    double rel_res_true;      /* FP64 ||b - A x||_c / ||b||_c (if requested; MIXED: always) */
+    double seconds;           /* host wall time of the call */
+} sem_cg_result;
+
+/*
+ * Solve A x = b with Algorithm 1 (unpreconditioned CG): A = mask o QQ^T o A_L.
+ * b, x: DEVICE buffers in local form (continuous, masked), double for
+ * SEM_FP64 / SEM_MIXED, float for SEM_FP32.  x holds the initial guess on
+ * entry (its Dirichlet entries are zeroed) and the iterate on return.
+ * Readings of Algorithm 1 used: rho_0 = <r0, r0, c>; convergence when
+ * sqrt(rho_i / rho_0) <= tol; CG scalars are kept in FP64 on the device.
+ * SEM_MIXED: outer FP64 residual r = b - A x (FP64 operator), inner FP32 CG
+ * on r / ||r||_c to inner_tol, x += ||r||_c d, until ||r||_c / ||b||_c <= tol.
+ * Blocks until done.  Returns SEM_EBREAKDOWN if CG broke down (x holds the
+ * last iterate).
+ */
+sem_status sem_cg_solve(sem_mesh_t mesh, const sem_cg_opts *opts, const void *b_dev,
+                        void *x_dev, sem_cg_result *result, void *hip_stream);
+
+/*
+ * Batched solves: many independent meshes (any mix of E and N) advanced
+ * together, one CG iteration of every active problem per step, with the
+ * per-problem CG scalars on the device (each problem's arithmetic and
+ * reduction order is the same as in its own sem_cg_solve, so its result is
+ * bitwise identical).  The batch keeps pointers to the meshes; they must
+ * outlive it.  Entries of `meshes` must be distinct.
+ */
+sem_status sem_batch_create(int count, const sem_mesh_t *meshes, sem_batch_t *out);
+void sem_batch_destroy(sem_batch_t batch);
+
+/* b[i], x[i]: DEVICE buffers of problem i (as in sem_cg_solve); results[i]
+ * receives its outcome.  Blocks until every problem has stopped. */
+sem_status sem_batch_solve(sem_batch_t batch, const sem_cg_opts *opts,
+                           const void *const *b_dev, void *const *x_dev,
+                           sem_cg_result *results, void *hip_stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *sem_last_error(void);
+
+/* Library version string. */
+const char *sem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

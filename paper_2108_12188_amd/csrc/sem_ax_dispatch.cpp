@@ -1,0 +1,102 @@
+// sem_ax_dispatch.cpp -- order dispatch and launch shapes of the local operator.
+#include "sem_internal.h"
+
+#include <cstdlib>
+
+namespace sem {
+
+#define SEM_DECL_ORDER(N)                                                                       \
+    void ax_order_##N##_f32(bool, AxMode, const AxArgs<float> &, const double *, const double *, \
+                            const double *, hipStream_t);                                       \
+    void ax_order_##N##_f64(bool, AxMode, const AxArgs<double> &, const double *,               \
+                            const double *, const double *, hipStream_t);
+SEM_DECL_ORDER(1)
+SEM_DECL_ORDER(2)
+SEM_DECL_ORDER(3)
+SEM_DECL_ORDER(4)
+SEM_DECL_ORDER(5)
+SEM_DECL_ORDER(6)
+SEM_DECL_ORDER(7)
+SEM_DECL_ORDER(8)
+SEM_DECL_ORDER(9)
+SEM_DECL_ORDER(10)
+SEM_DECL_ORDER(11)
+#undef SEM_DECL_ORDER
+
+using Fn32 = void (*)(bool, AxMode, const AxArgs<float> &, const double *, const double *,
+                      const double *, hipStream_t);
+using Fn64 = void (*)(bool, AxMode, const AxArgs<double> &, const double *, const double *,
+                      const double *, hipStream_t);
+
+static const Fn32 kFn32[kMaxOrder + 1] = {nullptr,        ax_order_1_f32, ax_order_2_f32,
+                                          ax_order_3_f32, ax_order_4_f32, ax_order_5_f32,
+                                          ax_order_6_f32, ax_order_7_f32, ax_order_8_f32,
+                                          ax_order_9_f32, ax_order_10_f32, ax_order_11_f32};
+static const Fn64 kFn64[kMaxOrder + 1] = {nullptr,        ax_order_1_f64, ax_order_2_f64,
+                                          ax_order_3_f64, ax_order_4_f64, ax_order_5_f64,
+                                          ax_order_6_f64, ax_order_7_f64, ax_order_8_f64,
+                                          ax_order_9_f64, ax_order_10_f64, ax_order_11_f64};
+
+// Default elements per block: fill a multiple of 64 lanes with (i, j)
+// columns as tightly as possible, at most 512 threads and 64 KiB of LDS.
+static const int kEpb32[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 5, 2, 3};
+static const int kEpb64[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 3, 2, 1};
+
+// Per-process overrides, e.g. from the autotuner: SEM_AX_EPB_<N>=<epb>.
+static int epb_from_env(int N) {
+    char name[32];
+    std::snprintf(name, sizeof name, "SEM_AX_EPB_%d", N);
+    const char *v = std::getenv(name);
+    return v ? std::atoi(v) : 0;
+}
+
+AxShape ax_shape(int N, bool fp64, int epb_override) {
+    const int P = N + 1, P2 = P * P, P3 = P2 * P;
+    const size_t tsz = fp64 ? 8 : 4;
+    int epb = epb_override > 0 ? epb_override : epb_from_env(N);
+    if (epb <= 0) epb = fp64 ? kEpb64[N] : kEpb32[N];
+    // clamp to the kernel limits
+    while (epb > 1 && (((epb * P2 + 63) / 64) * 64 > 512 || 2 * tsz * epb * P3 > 65536)) --epb;
+    AxShape s;
+    s.epb = epb;
+    s.threads = ((epb * P2 + 63) / 64) * 64;
+    s.lds = 2 * tsz * (size_t)epb * P3;
+    return s;
+}
+
+template <>
+void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hipStream_t s) {
+    const AxShape sh = ax_shape(m.N, false, a.epb);
+    a.epb = sh.epb;
+    a.E = m.E;
+    a.D = m.b32.D;
+    a.Dt = m.b32.Dt;
+    a.xi = m.b32.xi;
+    a.wq = m.b32.w;
+    a.vert = m.vert32;
+    if (!otf) a.G = m.G32;
+    kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), s);
+    check_hip(hipGetLastError(), "ax kernel launch (fp32)");
+}
+
+template <>
+void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, hipStream_t s) {
+    const AxShape sh = ax_shape(m.N, true, a.epb);
+    a.epb = sh.epb;
+    a.E = m.E;
+    a.D = m.b64.D;
+    a.Dt = m.b64.Dt;
+    a.xi = m.b64.xi;
+    a.wq = m.b64.w;
+    a.vert = m.vert64;
+    if (!otf) a.G = m.G64;
+    kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), s);
+    check_hip(hipGetLastError(), "ax kernel launch (fp64)");
+}
+
+int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override) {
+    const AxShape sh = ax_shape(m.N, fp64, epb_override);
+    return (m.E + sh.epb - 1) / sh.epb;
+}
+
+}  // namespace sem

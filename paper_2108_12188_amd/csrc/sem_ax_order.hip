@@ -1,0 +1,319 @@
+// sem_ax_order.hip -- the local operator A_L for one polynomial order.
+//
+// Compiled once per order with -DSEM_ORDER=N.  Implements Eq. 4-5 of the
+// paper (w_e = D^T G^e D u_e, per element, no gather-scatter) in two forms:
+//   * precomputed G: the six symmetric factors are streamed from HBM
+//     (Sec. 4.2: 6 words per point, the HBM-bound form);
+//   * on-the-fly G ("rematerialization", Sec. 5.1, Eq. 13-14): G is rebuilt
+//     at every point from the element's 8 vertices, so only u and w move.
+// and two modes:
+//   * Plain: w = A_L u;
+//   * CgFused: the p-update of Algorithm 1 is the prologue (p <- r + beta p,
+//     the loop fusion of Sec. 5.1), the Dirichlet mask is the epilogue, and
+//     the FP64 partial of <p, w, c> over points of multiplicity 1 is reduced
+//     per block (those points are untouched by the gather-scatter).
+//
+// Work decomposition (gfx950, 64-lane waves): a block holds `epb` elements;
+// one thread owns one (i, j) column of one element and walks the k
+// direction in registers.  The i- and j-direction contractions read the
+// element tile from LDS; the k-direction contraction is register-only with
+// D entries that are wave-uniform (kernel-argument / scalar registers).
+#include "sem_internal.h"
+
+#ifndef SEM_ORDER
+#error "compile with -DSEM_ORDER=<N>"
+#endif
+
+namespace sem {
+namespace {
+
+constexpr int kOrder = SEM_ORDER;
+constexpr int kP = kOrder + 1;
+
+// Kernel-argument copy of the basis: indexed only with compile-time
+// constants, so every access is a scalar load.
+template <typename T>
+struct BasisK {
+    T D[kP * kP];   // D[k*P + l] = l_l'(xi_k)
+    T xi[kP];
+    T w[kP];
+};
+
+template <typename T>
+__device__ __forceinline__ T rcp(T x) { return T(1) / x; }
+template <>
+__device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename T>
+struct Vec3 {
+    T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ Vec3<T> cross(const Vec3<T> &a, const Vec3<T> &b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ T dot3(const Vec3<T> &a, const Vec3<T> &b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename T>
+__device__ __forceinline__ Vec3<T> axpy3(T s, const Vec3<T> &a, const Vec3<T> &b) {
+    return {b.x + s * a.x, b.y + s * a.y, b.z + s * a.z};   // b + s a
+}
+template <typename T>
+__device__ __forceinline__ Vec3<T> add3(const Vec3<T> &a, const Vec3<T> &b) {
+    return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+
+// Per-thread constants of the trilinear map along one (i, j) column.
+// Along the column only gamma varies, and
+//   x_xi(gamma) = A0 + gamma A1,  x_eta(gamma) = B0 + gamma B1,  x_gamma = C,
+// so the cofactor rows r0 = x_eta x x_gamma, r1 = x_gamma x x_xi,
+// r2 = x_xi x x_eta and |J| = x_xi . r0 are low-degree polynomials in gamma.
+template <typename T>
+struct ColumnGeom {
+    Vec3<T> R00, R01, R10, R11, R20, R21, R22;
+    T d0, d1, d2, wij;
+};
+
+template <typename T>
+__device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T xi_i,
+                                                     T eta_j, T wij) {
+    const T fi0 = T(0.5) * (T(1) - xi_i), fi1 = T(0.5) * (T(1) + xi_i);
+    const T fj0 = T(0.5) * (T(1) - eta_j), fj1 = T(0.5) * (T(1) + eta_j);
+    T A0[3], A1[3], B0[3], B1[3], Cc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T v0 = ve[0 * 3 + d], v1 = ve[1 * 3 + d], v2 = ve[2 * 3 + d], v3 = ve[3 * 3 + d];
+        const T v4 = ve[4 * 3 + d], v5 = ve[5 * 3 + d], v6 = ve[6 * 3 + d], v7 = ve[7 * 3 + d];
+        // d/dxi at (eta_j, gamma corner c)
+        const T a0 = T(0.5) * ((v1 - v0) * fj0 + (v3 - v2) * fj1);
+        const T a1 = T(0.5) * ((v5 - v4) * fj0 + (v7 - v6) * fj1);
+        // d/deta at (xi_i, gamma corner c)
+        const T b0 = T(0.5) * ((v2 - v0) * fi0 + (v3 - v1) * fi1);
+        const T b1 = T(0.5) * ((v6 - v4) * fi0 + (v7 - v5) * fi1);
+        A0[d] = T(0.5) * (a0 + a1);
+        A1[d] = T(0.5) * (a1 - a0);
+        B0[d] = T(0.5) * (b0 + b1);
+        B1[d] = T(0.5) * (b1 - b0);
+        Cc[d] = T(0.5) * ((v4 - v0) * fi0 * fj0 + (v5 - v1) * fi1 * fj0 +
+                          (v6 - v2) * fi0 * fj1 + (v7 - v3) * fi1 * fj1);
+    }
+    const Vec3<T> a0{A0[0], A0[1], A0[2]}, a1{A1[0], A1[1], A1[2]};
+    const Vec3<T> b0{B0[0], B0[1], B0[2]}, b1{B1[0], B1[1], B1[2]};
+    const Vec3<T> c{Cc[0], Cc[1], Cc[2]};
+    ColumnGeom<T> g;
+    g.R00 = cross(b0, c);
+    g.R01 = cross(b1, c);
+    g.R10 = cross(c, a0);
+    g.R11 = cross(c, a1);
+    g.R20 = cross(a0, b0);
+    g.R21 = add3(cross(a0, b1), cross(a1, b0));
+    g.R22 = cross(a1, b1);
+    g.d0 = dot3(a0, g.R00);
+    g.d1 = dot3(a0, g.R01) + dot3(a1, g.R00);
+    g.d2 = dot3(a1, g.R01);
+    g.wij = wij;
+    return g;
+}
+
+// Deterministic block sum of one double per thread; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int q = 0; q < nw; ++q) s += red[q];
+    }
+    return s;
+}
+
+template <typename T, bool OTF, bool FUSED>
+__global__ void __launch_bounds__(512)
+ax_kernel(const AxArgs<T> a, const BasisK<T> bk) {
+    constexpr int P = kP, P2 = P * P, P3 = P2 * P;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *const sA = reinterpret_cast<T *>(lds_raw);
+    T *const sB = sA + a.epb * P3;
+
+    if constexpr (FUSED) {
+        if (a.st->stop) return;          // uniform: the whole grid exits
+    }
+
+    const int t = threadIdx.x;
+    const int el = t / P2;
+    const int col = t - el * P2;
+    const int i = col % P;
+    const int j = col / P;
+    const int64_t e = (int64_t)blockIdx.x * a.epb + el;
+    const bool valid = (el < a.epb) && (e < a.E);
+    const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
+    T *const sa = sA + el * P3;
+    T *const sb = sB + el * P3;
+
+    T uc[P];
+    T beta = T(0);
+    if constexpr (FUSED) beta = (T)a.st->beta;
+    if (valid) {
+        if constexpr (FUSED) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const T r = a.u[base + k * P2];
+                const T pold = a.p[base + k * P2];
+                uc[k] = r + beta * pold;
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) sa[k * P2 + col] = uc[k];
+    }
+
+    // per-lane rows of D and D^T for the i and j contractions
+    T Di[P], Dj[P], DiT[P], DjT[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        Di[l] = a.D[i * P + l];
+        Dj[l] = a.D[j * P + l];
+        DiT[l] = a.Dt[i * P + l];
+        DjT[l] = a.Dt[j * P + l];
+    }
+
+    ColumnGeom<T> cg;
+    if constexpr (OTF) {
+        if (valid) {
+            cg = column_geom<T>(a.vert + e * 24, a.xi[i], a.xi[j], a.wq[i] * a.wq[j]);
+        }
+    }
+    __syncthreads();
+
+    T vsr[P], vtr[P];
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T ur = T(0), us = T(0), ut = T(0);
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                ur += Di[l] * sa[k * P2 + j * P + l];
+                us += Dj[l] * sa[k * P2 + l * P + i];
+                ut += bk.D[k * P + l] * uc[l];
+            }
+            T vr, vs, vt;
+            if constexpr (OTF) {
+                const T gam = bk.xi[k];
+                const Vec3<T> r0 = axpy3(gam, cg.R01, cg.R00);
+                const Vec3<T> r1 = axpy3(gam, cg.R11, cg.R10);
+                const Vec3<T> r2 = axpy3(gam, axpy3(gam, cg.R22, cg.R21), cg.R20);
+                const T det = cg.d0 + gam * (cg.d1 + gam * cg.d2);
+                const T s = cg.wij * bk.w[k] * rcp<T>(det);
+                const Vec3<T> g{r0.x * ur + r1.x * us + r2.x * ut,
+                                r0.y * ur + r1.y * us + r2.y * ut,
+                                r0.z * ur + r1.z * us + r2.z * ut};
+                vr = s * dot3(r0, g);
+                vs = s * dot3(r1, g);
+                vt = s * dot3(r2, g);
+            } else {
+                const T *Ge = a.G + e * (6 * P3) + col + k * P2;
+                const T g11 = Ge[0], g12 = Ge[P3], g13 = Ge[2 * P3];
+                const T g22 = Ge[3 * P3], g23 = Ge[4 * P3], g33 = Ge[5 * P3];
+                vr = g11 * ur + g12 * us + g13 * ut;
+                vs = g12 * ur + g22 * us + g23 * ut;
+                vt = g13 * ur + g23 * us + g33 * ut;
+            }
+            sb[k * P2 + col] = vr;
+            vsr[k] = vs;
+            vtr[k] = vt;
+        }
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) sa[k * P2 + col] = vsr[k];
+    }
+    __syncthreads();
+
+    double acc = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T wv = T(0);
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                wv += DiT[l] * sb[k * P2 + j * P + l];
+                wv += DjT[l] * sa[k * P2 + l * P + i];
+                wv += bk.D[l * P + k] * vtr[l];
+            }
+            if constexpr (FUSED) {
+                const uint8_t m = a.mcode[base + k * P2];
+                if (m == 0) wv = T(0);
+                if (m == 1) acc += (double)uc[k] * (double)wv;
+            }
+            a.w[base + k * P2] = wv;
+        }
+    }
+    if constexpr (FUSED) {
+        const double s = block_sum(acc);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+    }
+}
+
+template <typename T>
+BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
+    BasisK<T> b;
+    for (int q = 0; q < kP * kP; ++q) b.D[q] = (T)D[q];
+    for (int q = 0; q < kP; ++q) {
+        b.xi[q] = (T)xi[q];
+        b.w[q] = (T)w[q];
+    }
+    return b;
+}
+
+template <typename T, bool OTF, bool FUSED>
+void launch(const AxArgs<T> &a, const BasisK<T> &bk, hipStream_t s) {
+    constexpr int P3 = kP * kP * kP;
+    const int threads = ((a.epb * kP * kP + 63) / 64) * 64;
+    const size_t lds = 2 * sizeof(T) * (size_t)a.epb * P3;
+    const int64_t blocks = (a.E + a.epb - 1) / a.epb;
+    hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED>), dim3((unsigned)blocks), dim3(threads), lds, s,
+                       a, bk);
+}
+
+}  // namespace
+
+#define SEM_CAT3_(a, b, c) a##b##c
+#define SEM_CAT3(a, b, c) SEM_CAT3_(a, b, c)
+
+template <typename T>
+static void ax_entry(bool otf, AxMode mode, const AxArgs<T> &a, const double *D,
+                     const double *xi, const double *w, hipStream_t s) {
+    const BasisK<T> bk = make_basis<T>(D, xi, w);
+    const bool fused = mode == AxMode::CgFused;
+    if (otf) {
+        if (fused) launch<T, true, true>(a, bk, s);
+        else launch<T, true, false>(a, bk, s);
+    } else {
+        if (fused) launch<T, false, true>(a, bk, s);
+        else launch<T, false, false>(a, bk, s);
+    }
+}
+
+void SEM_CAT3(ax_order_, SEM_ORDER, _f32)(bool otf, AxMode mode, const AxArgs<float> &a,
+                                           const double *D, const double *xi, const double *w,
+                                           hipStream_t s) {
+    ax_entry<float>(otf, mode, a, D, xi, w, s);
+}
+void SEM_CAT3(ax_order_, SEM_ORDER, _f64)(bool otf, AxMode mode, const AxArgs<double> &a,
+                                           const double *D, const double *xi, const double *w,
+                                           hipStream_t s) {
+    ax_entry<double>(otf, mode, a, D, xi, w, s);
+}
+
+}  // namespace sem

@@ -1,0 +1,199 @@
+// sem_internal.h -- shared host/device definitions of the SEM library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+
+namespace sem {
+
+constexpr int kMaxOrder = 11;
+constexpr int kMaxP = kMaxOrder + 1;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+[[noreturn]] void fail(sem_status code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+
+#define SEM_HIP(call) ::sem::check_hip((call), #call)
+
+// ---------------------------------------------------------------------------
+// Device-resident CG scalars of one solve (Algorithm 1: rho, alpha, beta).
+// Written only by the last block of a reduction kernel; read by every block
+// of the next kernel in stream order.
+// ---------------------------------------------------------------------------
+struct CgState {
+    double rho;        // rho_{i-1}: <r, r, c> of the current residual
+    double rho0;       // rho_0
+    double alpha;      // alpha_i
+    double beta;       // beta_{i-1} used by the next p-update
+    double pw;         // <p, w, c> of the current iteration
+    double thresh;     // stop when rho <= thresh (= tol^2 rho_0)
+    int iter;          // completed iterations
+    int max_iter;      // iteration cap
+    int stop;          // 0 running, 1 converged, 2 cap reached, 3 breakdown
+    int fixed;         // 1: no convergence test
+    unsigned int cnt_gs;   // completion counters of the last-block reductions
+    unsigned int cnt_upd;
+    unsigned int cnt_aux;
+    int hist_len;      // capacity of the history arrays
+    double *hist_rho;  // device history (may be null)
+    double *hist_alpha;
+};
+
+// ---------------------------------------------------------------------------
+// Mesh handle
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Basis {
+    T *D = nullptr;    // [P][P]  D_ij = l_j'(xi_i)
+    T *Dt = nullptr;   // [P][P]  transpose
+    T *xi = nullptr;   // [P]
+    T *w = nullptr;    // [P]
+};
+
+struct Workspace;      // CG vectors of one precision (sem_cg.cpp)
+
+// Gather-scatter groups by size class (see sem_gs.hip).
+constexpr int kMaxGsClasses = 32;
+struct GsClasses {
+    int ncls;
+    int M[kMaxGsClasses];          // copies per group in this class
+    int64_t ng[kMaxGsClasses];     // groups in this class
+    int64_t io[kMaxGsClasses];     // offset of the class in gs_idx
+    int64_t blk0[kMaxGsClasses];   // first block of the class in a gs launch
+};
+void gs_classes_finish(GsClasses &c);
+
+struct Mesh {
+    int device = 0;
+    int64_t E = 0;
+    int N = 0, P = 0, P3 = 0;
+    int64_t n = 0;            // local points
+    int64_t n_glob = 0;
+    int64_t n_groups = 0, n_shared = 0, n_dir = 0;
+    GsClasses gs{};           // shared-point groups by size class
+
+    // host copies of the basis (FP64, this library's own construction)
+    std::vector<double> h_xi, h_w, h_D;
+
+    // device arrays
+    double *vert64 = nullptr;     // [E][8][3]
+    float *vert32 = nullptr;      // [E][8][3]
+    float *G32 = nullptr;         // [E][6][P3]
+    double *G64 = nullptr;        // [E][6][P3]
+    double *B64 = nullptr;        // [E][P3] mass w_q |J_q|
+    uint8_t *mcode = nullptr;     // [n]: 0 Dirichlet, else multiplicity
+    int32_t *gs_idx = nullptr;    // [n_shared], class-major, groups of M ascending indices
+    int32_t *dir_idx = nullptr;   // [n_dir]
+    Basis<float> b32;
+    Basis<double> b64;
+    void *basis_blob = nullptr;
+    double *scratch = nullptr;    // reduction partials / small scalars
+    size_t scratch_len = 0;       // in doubles
+    CgState *state = nullptr;     // device CG state for sem_dot / solves
+    size_t device_bytes = 0;
+
+    Workspace *ws32 = nullptr;
+    Workspace *ws64 = nullptr;
+};
+
+Mesh *as_mesh(sem_mesh_t m);
+
+// ---------------------------------------------------------------------------
+// Host basis construction (sem_basis.cpp)
+// ---------------------------------------------------------------------------
+void gll_points(int N, std::vector<double> &xi, std::vector<double> &w);
+void derivative_matrix(const std::vector<double> &xi, std::vector<double> &D);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers
+// ---------------------------------------------------------------------------
+enum class AxMode { Plain = 0, CgFused = 1 };
+
+template <typename T>
+struct AxArgs {
+    int64_t E;
+    int epb;                    // elements per block
+    const T *u;                 // Plain: input u. CgFused: residual r
+    T *p;                       // CgFused: search direction, updated in place
+    T *w;                       // output
+    const T *G;                 // precomputed factors [E][6][P3]
+    const T *vert;              // vertices [E][8][3] (on-the-fly form)
+    const T *D;                 // [P][P]
+    const T *Dt;                // [P][P]
+    const T *xi;                // [P]
+    const T *wq;                // [P]
+    const uint8_t *mcode;       // CgFused: mask / interior weights
+    CgState *st;                // CgFused: beta, stop flag
+    double *partial;            // CgFused: one FP64 partial of <p, w, c> per block
+};
+
+// Launch configuration chosen for an order (threads, elements per block,
+// dynamic LDS bytes).  `variant` selects among the tuned shapes.
+struct AxShape {
+    int epb;
+    int threads;
+    size_t lds;
+};
+AxShape ax_shape(int N, bool fp64, int epb_override);
+
+// Fills the basis / geometry pointers and the shape from the mesh; the
+// caller sets u, p, w, mcode, st, partial (and epb to force a shape).
+template <typename T>
+void launch_ax(const Mesh &m, bool otf, AxMode mode, AxArgs<T> a, hipStream_t s);
+int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override);
+
+// gather-scatter / mask / vector kernels (sem_gs.hip, sem_vec.hip)
+template <typename T>
+void launch_gs(const Mesh &m, T *w, hipStream_t s);
+template <typename T>
+void launch_mask(const Mesh &m, T *w, hipStream_t s);
+template <typename T>
+void launch_gs_cg(const Mesh &m, T *w, const T *p, CgState *st, const double *ax_partial,
+                  int n_ax_partial, double *gs_partial, hipStream_t s);
+int gs_cg_blocks(const Mesh &m);
+
+// Algorithm 1 vector kernels (sem_vec.hip).  Reductions use one FP64
+// partial per block (`partial`, at least vec_blocks(n) entries) and the
+// completion counters inside `st`.
+int vec_blocks(int64_t n);
+// x += alpha p; r -= alpha w; rho = <r, r, c>; beta, convergence, history
+template <typename T>
+void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
+                   double *partial, hipStream_t s);
+// r = b - w (w may be null: r = b); p = 0; rho_0 = <r, r, c>; initial state
+template <typename T>
+void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
+                    double *partial, hipStream_t s);
+// *out = <a, b, c>
+template <typename T>
+void launch_dot(const Mesh &m, const T *a, const T *b, double *out, CgState *st,
+                double *partial, hipStream_t s);
+// r = b - w and *out = <r, r, c>  (FP64 outer residual of the refinement)
+void launch_residual64(const Mesh &m, const double *b, const double *w, double *r, double *out,
+                       CgState *st, double *partial, hipStream_t s);
+// dst = (float)(src / sqrt(*nrm2))
+void launch_scale_to_f32(int64_t n, const double *src, const double *nrm2, float *dst,
+                         hipStream_t s);
+// x += sqrt(*nrm2) * (double)d
+void launch_axpy_from_f32(int64_t n, double *x, const double *nrm2, const float *d,
+                          hipStream_t s);
+// elementwise helpers
+template <typename Ts, typename Td>
+void launch_convert(int64_t n, const Ts *src, Td *dst, hipStream_t s);
+void launch_mul64(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+
+// FP64 geometry setup (sem_geom.hip)
+int64_t launch_geometry(Mesh &m, hipStream_t s);
+void launch_coords(const Mesh &m, double *xyz, hipStream_t s);
+template <typename T>
+void launch_rhs_mass(const Mesh &m, const double *f, T *b, hipStream_t s);
+
+}  // namespace sem

@@ -1,0 +1,285 @@
+// sem_vec.hip -- the vector updates and weighted reductions of Algorithm 1.
+//
+// All reductions accumulate in FP64 (a product of two FP32 values is exact
+// in FP64) with the weights c_l = 1/m_l of the weighted inner product
+// <a, b, c>; the multiplicity code m_l = 0 marks Dirichlet points (weight 0,
+// the vectors vanish there anyway).  The grid size depends only on n, and
+// the block partials are summed in index order by the last block, so every
+// result is bitwise reproducible.
+#include "sem_internal.h"
+#include "sem_reduce.h"
+
+namespace sem {
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kVecMaxBlocks = 2048;
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Pack4 {
+    T v[4];
+};
+struct alignas(4) Code4 {
+    uint8_t v[4];
+};
+
+__device__ __forceinline__ void weights_lds(double *cw) {
+    // 1/m for m = 1..255 (exact for powers of two); 0 for the Dirichlet code
+    cw[threadIdx.x] = threadIdx.x ? 1.0 / (double)threadIdx.x : 0.0;
+    __syncthreads();
+}
+
+// x += alpha p; r -= alpha w; rho_i = <r, r, c>  (Algorithm 1, fused updates
+// and reduction), then beta_i = rho_i / rho_{i-1} and the convergence test.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+update_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
+              const T *__restrict__ w, const uint8_t *__restrict__ mcode, CgState *st,
+              double *partial) {
+    if (st->stop) return;
+    __shared__ double cw[kVecThreads];
+    __shared__ double red[16];
+    __shared__ int last_flag;
+    weights_lds(cw);
+    const T a = (T)st->alpha;
+    double acc = 0.0;
+    const int64_t n4 = n >> 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t q = tid; q < n4; q += stride) {
+        Pack4<T> xv = reinterpret_cast<const Pack4<T> *>(x)[q];
+        Pack4<T> rv = reinterpret_cast<const Pack4<T> *>(r)[q];
+        const Pack4<T> pv = reinterpret_cast<const Pack4<T> *>(p)[q];
+        const Pack4<T> wv = reinterpret_cast<const Pack4<T> *>(w)[q];
+        const Code4 mv = reinterpret_cast<const Code4 *>(mcode)[q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            xv.v[t] += a * pv.v[t];
+            rv.v[t] -= a * wv.v[t];
+            const double rd = (double)rv.v[t];
+            acc += rd * rd * cw[mv.v[t]];
+        }
+        reinterpret_cast<Pack4<T> *>(x)[q] = xv;
+        reinterpret_cast<Pack4<T> *>(r)[q] = rv;
+    }
+    for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
+        x[q] += a * p[q];
+        const T rn = r[q] - a * w[q];
+        r[q] = rn;
+        acc += (double)rn * (double)rn * cw[mcode[q]];
+    }
+    const double s = block_sum_f64(acc, red);
+    if (publish_partial(s, partial, &st->cnt_upd, gridDim.x, &last_flag)) {
+        const double rho = sum_partials(partial, (int)gridDim.x, red);
+        if (threadIdx.x == 0) {
+            const double beta = rho / st->rho;
+            st->beta = beta;
+            st->rho = rho;
+            const int it = st->iter + 1;
+            st->iter = it;
+            if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rho;
+            if (!isfinite(rho)) st->stop = 3;
+            else if (!st->fixed && rho <= st->thresh) st->stop = 1;
+            else if (it >= st->max_iter) st->stop = 2;
+        }
+    }
+}
+
+// r0 = b - A x0 (w holds A x0, or is null for x0 = 0); p0 = 0; beta_0 = 0;
+// rho_0 = <r0, r0, c>; the threshold becomes tol^2 rho_0.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+cg_init_kernel(int64_t n, const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ r,
+               T *__restrict__ p, const uint8_t *__restrict__ mcode, CgState *st,
+               double *partial) {
+    __shared__ double cw[kVecThreads];
+    __shared__ double red[16];
+    __shared__ int last_flag;
+    weights_lds(cw);
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const T rv = w ? b[q] - w[q] : b[q];
+        r[q] = rv;
+        p[q] = T(0);
+        acc += (double)rv * (double)rv * cw[mcode[q]];
+    }
+    const double s = block_sum_f64(acc, red);
+    if (publish_partial(s, partial, &st->cnt_upd, gridDim.x, &last_flag)) {
+        const double rho0 = sum_partials(partial, (int)gridDim.x, red);
+        if (threadIdx.x == 0) {
+            st->rho = rho0;
+            st->rho0 = rho0;
+            st->thresh = st->thresh * rho0;
+            st->beta = 0.0;
+            st->alpha = 0.0;
+            st->iter = 0;
+            if (st->hist_rho && st->hist_len > 0) st->hist_rho[0] = rho0;
+            int stop = 0;
+            if (!isfinite(rho0)) stop = 3;
+            else if (rho0 == 0.0) stop = 1;
+            else if (st->max_iter <= 0) stop = 2;
+            st->stop = stop;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+dot_kernel(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
+           const uint8_t *__restrict__ mcode, double *out, CgState *st, double *partial) {
+    __shared__ double cw[kVecThreads];
+    __shared__ double red[16];
+    __shared__ int last_flag;
+    weights_lds(cw);
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        acc += (double)a[q] * (double)b[q] * cw[mcode[q]];
+    const double s = block_sum_f64(acc, red);
+    if (publish_partial(s, partial, &st->cnt_aux, gridDim.x, &last_flag)) {
+        const double v = sum_partials(partial, (int)gridDim.x, red);
+        if (threadIdx.x == 0) *out = v;
+    }
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+residual64_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ w,
+                  double *__restrict__ r, const uint8_t *__restrict__ mcode, double *out,
+                  CgState *st, double *partial) {
+    __shared__ double cw[kVecThreads];
+    __shared__ double red[16];
+    __shared__ int last_flag;
+    weights_lds(cw);
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const double rv = b[q] - w[q];
+        r[q] = rv;
+        acc += rv * rv * cw[mcode[q]];
+    }
+    const double s = block_sum_f64(acc, red);
+    if (publish_partial(s, partial, &st->cnt_aux, gridDim.x, &last_flag)) {
+        const double v = sum_partials(partial, (int)gridDim.x, red);
+        if (threadIdx.x == 0) *out = v;
+    }
+}
+
+__global__ void scale_to_f32_kernel(int64_t n, const double *__restrict__ src,
+                                    const double *__restrict__ nrm2, float *__restrict__ dst) {
+    const double inv = 1.0 / sqrt(*nrm2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        dst[q] = (float)(src[q] * inv);
+}
+
+__global__ void axpy_from_f32_kernel(int64_t n, double *__restrict__ x,
+                                     const double *__restrict__ nrm2, const float *__restrict__ d) {
+    const double sc = sqrt(*nrm2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        x[q] += sc * (double)d[q];
+}
+
+template <typename Ts, typename Td>
+__global__ void convert_kernel(int64_t n, const Ts *__restrict__ src, Td *__restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        dst[q] = (Td)src[q];
+}
+
+__global__ void mul64_kernel(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                             double *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        out[q] = a[q] * b[q];
+}
+
+int elem_blocks(int64_t n) {
+    int64_t b = (n + kVecThreads - 1) / kVecThreads;
+    if (b > 8192) b = 8192;
+    return (int)(b > 0 ? b : 1);
+}
+
+}  // namespace
+
+int vec_blocks(int64_t n) {
+    int64_t b = (n + 4 * kVecThreads - 1) / (4 * kVecThreads);
+    if (b > kVecMaxBlocks) b = kVecMaxBlocks;
+    return (int)(b > 0 ? b : 1);
+}
+
+template <typename T>
+void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
+                   double *partial, hipStream_t s) {
+    hipLaunchKernelGGL((update_kernel<T>), dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n, x,
+                       r, p, w, m.mcode, st, partial);
+    check_hip(hipGetLastError(), "update kernel launch");
+}
+
+template <typename T>
+void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
+                    double *partial, hipStream_t s) {
+    hipLaunchKernelGGL((cg_init_kernel<T>), dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n,
+                       b, w, r, p, m.mcode, st, partial);
+    check_hip(hipGetLastError(), "cg init kernel launch");
+}
+
+template <typename T>
+void launch_dot(const Mesh &m, const T *a, const T *b, double *out, CgState *st, double *partial,
+                hipStream_t s) {
+    hipLaunchKernelGGL((dot_kernel<T>), dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n, a,
+                       b, m.mcode, out, st, partial);
+    check_hip(hipGetLastError(), "dot kernel launch");
+}
+
+void launch_residual64(const Mesh &m, const double *b, const double *w, double *r, double *out,
+                       CgState *st, double *partial, hipStream_t s) {
+    hipLaunchKernelGGL(residual64_kernel, dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n, b,
+                       w, r, m.mcode, out, st, partial);
+    check_hip(hipGetLastError(), "residual kernel launch");
+}
+
+void launch_scale_to_f32(int64_t n, const double *src, const double *nrm2, float *dst,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(scale_to_f32_kernel, dim3(elem_blocks(n)), dim3(kVecThreads), 0, s, n, src,
+                       nrm2, dst);
+    check_hip(hipGetLastError(), "scale kernel launch");
+}
+
+void launch_axpy_from_f32(int64_t n, double *x, const double *nrm2, const float *d,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(axpy_from_f32_kernel, dim3(elem_blocks(n)), dim3(kVecThreads), 0, s, n, x,
+                       nrm2, d);
+    check_hip(hipGetLastError(), "axpy kernel launch");
+}
+
+template <typename Ts, typename Td>
+void launch_convert(int64_t n, const Ts *src, Td *dst, hipStream_t s) {
+    hipLaunchKernelGGL((convert_kernel<Ts, Td>), dim3(elem_blocks(n)), dim3(kVecThreads), 0, s, n,
+                       src, dst);
+    check_hip(hipGetLastError(), "convert kernel launch");
+}
+
+void launch_mul64(int64_t n, const double *a, const double *b, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(mul64_kernel, dim3(elem_blocks(n)), dim3(kVecThreads), 0, s, n, a, b, out);
+    check_hip(hipGetLastError(), "mul kernel launch");
+}
+
+template void launch_update<float>(const Mesh &, float *, float *, const float *, const float *,
+                                   CgState *, double *, hipStream_t);
+template void launch_update<double>(const Mesh &, double *, double *, const double *,
+                                    const double *, CgState *, double *, hipStream_t);
+template void launch_cg_init<float>(const Mesh &, const float *, const float *, float *, float *,
+                                    CgState *, double *, hipStream_t);
+template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,
+                                     double *, CgState *, double *, hipStream_t);
+template void launch_dot<float>(const Mesh &, const float *, const float *, double *, CgState *,
+                                double *, hipStream_t);
+template void launch_dot<double>(const Mesh &, const double *, const double *, double *,
+                                 CgState *, double *, hipStream_t);
+template void launch_convert<float, double>(int64_t, const float *, double *, hipStream_t);
+template void launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);
+template void launch_convert<double, double>(int64_t, const double *, double *, hipStream_t);
+
+}  // namespace sem

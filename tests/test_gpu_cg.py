@@ -1,0 +1,153 @@
+"""Parity of the HIP CG solver (Algorithm 1) and its mixed-precision
+refinement with the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import rel_norm, say, to_dev, to_host
+from seminputs import box_mesh, random_global_rhs
+
+pytestmark = pytest.mark.gpu
+
+
+def _manufactured(gm, pr, prec):
+    import torch
+    import paper_2108_12188_amd as sem
+    xyz = gm.coords()
+    f = 3 * math.pi ** 2 * torch.sin(math.pi * xyz[0]) * torch.sin(math.pi * xyz[1]) \
+        * torch.sin(math.pi * xyz[2])
+    return gm.rhs(f.contiguous(), prec=prec)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_cg_fp64_small_box_matches_oracle(graph):
+    """4x4x4 affine elements, N = 7, manufactured forcing, tol 1e-8."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"cg fp64 4^3 N=7 graph={graph}")
+    mesh = box_mesh(4, 4, 4, 7)
+    pr = oracle.Problem(mesh)
+    gm = sem.Mesh.from_box(mesh, g_fp64=True)
+    b = _manufactured(gm, pr, sem.FP64)
+    bh = to_host(b)
+    bref, u_exact = pr.rhs_manufactured()
+    assert rel_norm(bh, bref) < 1e-14
+    xo, it_o, hist = pr.cg(bh, tol=1e-8, max_iter=2000)
+    x, res = gm.cg_solve(b, prec=sem.FP64, tol=1e-8, max_iter=2000, use_graph=graph,
+                         true_residual=True, history=60)
+    assert res["converged"] == 1
+    assert abs(res["iters"] - it_o) <= 2
+    k = min(50, len(res["hist_rho"]), len(hist["rho"]))
+    np.testing.assert_allclose(res["hist_rho"][:k], hist["rho"][:k], rtol=1e-8)
+    np.testing.assert_allclose(res["hist_alpha"][1:k], hist["alpha"][1:k], rtol=1e-8)
+    xg = to_host(x)
+    assert rel_norm(xg, xo) < 1e-6
+    assert res["rel_res_true"] < 1.1e-8
+    assert pr.true_rel_residual(bh, xg) < 1.1e-8
+    assert np.max(np.abs(xg - u_exact)) < 1e-5
+    gm.close()
+
+
+@pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
+def test_cg_fp32_first_iterations_match_oracle(geom):
+    """Deformed 6x5x4 mesh, N = 5, random continuous RHS: alpha_i and beta_i of
+    the FP32 solver follow the FP64 oracle to 1e-4 for i <= 10."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"cg fp32 first iterations geom={geom}")
+    mesh = box_mesh(6, 5, 4, 5, perturb=0.1, seed=2110, permute=True, reorient=True)
+    pr = oracle.Problem(mesh)
+    gm = sem.Mesh.from_box(mesh)
+    b = random_global_rhs(mesh, seed=12188)
+    xo, it_o, hist = pr.cg(b, fixed=10)
+    x, res = gm.cg_solve(to_dev(b, torch.float32), prec=sem.FP32, geom=geom, fixed_iters=10,
+                         history=12)
+    assert res["iters"] == 10
+    rho_o, rho_g = hist["rho"][:11], res["hist_rho"][:11]
+    np.testing.assert_allclose(rho_g, rho_o, rtol=1e-4)
+    np.testing.assert_allclose(res["hist_alpha"][1:11], hist["alpha"][1:11], rtol=1e-4)
+    beta_g = rho_g[1:] / rho_g[:-1]
+    np.testing.assert_allclose(beta_g, hist["beta"][1:11], rtol=1e-4)
+    assert rel_norm(to_host(x), xo) < 1e-4
+    gm.close()
+
+
+def test_cg_deterministic_and_graph_equals_plain():
+    import torch
+    import paper_2108_12188_amd as sem
+    mesh = box_mesh(5, 4, 4, 7, perturb=0.1, seed=4)
+    gm = sem.Mesh.from_box(mesh)
+    b = to_dev(random_global_rhs(mesh, seed=5), torch.float32)
+    x1, r1 = gm.cg_solve(b, prec=sem.FP32, fixed_iters=37, use_graph=True)
+    x2, r2 = gm.cg_solve(b, prec=sem.FP32, fixed_iters=37, use_graph=True)
+    x3, r3 = gm.cg_solve(b, prec=sem.FP32, fixed_iters=37, use_graph=False, poll_every=5)
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
+    assert r1["rel_res_recursive"] == r2["rel_res_recursive"] == r3["rel_res_recursive"]
+    gm.close()
+
+
+def test_cg_zero_rhs_and_nonzero_guess():
+    import torch
+    import paper_2108_12188_amd as sem
+    mesh = box_mesh(3, 3, 3, 4, perturb=0.1, seed=1)
+    pr = oracle.Problem(mesh)
+    gm = sem.Mesh.from_box(mesh, g_fp64=True)
+    b = torch.zeros(mesh.n_local, dtype=torch.float64, device="cuda")
+    x, res = gm.cg_solve(b, prec=sem.FP64, tol=1e-10)
+    assert res["iters"] == 0 and res["converged"] == 1
+    assert float(x.abs().max()) == 0.0
+    # nonzero initial guess: same solution as from zero
+    bb = random_global_rhs(mesh, seed=2)
+    xg0 = to_dev(np.random.default_rng(0).uniform(-1, 1, mesh.n_local), torch.float64)
+    xg0 = to_dev(pr.gs(to_host(xg0)) / pr.m, torch.float64)     # continuous guess
+    x1, r1 = gm.cg_solve(to_dev(bb, torch.float64), x=xg0, prec=sem.FP64, tol=1e-11)
+    xo, _, _ = pr.cg(bb, tol=1e-12, max_iter=5000)
+    assert rel_norm(to_host(x1), xo) < 1e-8
+    assert r1["converged"] == 1
+    gm.close()
+
+
+def test_cg_max_iter_cap():
+    import torch
+    import paper_2108_12188_amd as sem
+    mesh = box_mesh(4, 4, 4, 5, perturb=0.1, seed=3)
+    gm = sem.Mesh.from_box(mesh)
+    b = to_dev(random_global_rhs(mesh, seed=2), torch.float32)
+    x, res = gm.cg_solve(b, prec=sem.FP32, tol=1e-12, max_iter=7)
+    assert res["iters"] == 7 and res["converged"] == 0 and res["status"] == 2
+    gm.close()
+
+
+def test_cg_nan_rhs_is_breakdown():
+    import torch
+    import paper_2108_12188_amd as sem
+    mesh = box_mesh(2, 2, 2, 3)
+    gm = sem.Mesh.from_box(mesh)
+    b = torch.ones(mesh.n_local, dtype=torch.float32, device="cuda")
+    b[5] = float("nan")
+    x, res = gm.cg_solve(b, prec=sem.FP32, tol=1e-6, max_iter=10)
+    assert res["status"] == 3 and res["converged"] == 0
+    gm.close()
+
+
+@pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
+def test_mixed_precision_reaches_1e10(geom):
+    """FP32 inner CG + FP64 outer residual: the true FP64 residual (checked
+    with the oracle's operator on the returned x) reaches 1e-10."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"mixed geom={geom}")
+    mesh = box_mesh(4, 4, 3, 9, perturb=0.1, seed=2111, reorient=True)
+    pr = oracle.Problem(mesh)
+    gm = sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=False)
+    b = _manufactured(gm, pr, sem.FP64)
+    bh = to_host(b)
+    x, res = gm.cg_solve(b, prec=sem.MIXED, geom=geom, tol=1e-10, inner_tol=1e-5)
+    assert res["converged"] == 1 and res["outer"] >= 2
+    xh = to_host(x)
+    assert pr.true_rel_residual(bh, xh) < 1.2e-10
+    xs, _, _ = pr.cg(bh, tol=1e-12, max_iter=20000)
+    assert rel_norm(xh, xs) < 1e-8
+    gm.close()
