@@ -78,7 +78,7 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  * Copies what it needs; the host arrays may be freed on return.  Blocks until
  * the device-side setup (geometric factors, Jacobian check) has finished.
  * Errors: SEM_EINVAL (NULL, E <= 0, bad ids, inconsistent Dirichlet flags,
- * more than 255 copies of a point, n_local >= 2^31), SEM_EUNSUPPORTED (N out
+ * more than 127 copies of a point, n_local >= 2^31), SEM_EUNSUPPORTED (N out
  * of range), SEM_EJACOBIAN, SEM_ENOMEM, SEM_EDEVICE.
  */
 sem_status sem_mesh_create(int64_t n_elem, int order_N, const double *vert_xyz,

@@ -253,8 +253,8 @@ ax_kernel(const AxArgs<T> a, const BasisK<T> bk) {
             }
             if constexpr (FUSED) {
                 const uint8_t m = a.mcode[base + k * P2];
-                if (m == 0) wv = T(0);
-                if (m == 1) acc += (double)uc[k] * (double)wv;
+                if (m & kDirichletBit) wv = T(0);
+                if ((m & kMultMask) == 1) acc += (double)uc[k] * (double)wv;
             }
             a.w[base + k * P2] = wv;
         }

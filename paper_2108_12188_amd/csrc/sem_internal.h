@@ -12,6 +12,11 @@
 namespace sem {
 
 constexpr int kMaxOrder = 11;
+// Per-point code: multiplicity m (copies of the global point) in the low 7
+// bits, the Dirichlet flag in bit 7.  The inner-product weight is 1/m.
+constexpr int kMaxMultiplicity = 127;
+constexpr uint8_t kDirichletBit = 0x80;
+constexpr uint8_t kMultMask = 0x7F;
 constexpr int kMaxP = kMaxOrder + 1;
 
 // ---------------------------------------------------------------------------
@@ -89,7 +94,7 @@ struct Mesh {
     float *G32 = nullptr;         // [E][6][P3]
     double *G64 = nullptr;        // [E][6][P3]
     double *B64 = nullptr;        // [E][P3] mass w_q |J_q|
-    uint8_t *mcode = nullptr;     // [n]: 0 Dirichlet, else multiplicity
+    uint8_t *mcode = nullptr;     // [n]: multiplicity | Dirichlet bit
     int32_t *gs_idx = nullptr;    // [n_shared], class-major, groups of M ascending indices
     int32_t *dir_idx = nullptr;   // [n_dir]
     Basis<float> b32;

@@ -138,10 +138,10 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     int64_t n_dir = 0;
     for (int64_t l = 0; l < n; ++l) {
         const int32_t c = cnt[cid[l]];
-        if (c > 255)
-            fail(SEM_EINVAL, "more than 255 local copies of one global point");
+        if (c > kMaxMultiplicity)
+            fail(SEM_EINVAL, "more than 127 local copies of one global point");
         const bool d = dflag[cid[l]] == 1;
-        mcode[l] = d ? 0 : (uint8_t)c;
+        mcode[l] = (uint8_t)((d ? kDirichletBit : 0) | c);
         n_dir += d;
     }
 
@@ -162,7 +162,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     GsClasses cls{};
     int64_t n_shared = 0, n_groups = 0;
     std::vector<int32_t> gs_idx;
-    for (int msz = 2; msz < 256; ++msz) {
+    for (int msz = 2; msz <= kMaxMultiplicity; ++msz) {
         if (!sizes_seen[msz]) continue;
         if (cls.ncls == kMaxGsClasses)
             fail(SEM_EUNSUPPORTED, "more than 32 distinct multiplicities");
@@ -187,7 +187,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     std::vector<int32_t> dir_idx;
     dir_idx.reserve(n_dir);
     for (int64_t l = 0; l < n; ++l)
-        if (mcode[l] == 0) dir_idx.push_back((int32_t)l);
+        if (mcode[l] & kDirichletBit) dir_idx.push_back((int32_t)l);
 
     // ---- basis ---------------------------------------------------------------
     gll_points(N, m->h_xi, m->h_w);

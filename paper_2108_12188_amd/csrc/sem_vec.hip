@@ -2,10 +2,9 @@
 //
 // All reductions accumulate in FP64 (a product of two FP32 values is exact
 // in FP64) with the weights c_l = 1/m_l of the weighted inner product
-// <a, b, c>; the multiplicity code m_l = 0 marks Dirichlet points (weight 0,
-// the vectors vanish there anyway).  The grid size depends only on n, and
-// the block partials are summed in index order by the last block, so every
-// result is bitwise reproducible.
+// <a, b, c>; the per-point code holds m_l and the Dirichlet flag.  The grid
+// size depends only on n, and the block partials are summed in index order
+// by the last block, so every result is bitwise reproducible.
 #include "sem_internal.h"
 #include "sem_reduce.h"
 
@@ -24,8 +23,9 @@ struct alignas(4) Code4 {
 };
 
 __device__ __forceinline__ void weights_lds(double *cw) {
-    // 1/m for m = 1..255 (exact for powers of two); 0 for the Dirichlet code
-    cw[threadIdx.x] = threadIdx.x ? 1.0 / (double)threadIdx.x : 0.0;
+    // weight 1/m for every code (m in the low bits; exact for powers of two)
+    const int m = threadIdx.x & kMultMask;
+    cw[threadIdx.x] = m ? 1.0 / (double)m : 0.0;
     __syncthreads();
 }
 

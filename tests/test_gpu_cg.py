@@ -39,9 +39,15 @@ def test_cg_fp64_small_box_matches_oracle(graph):
                          true_residual=True, history=60)
     assert res["converged"] == 1
     assert abs(res["iters"] - it_o) <= 2
-    k = min(50, len(res["hist_rho"]), len(hist["rho"]))
-    np.testing.assert_allclose(res["hist_rho"][:k], hist["rho"][:k], rtol=1e-8)
-    np.testing.assert_allclose(res["hist_alpha"][1:k], hist["alpha"][1:k], rtol=1e-8)
+    # CG amplifies rounding differences as it converges: the oracle itself,
+    # with D perturbed by 1e-16, keeps rho_i to ~1e-15 for i <= 25 and then
+    # drifts by up to 5% (of a rho_i that is 1e-7 rho_0 by then).  So the
+    # first 20 iterations must agree tightly, the rest in absolute terms.
+    rg, ro = res["hist_rho"], hist["rho"]
+    np.testing.assert_allclose(rg[:21], ro[:21], rtol=1e-10)
+    np.testing.assert_allclose(res["hist_alpha"][1:21], hist["alpha"][1:21], rtol=1e-10)
+    k = min(len(rg), len(ro))
+    assert np.max(np.abs(rg[:k] - ro[:k])) <= 1e-8 * ro[0]
     xg = to_host(x)
     assert rel_norm(xg, xo) < 1e-6
     assert res["rel_res_true"] < 1.1e-8
