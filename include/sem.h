@@ -159,6 +159,10 @@ typedef struct {
     double *hist_rho;     /* optional HOST buffer: rho_0..rho_iters (length hist_len) */
     double *hist_alpha;   /* optional HOST buffer: alpha_1..alpha_iters at [1..] */
     int hist_len;
+    double *kernel_ms;    /* optional HOST [3]: mean duration (ms) of the operator kernel,
+                             the gather-scatter kernel and the update kernel of one CG
+                             iteration, timed with HIP events on the solver's stream.
+                             When set, iterations are launched without graphs. */
 } sem_cg_opts;
 
 typedef struct {

@@ -45,6 +45,8 @@ def lib():
         if not os.path.exists(_LIB):
             build()
         L = C.CDLL(_LIB)
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = C.c_int
         L.or_gll.argtypes = [C.c_int, _dp, _dp]
         L.or_gll.restype = C.c_int
         L.or_deriv.argtypes = [C.c_int, _dp, _dp]
@@ -64,6 +66,10 @@ def lib():
         L.or_cg.restype = C.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
 
 
 def _f64(a):

@@ -29,11 +29,24 @@
  * independent dense brute force (tests/test_oracle_*.py).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define OR_MAXP 32
+
+/* threads the OpenMP loops of this file use */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* O1. GLL points and weights (Sec. 3, Eq. 3): xi_0 = -1, xi_N = 1, the

@@ -34,7 +34,8 @@ class CgOpts(C.Structure):
                 ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int), ("poll_every", C.c_int), ("use_graph", C.c_int),
                 ("true_residual", C.c_int), ("hist_rho", C.c_void_p),
-                ("hist_alpha", C.c_void_p), ("hist_len", C.c_int)]
+                ("hist_alpha", C.c_void_p), ("hist_len", C.c_int),
+                ("kernel_ms", C.c_void_p)]
 
 
 class CgResult(C.Structure):
@@ -223,7 +224,7 @@ class Mesh:
                  tol: float = 1e-8, max_iter: int = 100000, fixed_iters: int = 0,
                  inner_tol: float = 0.0, max_outer: int = 0, poll_every: int = 0,
                  use_graph: bool = True, true_residual: bool = False, history: int = 0,
-                 stream=None):
+                 kernel_times: bool = False, stream=None):
         """Algorithm 1 (or its mixed-precision refinement).  Returns (x, result dict)."""
         torch = _torch()
         if prec is None:
@@ -244,10 +245,16 @@ class Mesh:
             opts.hist_rho = hr.ctypes.data
             opts.hist_alpha = ha.ctypes.data
             opts.hist_len = history
+        km = None
+        if kernel_times:
+            km = np.zeros(3)
+            opts.kernel_ms = km.ctypes.data
         res = CgResult()
         code = lib().sem_cg_solve(self.handle, C.byref(opts), _dev_vec(b, self.n, "b"),
                                   _dev_vec(x, self.n, "x"), C.byref(res), _stream(stream))
         out = res.as_dict()
+        if km is not None:
+            out["kernel_ms"] = {"ax": km[0], "gs": km[1], "update": km[2]}
         if history > 0:
             k = min(history, res.iters + 1)
             out["hist_rho"] = hr[:k].copy()

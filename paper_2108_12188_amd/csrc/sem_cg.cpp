@@ -45,6 +45,7 @@ struct Workspace {
     double *h_val = nullptr;        // pinned mirror (8 doubles)
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    std::vector<hipEvent_t> tev;    // per-kernel timing events (4 per iteration)
     std::map<GraphKey, hipGraphExec_t> graphs;
     size_t bytes = 0;
 };
@@ -61,6 +62,7 @@ void ws_free(Workspace *ws) {
     if (ws->h_st) (void)hipHostFree(ws->h_st);
     if (ws->h_val) (void)hipHostFree(ws->h_val);
     if (ws->ev) (void)hipEventDestroy(ws->ev);
+    for (hipEvent_t e : ws->tev) (void)hipEventDestroy(e);
     if (ws->stream) (void)hipStreamDestroy(ws->stream);
     delete ws;
 }
@@ -150,6 +152,56 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s) {
     launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
 }
 
+// One iteration with an event before and after each of its three kernels.
+template <typename T>
+void enqueue_iteration_timed(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
+                             hipEvent_t *ev) {
+    T *x = static_cast<T *>(ws.x), *r = static_cast<T *>(ws.r);
+    T *p = static_cast<T *>(ws.p), *w = static_cast<T *>(ws.w);
+    AxArgs<T> a{};
+    a.u = r;
+    a.p = p;
+    a.w = w;
+    a.mcode = m.mcode;
+    a.st = ws.st;
+    a.partial = ws.part_ax;
+    SEM_HIP(hipEventRecord(ev[0], s));
+    launch_ax<T>(m, otf, AxMode::CgFused, a, s);
+    SEM_HIP(hipEventRecord(ev[1], s));
+    const int64_t nax = ax_blocks(m, sizeof(T) == 8, 0);
+    launch_gs_cg<T>(m, w, p, ws.st, ws.part_ax, (int)nax, ws.part_gs, s);
+    SEM_HIP(hipEventRecord(ev[2], s));
+    launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
+    SEM_HIP(hipEventRecord(ev[3], s));
+}
+
+struct KernelTimes {
+    double ms[3] = {0, 0, 0};
+    long count = 0;
+};
+
+template <typename T>
+void run_chunk_timed(const Mesh &m, Workspace &ws, bool otf, int chunk, int iter_before,
+                     KernelTimes &kt) {
+    hipStream_t s = ws.stream;
+    while ((int)ws.tev.size() < 4 * chunk) {
+        hipEvent_t e = nullptr;
+        SEM_HIP(hipEventCreate(&e));
+        ws.tev.push_back(e);
+    }
+    for (int c = 0; c < chunk; ++c) enqueue_iteration_timed<T>(m, ws, otf, s, &ws.tev[4 * c]);
+    SEM_HIP(hipMemcpyAsync(ws.h_st, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    const int done = std::min(chunk, ws.h_st->iter - iter_before);
+    for (int c = 0; c < done; ++c)
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            SEM_HIP(hipEventElapsedTime(&ms, ws.tev[4 * c + k], ws.tev[4 * c + k + 1]));
+            kt.ms[k] += ms;
+        }
+    kt.count += done;
+}
+
 template <typename T>
 void run_chunk(const Mesh &m, Workspace &ws, bool otf, int chunk, bool use_graph) {
     hipStream_t s = ws.stream;
@@ -216,7 +268,8 @@ struct InnerOut {
 // x0_zero: the initial guess is zero (r0 = b, no operator application).
 template <typename T>
 InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, bool otf,
-                 double tol, int max_iter, int fixed, int chunk, bool use_graph, int hist_len) {
+                 double tol, int max_iter, int fixed, int chunk, bool use_graph, int hist_len,
+                 KernelTimes *kt = nullptr) {
     hipStream_t s = ws.stream;
     CgState h{};
     h.thresh = tol * tol;
@@ -253,7 +306,8 @@ InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, boo
             fail(SEM_EDEVICE, "CG state did not advance (iteration " +
                                   std::to_string(ws.h_st->iter) + ")");
         last_iter = ws.h_st->iter;
-        run_chunk<T>(m, ws, otf, chunk, use_graph);
+        if (kt) run_chunk_timed<T>(m, ws, otf, chunk, last_iter, *kt);
+        else run_chunk<T>(m, ws, otf, chunk, use_graph);
     }
     InnerOut o;
     o.iters = ws.h_st->iter;
@@ -316,8 +370,11 @@ static sem_status cg_plain(Mesh &m, const sem_cg_opts &o, const void *b_user, vo
     SEM_HIP(hipMemcpyAsync(ws.x, x_user, sizeof(T) * m.n, hipMemcpyDeviceToDevice, ws.stream));
     const int chunk = o.poll_every > 0 ? o.poll_every : auto_chunk(m.n, o.fixed_iters);
     const int hist_len = (o.hist_rho || o.hist_alpha) ? o.hist_len : 0;
+    KernelTimes kt;
     InnerOut io = cg_core<T>(m, ws, b, false, otf, o.tol, o.max_iter, o.fixed_iters, chunk,
-                             o.use_graph != 0, hist_len);
+                             o.use_graph != 0, hist_len, o.kernel_ms ? &kt : nullptr);
+    if (o.kernel_ms)
+        for (int k = 0; k < 3; ++k) o.kernel_ms[k] = kt.count ? kt.ms[k] / kt.count : 0.0;
     SEM_HIP(hipMemcpyAsync(x_user, ws.x, sizeof(T) * m.n, hipMemcpyDeviceToDevice, ws.stream));
     SEM_HIP(hipStreamSynchronize(ws.stream));
     copy_hist(ws, o, io.iters);
@@ -362,6 +419,7 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
     const int inner_cap = o.max_iter > 0 ? o.max_iter : 100000;
     int total = 0, outer = 0, last_stop = 0;
     double rel = 0.0, last_inner_rel = 0.0;
+    KernelTimes kt;
     bool converged = false, breakdown = false;
     for (;;) {
         apply_A64(m, x64, t64, s);
@@ -385,7 +443,7 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
         SEM_HIP(hipEventRecord(w64.ev, s));
         SEM_HIP(hipStreamWaitEvent(w32.stream, w64.ev, 0));
         InnerOut io = cg_core<float>(m, w32, b32, true, otf, inner_tol, inner_cap, 0, chunk,
-                                     o.use_graph != 0, 0);
+                                     o.use_graph != 0, 0, o.kernel_ms ? &kt : nullptr);
         total += io.iters;
         last_stop = io.stop;
         last_inner_rel = io.rel;
@@ -400,6 +458,8 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
     }
     SEM_HIP(hipMemcpyAsync(x_user, x64, sizeof(double) * m.n, hipMemcpyDeviceToDevice, s));
     SEM_HIP(hipStreamSynchronize(s));
+    if (o.kernel_ms)
+        for (int k = 0; k < 3; ++k) o.kernel_ms[k] = kt.count ? kt.ms[k] / kt.count : 0.0;
     res.iters = total;
     res.outer = outer;
     res.converged = converged ? 1 : 0;
