@@ -37,28 +37,35 @@ def _compile(src: str, obj: str, extra=()):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, out: str | None = None,
+          defines=(), build_dir: str | None = None) -> str:
+    """Compile every translation unit and link `out` (default: libsem.so in
+    the package).  `defines` are extra -D flags for every unit."""
+    bdir = build_dir or BUILD
+    lib = out or LIB
+    os.makedirs(bdir, exist_ok=True)
+    dflags = [f"-D{d}" for d in defines]
     jobs = jobs or min(16, os.cpu_count() or 4)
     tasks = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for N in ORDERS:
             tasks.append(ex.submit(_compile, "sem_ax_order.hip",
-                                   os.path.join(BUILD, f"ax_order_{N}.o"), [f"-DSEM_ORDER={N}"]))
+                                   os.path.join(bdir, f"ax_order_{N}.o"),
+                                   [f"-DSEM_ORDER={N}", *dflags]))
         for src in SOURCES:
             if os.path.exists(os.path.join(CSRC, src)):
-                obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-                tasks.append(ex.submit(_compile, src, obj))
+                obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+                tasks.append(ex.submit(_compile, src, obj, dflags))
         objs = [t.result() for t in tasks]
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

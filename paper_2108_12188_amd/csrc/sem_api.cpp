@@ -182,11 +182,10 @@ sem_status sem_dot(sem_mesh_t mesh, sem_precision prec, const void *a_dev, const
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         if (prec == SEM_FP32)
             launch_dot<float>(*m, static_cast<const float *>(a_dev),
-                              static_cast<const float *>(b_dev), out_dev, m->state, m->scratch, s);
+                              static_cast<const float *>(b_dev), out_dev, m->scratch, s);
         else
             launch_dot<double>(*m, static_cast<const double *>(a_dev),
-                               static_cast<const double *>(b_dev), out_dev, m->state, m->scratch,
-                               s);
+                               static_cast<const double *>(b_dev), out_dev, m->scratch, s);
         return SEM_OK;
     });
 }

@@ -7,9 +7,9 @@ namespace sem {
 
 #define SEM_DECL_ORDER(N)                                                                       \
     void ax_order_##N##_f32(bool, AxMode, const AxArgs<float> &, const double *, const double *, \
-                            const double *, hipStream_t);                                       \
+                            const double *, int64_t, hipStream_t);                              \
     void ax_order_##N##_f64(bool, AxMode, const AxArgs<double> &, const double *,               \
-                            const double *, const double *, hipStream_t);
+                            const double *, const double *, int64_t, hipStream_t);
 SEM_DECL_ORDER(1)
 SEM_DECL_ORDER(2)
 SEM_DECL_ORDER(3)
@@ -24,9 +24,21 @@ SEM_DECL_ORDER(11)
 #undef SEM_DECL_ORDER
 
 using Fn32 = void (*)(bool, AxMode, const AxArgs<float> &, const double *, const double *,
-                      const double *, hipStream_t);
+                      const double *, int64_t, hipStream_t);
 using Fn64 = void (*)(bool, AxMode, const AxArgs<double> &, const double *, const double *,
-                      const double *, hipStream_t);
+                      const double *, int64_t, hipStream_t);
+
+// The CG-fused operator writes one FP64 partial per block; its grid is
+// capped so that the partial sum stays short (tiles are then strided).
+#ifndef SEM_AX_FUSED_MAX_BLOCKS
+#define SEM_AX_FUSED_MAX_BLOCKS 2048
+#endif
+constexpr int64_t kAxFusedMaxBlocks = SEM_AX_FUSED_MAX_BLOCKS;
+
+static int64_t ax_grid(int64_t ntiles, AxMode mode) {
+    if (mode == AxMode::CgFused && ntiles > kAxFusedMaxBlocks) return kAxFusedMaxBlocks;
+    return ntiles;
+}
 
 static const Fn32 kFn32[kMaxOrder + 1] = {nullptr,        ax_order_1_f32, ax_order_2_f32,
                                           ax_order_3_f32, ax_order_4_f32, ax_order_5_f32,
@@ -75,7 +87,8 @@ void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hip
     a.wq = m.b32.w;
     a.vert = m.vert32;
     if (!otf) a.G = m.G32;
-    kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), s);
+    const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
+    kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), ax_grid(ntiles, mode), s);
     check_hip(hipGetLastError(), "ax kernel launch (fp32)");
 }
 
@@ -90,13 +103,14 @@ void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, h
     a.wq = m.b64.w;
     a.vert = m.vert64;
     if (!otf) a.G = m.G64;
-    kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), s);
+    const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
+    kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), ax_grid(ntiles, mode), s);
     check_hip(hipGetLastError(), "ax kernel launch (fp64)");
 }
 
 int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override) {
     const AxShape sh = ax_shape(m.N, fp64, epb_override);
-    return (m.E + sh.epb - 1) / sh.epb;
+    return ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused);
 }
 
 }  // namespace sem

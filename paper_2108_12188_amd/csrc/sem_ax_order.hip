@@ -10,8 +10,11 @@
 //   * Plain: w = A_L u;
 //   * CgFused: the p-update of Algorithm 1 is the prologue (p <- r + beta p,
 //     the loop fusion of Sec. 5.1), the Dirichlet mask is the epilogue, and
-//     the FP64 partial of <p, w, c> over points of multiplicity 1 is reduced
-//     per block (those points are untouched by the gather-scatter).
+//     the block's FP64 partial of sum_l p_l w_l is reduced.  Because p is
+//     continuous (p = Q p_g) and the weights of every group add up to one,
+//     <p, QQ^T w, c> = p_g^T Q^T w = sum_l p_l w_l over the local, not yet
+//     gathered w: the whole alpha reduction of Algorithm 1 happens here, before
+//     the gather-scatter, instead of after it as in Sec. 5.1.
 //
 // Work decomposition (gfx950, 64-lane waves): a block holds `epb` elements;
 // one thread owns one (i, j) column of one element and walks the k
@@ -19,6 +22,7 @@
 // element tile from LDS; the k-direction contraction is register-only with
 // D entries that are wave-uniform (kernel-argument / scalar registers).
 #include "sem_internal.h"
+#include "sem_reduce.h"
 
 #ifndef SEM_ORDER
 #error "compile with -DSEM_ORDER=<N>"
@@ -29,6 +33,16 @@ namespace {
 
 constexpr int kOrder = SEM_ORDER;
 constexpr int kP = kOrder + 1;
+
+// Precomputed form: issue the loads of all 6 P factors of a column before
+// the first barrier (more loads in flight per wave) when the registers allow.
+#ifndef SEM_AX_PREFETCH_G
+#define SEM_AX_PREFETCH_G 0
+#endif
+template <typename T>
+constexpr bool prefetch_g() {
+    return SEM_AX_PREFETCH_G && 6 * kP * sizeof(T) <= 6 * 8 * 4;
+}
 
 // Kernel-argument copy of the basis: indexed only with compile-time
 // constants, so every access is a scalar load.
@@ -117,25 +131,20 @@ __device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T
     return g;
 }
 
-// Deterministic block sum of one double per thread; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double red[16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int q = 0; q < nw; ++q) s += red[q];
-    }
-    return s;
+    return block_sum_f64(v, red);
 }
 
+// FP32 kernels up to N = 7 are held to 128 VGPRs (4 waves per SIMD): the
+// on-the-fly form is latency-bound below that occupancy.  Higher orders and
+// FP64 keep their registers (capping them spills).
+template <typename T>
+constexpr int ax_min_waves() { return (sizeof(T) == 4 && kP <= 8) ? 4 : 1; }
+
 template <typename T, bool OTF, bool FUSED>
-__global__ void __launch_bounds__(512)
-ax_kernel(const AxArgs<T> a, const BasisK<T> bk) {
+__global__ void __launch_bounds__(512, ax_min_waves<T>())
+ax_kernel(const AxArgs<T> a, const BasisK<T> bk, int64_t ntiles) {
     constexpr int P = kP, P2 = P * P, P3 = P2 * P;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *const sA = reinterpret_cast<T *>(lds_raw);
@@ -150,32 +159,8 @@ ax_kernel(const AxArgs<T> a, const BasisK<T> bk) {
     const int col = t - el * P2;
     const int i = col % P;
     const int j = col / P;
-    const int64_t e = (int64_t)blockIdx.x * a.epb + el;
-    const bool valid = (el < a.epb) && (e < a.E);
-    const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
     T *const sa = sA + el * P3;
     T *const sb = sB + el * P3;
-
-    T uc[P];
-    T beta = T(0);
-    if constexpr (FUSED) beta = (T)a.st->beta;
-    if (valid) {
-        if constexpr (FUSED) {
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const T r = a.u[base + k * P2];
-                const T pold = a.p[base + k * P2];
-                uc[k] = r + beta * pold;
-            }
-#pragma unroll
-            for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
-        }
-#pragma unroll
-        for (int k = 0; k < P; ++k) sa[k * P2 + col] = uc[k];
-    }
 
     // per-lane rows of D and D^T for the i and j contractions
     T Di[P], Dj[P], DiT[P], DjT[P];
@@ -186,78 +171,123 @@ ax_kernel(const AxArgs<T> a, const BasisK<T> bk) {
         DiT[l] = a.Dt[i * P + l];
         DjT[l] = a.Dt[j * P + l];
     }
-
-    ColumnGeom<T> cg;
-    if constexpr (OTF) {
-        if (valid) {
-            cg = column_geom<T>(a.vert + e * 24, a.xi[i], a.xi[j], a.wq[i] * a.wq[j]);
-        }
-    }
-    __syncthreads();
-
-    T vsr[P], vtr[P];
-    if (valid) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            T ur = T(0), us = T(0), ut = T(0);
-#pragma unroll
-            for (int l = 0; l < P; ++l) {
-                ur += Di[l] * sa[k * P2 + j * P + l];
-                us += Dj[l] * sa[k * P2 + l * P + i];
-                ut += bk.D[k * P + l] * uc[l];
-            }
-            T vr, vs, vt;
-            if constexpr (OTF) {
-                const T gam = bk.xi[k];
-                const Vec3<T> r0 = axpy3(gam, cg.R01, cg.R00);
-                const Vec3<T> r1 = axpy3(gam, cg.R11, cg.R10);
-                const Vec3<T> r2 = axpy3(gam, axpy3(gam, cg.R22, cg.R21), cg.R20);
-                const T det = cg.d0 + gam * (cg.d1 + gam * cg.d2);
-                const T s = cg.wij * bk.w[k] * rcp<T>(det);
-                const Vec3<T> g{r0.x * ur + r1.x * us + r2.x * ut,
-                                r0.y * ur + r1.y * us + r2.y * ut,
-                                r0.z * ur + r1.z * us + r2.z * ut};
-                vr = s * dot3(r0, g);
-                vs = s * dot3(r1, g);
-                vt = s * dot3(r2, g);
-            } else {
-                const T *Ge = a.G + e * (6 * P3) + col + k * P2;
-                const T g11 = Ge[0], g12 = Ge[P3], g13 = Ge[2 * P3];
-                const T g22 = Ge[3 * P3], g23 = Ge[4 * P3], g33 = Ge[5 * P3];
-                vr = g11 * ur + g12 * us + g13 * ut;
-                vs = g12 * ur + g22 * us + g23 * ut;
-                vt = g13 * ur + g23 * us + g33 * ut;
-            }
-            sb[k * P2 + col] = vr;
-            vsr[k] = vs;
-            vtr[k] = vt;
-        }
-    }
-    __syncthreads();
-    if (valid) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) sa[k * P2 + col] = vsr[k];
-    }
-    __syncthreads();
+    T beta = T(0);
+    if constexpr (FUSED) beta = (T)a.st->beta;
 
     double acc = 0.0;
-    if (valid) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            T wv = T(0);
-#pragma unroll
-            for (int l = 0; l < P; ++l) {
-                wv += DiT[l] * sb[k * P2 + j * P + l];
-                wv += DjT[l] * sa[k * P2 + l * P + i];
-                wv += bk.D[l * P + k] * vtr[l];
-            }
+    // a tile is `epb` consecutive elements; the grid strides over tiles
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t e = tile * a.epb + el;
+        const bool valid = (el < a.epb) && (e < a.E);
+        const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
+
+        T uc[P];
+        if (valid) {
             if constexpr (FUSED) {
-                const uint8_t m = a.mcode[base + k * P2];
-                if (m & kDirichletBit) wv = T(0);
-                if ((m & kMultMask) == 1) acc += (double)uc[k] * (double)wv;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const T r = a.u[base + k * P2];
+                    const T pold = a.p[base + k * P2];
+                    uc[k] = r + beta * pold;
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
             }
-            a.w[base + k * P2] = wv;
+#pragma unroll
+            for (int k = 0; k < P; ++k) sa[k * P2 + col] = uc[k];
         }
+
+        ColumnGeom<T> cg;
+        if constexpr (OTF) {
+            if (valid) {
+                cg = column_geom<T>(a.vert + e * 24, a.xi[i], a.xi[j], a.wq[i] * a.wq[j]);
+            }
+        }
+        constexpr bool kPre = !OTF && prefetch_g<T>();
+        T gq[kPre ? 6 : 1][kPre ? P : 1];
+        if constexpr (kPre) {
+            if (valid) {
+                const T *Ge = a.G + e * (6 * P3) + col;
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+#pragma unroll
+                    for (int k = 0; k < P; ++k) gq[c][k] = Ge[c * P3 + k * P2];
+            }
+        }
+        __syncthreads();
+
+        T vsr[P], vtr[P];
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                T ur = T(0), us = T(0), ut = T(0);
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    ur += Di[l] * sa[k * P2 + j * P + l];
+                    us += Dj[l] * sa[k * P2 + l * P + i];
+                    ut += bk.D[k * P + l] * uc[l];
+                }
+                T vr, vs, vt;
+                if constexpr (OTF) {
+                    const T gam = bk.xi[k];
+                    const Vec3<T> r0 = axpy3(gam, cg.R01, cg.R00);
+                    const Vec3<T> r1 = axpy3(gam, cg.R11, cg.R10);
+                    const Vec3<T> r2 = axpy3(gam, axpy3(gam, cg.R22, cg.R21), cg.R20);
+                    const T det = cg.d0 + gam * (cg.d1 + gam * cg.d2);
+                    const T s = cg.wij * bk.w[k] * rcp<T>(det);
+                    const Vec3<T> g{r0.x * ur + r1.x * us + r2.x * ut,
+                                    r0.y * ur + r1.y * us + r2.y * ut,
+                                    r0.z * ur + r1.z * us + r2.z * ut};
+                    vr = s * dot3(r0, g);
+                    vs = s * dot3(r1, g);
+                    vt = s * dot3(r2, g);
+                } else {
+                    T g11, g12, g13, g22, g23, g33;
+                    if constexpr (kPre) {
+                        g11 = gq[0][k], g12 = gq[1][k], g13 = gq[2][k];
+                        g22 = gq[3][k], g23 = gq[4][k], g33 = gq[5][k];
+                    } else {
+                        const T *Ge = a.G + e * (6 * P3) + col + k * P2;
+                        g11 = Ge[0], g12 = Ge[P3], g13 = Ge[2 * P3];
+                        g22 = Ge[3 * P3], g23 = Ge[4 * P3], g33 = Ge[5 * P3];
+                    }
+                    vr = g11 * ur + g12 * us + g13 * ut;
+                    vs = g12 * ur + g22 * us + g23 * ut;
+                    vt = g13 * ur + g23 * us + g33 * ut;
+                }
+                sb[k * P2 + col] = vr;
+                vsr[k] = vs;
+                vtr[k] = vt;
+            }
+        }
+        __syncthreads();
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) sa[k * P2 + col] = vsr[k];
+        }
+        __syncthreads();
+
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                T wv = T(0);
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    wv += DiT[l] * sb[k * P2 + j * P + l];
+                    wv += DjT[l] * sa[k * P2 + l * P + i];
+                    wv += bk.D[l * P + k] * vtr[l];
+                }
+                if constexpr (FUSED) {
+                    if (a.mcode[base + k * P2] & kDirichletBit) wv = T(0);
+                    acc += (double)uc[k] * (double)wv;
+                }
+                a.w[base + k * P2] = wv;
+            }
+        }
+        __syncthreads();   // the next tile overwrites the LDS tile
     }
     if constexpr (FUSED) {
         const double s = block_sum(acc);
@@ -277,13 +307,13 @@ BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
 }
 
 template <typename T, bool OTF, bool FUSED>
-void launch(const AxArgs<T> &a, const BasisK<T> &bk, hipStream_t s) {
+void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s) {
     constexpr int P3 = kP * kP * kP;
     const int threads = ((a.epb * kP * kP + 63) / 64) * 64;
     const size_t lds = 2 * sizeof(T) * (size_t)a.epb * P3;
-    const int64_t blocks = (a.E + a.epb - 1) / a.epb;
-    hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       a, bk);
+    const int64_t ntiles = (a.E + a.epb - 1) / a.epb;
+    hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED>), dim3((unsigned)grid), dim3(threads), lds, s, a,
+                       bk, ntiles);
 }
 
 }  // namespace
@@ -293,27 +323,27 @@ void launch(const AxArgs<T> &a, const BasisK<T> &bk, hipStream_t s) {
 
 template <typename T>
 static void ax_entry(bool otf, AxMode mode, const AxArgs<T> &a, const double *D,
-                     const double *xi, const double *w, hipStream_t s) {
+                     const double *xi, const double *w, int64_t grid, hipStream_t s) {
     const BasisK<T> bk = make_basis<T>(D, xi, w);
     const bool fused = mode == AxMode::CgFused;
     if (otf) {
-        if (fused) launch<T, true, true>(a, bk, s);
-        else launch<T, true, false>(a, bk, s);
+        if (fused) launch<T, true, true>(a, bk, grid, s);
+        else launch<T, true, false>(a, bk, grid, s);
     } else {
-        if (fused) launch<T, false, true>(a, bk, s);
-        else launch<T, false, false>(a, bk, s);
+        if (fused) launch<T, false, true>(a, bk, grid, s);
+        else launch<T, false, false>(a, bk, grid, s);
     }
 }
 
 void SEM_CAT3(ax_order_, SEM_ORDER, _f32)(bool otf, AxMode mode, const AxArgs<float> &a,
                                            const double *D, const double *xi, const double *w,
-                                           hipStream_t s) {
-    ax_entry<float>(otf, mode, a, D, xi, w, s);
+                                           int64_t grid, hipStream_t s) {
+    ax_entry<float>(otf, mode, a, D, xi, w, grid, s);
 }
 void SEM_CAT3(ax_order_, SEM_ORDER, _f64)(bool otf, AxMode mode, const AxArgs<double> &a,
                                            const double *D, const double *xi, const double *w,
-                                           hipStream_t s) {
-    ax_entry<double>(otf, mode, a, D, xi, w, s);
+                                           int64_t grid, hipStream_t s) {
+    ax_entry<double>(otf, mode, a, D, xi, w, grid, s);
 }
 
 }  // namespace sem

@@ -2,12 +2,12 @@
 // refinement built on it.
 //
 // One CG iteration is three kernels:
-//   1. p <- r + beta p fused with w <- mask(A_L p) and the interior part of
-//      <p, w, c>  (Algorithm 1, p-update, operator and mask steps);
-//   2. w <- QQ^T w on the shared points, the shared part of <p, w, c>, and
-//      alpha = rho / <p, w, c> in the last block;
-//   3. x += alpha p, r -= alpha w, rho = <r, r, c>, beta and the convergence
-//      test in the last block.
+//   1. p <- r + beta p fused with w <- mask(A_L p) and the block partials of
+//      <p, w, c> (Algorithm 1: p-update, operator and mask steps);
+//   2. w <- QQ^T w on the shared points, then a one-block kernel forms
+//      alpha = rho / <p, w, c>;
+//   3. x += alpha p, r -= alpha w and the partials of rho = <r, r, c>, then a
+//      one-block kernel forms beta and runs the convergence test.
 // The CG scalars never leave the device.  Iterations are enqueued in chunks
 // (replayed HIP graphs by default); after each chunk the host reads the
 // state once.  Kernels of iterations past convergence exit at their first
@@ -34,9 +34,9 @@ struct Workspace {
     int64_t n = 0;
     int device = 0;
     void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *b = nullptr;
-    double *part_ax = nullptr, *part_gs = nullptr, *part_vec = nullptr;
+    double *part_ax = nullptr, *part_vec = nullptr;
     int64_t cap_ax = 0;
-    int cap_gs = 0, cap_vec = 0;
+    int cap_vec = 0;
     CgState *st = nullptr;          // device state of this workspace's solves
     CgState *h_st = nullptr;        // pinned mirror
     double *hist = nullptr;         // device histories: rho [cap], alpha [cap]
@@ -55,7 +55,7 @@ namespace {
 void ws_free(Workspace *ws) {
     if (!ws) return;
     for (auto &kv : ws->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->part_ax, ws->part_gs, ws->part_vec,
+    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->part_ax, ws->part_vec,
                    ws->st, ws->hist, ws->dval};
     for (void *q : dev)
         if (q) (void)hipFree(q);
@@ -94,10 +94,8 @@ Workspace *ws_create(const Mesh &m, bool fp64) {
         ws->b = ws_alloc<char>(*ws, nv);
         // the smallest shape (1 element per block) bounds the Ax partial count
         ws->cap_ax = m.E;
-        ws->cap_gs = gs_cg_blocks(m);
         ws->cap_vec = vec_blocks(m.n);
         ws->part_ax = ws_alloc<double>(*ws, ws->cap_ax);
-        ws->part_gs = ws_alloc<double>(*ws, ws->cap_gs);
         ws->part_vec = ws_alloc<double>(*ws, ws->cap_vec);
         ws->st = ws_alloc<CgState>(*ws, 1);
         ws->dval = ws_alloc<double>(*ws, 8);
@@ -148,7 +146,7 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s) {
     a.partial = ws.part_ax;
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, 0);
-    launch_gs_cg<T>(m, w, p, ws.st, ws.part_ax, (int)nax, ws.part_gs, s);
+    launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
 }
 
@@ -169,7 +167,7 @@ void enqueue_iteration_timed(const Mesh &m, Workspace &ws, bool otf, hipStream_t
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     SEM_HIP(hipEventRecord(ev[1], s));
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, 0);
-    launch_gs_cg<T>(m, w, p, ws.st, ws.part_ax, (int)nax, ws.part_gs, s);
+    launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     SEM_HIP(hipEventRecord(ev[2], s));
     launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
     SEM_HIP(hipEventRecord(ev[3], s));
@@ -337,8 +335,8 @@ double true_residual64(Mesh &m, const double *b64, const double *x64, Workspace 
     hipStream_t s = w64.stream;
     double *r = static_cast<double *>(w64.r), *wv = static_cast<double *>(w64.w);
     apply_A64(m, x64, wv, s);
-    launch_residual64(m, b64, wv, r, w64.dval + 0, w64.st, w64.part_vec, s);
-    launch_dot<double>(m, b64, b64, w64.dval + 1, w64.st, w64.part_vec, s);
+    launch_residual64(m, b64, wv, r, w64.dval + 0, w64.part_vec, s);
+    launch_dot<double>(m, b64, b64, w64.dval + 1, w64.part_vec, s);
     SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
     const double rr = w64.h_val[0], bb = w64.h_val[1];
@@ -412,7 +410,7 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
     double *t64 = static_cast<double *>(w64.w);
     SEM_HIP(hipMemcpyAsync(x64, x_user, sizeof(double) * m.n, hipMemcpyDeviceToDevice, s));
     launch_mask<double>(m, x64, s);
-    launch_dot<double>(m, b, b, w64.dval + 1, w64.st, w64.part_vec, s);
+    launch_dot<double>(m, b, b, w64.dval + 1, w64.part_vec, s);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
     const int chunk = o.poll_every > 0 ? o.poll_every : auto_chunk(m.n, 0);
@@ -423,7 +421,7 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
     bool converged = false, breakdown = false;
     for (;;) {
         apply_A64(m, x64, t64, s);
-        launch_residual64(m, b, t64, r64, w64.dval + 0, w64.st, w64.part_vec, s);
+        launch_residual64(m, b, t64, r64, w64.dval + 0, w64.part_vec, s);
         SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         SEM_HIP(hipStreamSynchronize(s));
         const double rr = w64.h_val[0], bb = w64.h_val[1];

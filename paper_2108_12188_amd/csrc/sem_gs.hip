@@ -1,5 +1,4 @@
-// sem_gs.hip -- gather-scatter QQ^T, Dirichlet mask, and the fused
-// <p, w, c> reduction of Algorithm 1.
+// sem_gs.hip -- gather-scatter QQ^T and the Dirichlet mask.
 //
 // Gather-scatter (Sec. 3.1, Sec. 4.3): every global point held by m > 1
 // local copies forms a group; the copies' values are summed in ascending
@@ -9,95 +8,105 @@
 // offsets array.  Inside a class, groups are in ascending order of their
 // first local index, which keeps neighbouring lanes on neighbouring faces.
 #include "sem_internal.h"
-#include "sem_reduce.h"
 
 namespace sem {
 namespace {
 
 constexpr int kGsThreads = 256;
-constexpr int kGsPerThread = 4;                   // groups per thread
-constexpr int kGsPerBlock = kGsThreads * kGsPerThread;
+constexpr int kXcds = 8;                          // MI355X: 8 XCDs, blocks dealt round-robin
 
+// groups per thread for a group size: about 8 copies per thread in flight
+__host__ __device__ constexpr int gs_per_thread(int M) { return M >= 8 ? 1 : (M >= 4 ? 2 : 4); }
+__host__ __device__ constexpr int64_t gs_per_block(int M) {
+    return (int64_t)kGsThreads * gs_per_thread(M);
+}
+
+template <int M>
+struct alignas(M * 4 <= 16 ? M * 4 : 16) IdxVec {
+    int32_t v[M];
+};
+
+// Groups of a compile-time size M: every lane first issues the index loads
+// of all its groups, then all value loads, so each lane keeps
+// kGsPerThread * M independent loads in flight (groups are disjoint, so the
+// stores of one group never alias the loads of another).
 template <typename T, int M>
-__device__ __forceinline__ void group_sum(const int32_t *__restrict__ idx, T *__restrict__ w,
-                                          const T *__restrict__ p, double &acc, bool dot) {
-    int32_t q[M];
+__device__ __forceinline__ void gs_groups_fixed(const int32_t *__restrict__ ib, int64_t g0,
+                                                int64_t ng, T *__restrict__ w) {
+    constexpr int kGsPerThread = gs_per_thread(M);
+    int32_t q[kGsPerThread][M];
+    bool ok[kGsPerThread];
 #pragma unroll
-    for (int t = 0; t < M; ++t) q[t] = idx[t];
-    T v[M];
+    for (int it = 0; it < kGsPerThread; ++it) {
+        const int64_t g = g0 + (int64_t)it * kGsThreads;
+        ok[it] = g < ng;
+        if (ok[it]) {
+            const IdxVec<M> *src = reinterpret_cast<const IdxVec<M> *>(ib + g * M);
+            const IdxVec<M> iv = *src;
 #pragma unroll
-    for (int t = 0; t < M; ++t) v[t] = w[q[t]];
-    T s = v[0];
+            for (int t = 0; t < M; ++t) q[it][t] = iv.v[t];
+        } else {
 #pragma unroll
-    for (int t = 1; t < M; ++t) s += v[t];
+            for (int t = 0; t < M; ++t) q[it][t] = 0;
+        }
+    }
+    T v[kGsPerThread][M];
 #pragma unroll
-    for (int t = 0; t < M; ++t) w[q[t]] = s;
-    if (dot) acc += (double)p[q[0]] * (double)s;
+    for (int it = 0; it < kGsPerThread; ++it)
+#pragma unroll
+        for (int t = 0; t < M; ++t) v[it][t] = ok[it] ? w[q[it][t]] : T(0);
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it) {
+        if (!ok[it]) continue;
+        T s = v[it][0];
+#pragma unroll
+        for (int t = 1; t < M; ++t) s += v[it][t];
+#pragma unroll
+        for (int t = 0; t < M; ++t) w[q[it][t]] = s;
+    }
 }
 
 template <typename T>
-__device__ __forceinline__ void group_sum_any(const int32_t *__restrict__ idx, int M,
-                                              T *__restrict__ w, const T *__restrict__ p,
-                                              double &acc, bool dot) {
-    T s = w[idx[0]];
-    for (int t = 1; t < M; ++t) s += w[idx[t]];
-    for (int t = 0; t < M; ++t) w[idx[t]] = s;
-    if (dot) acc += (double)p[idx[0]] * (double)s;
+__device__ __forceinline__ void gs_groups_any(const int32_t *__restrict__ ib, int M, int64_t g0,
+                                              int64_t ng, T *__restrict__ w) {
+    for (int it = 0; it < gs_per_thread(M); ++it) {
+        const int64_t g = g0 + (int64_t)it * kGsThreads;
+        if (g >= ng) break;
+        const int32_t *gi = ib + g * M;
+        T s = w[gi[0]];
+        for (int t = 1; t < M; ++t) s += w[gi[t]];
+        for (int t = 0; t < M; ++t) w[gi[t]] = s;
+    }
 }
 
-struct GsCfg {
-    GsClasses cls;
-    int64_t total_blocks;
-};
+// Physical block b runs logical block lb: the blocks that land on one XCD
+// (b mod 8) take one contiguous range of the group list, i.e. one region
+// of the mesh, so the neighbouring copies they touch share that XCD's L2.
+__device__ __forceinline__ int64_t logical_block(int64_t b, int64_t nb_phys) {
+    const int64_t per = nb_phys / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
 
-template <typename T, bool FUSED>
+// st (may be null): a stopped CG state makes the whole grid exit at once.
+template <typename T>
 __global__ void __launch_bounds__(kGsThreads)
-gs_kernel(const GsClasses cls, const int32_t *__restrict__ idx, T *__restrict__ w,
-          const T *__restrict__ p, CgState *st, const double *__restrict__ ax_partial,
-          int n_ax_partial, double *gs_partial) {
-    if constexpr (FUSED) {
-        if (st->stop) return;
-    }
-    // locate the size class of this block (uniform)
-    const int64_t b = blockIdx.x;
-    int c = 0;
-    while (c + 1 < cls.ncls && b >= cls.blk0[c + 1]) ++c;
-    double acc = 0.0;
-    if (c < cls.ncls && cls.ng[c] > 0) {
+gs_kernel(const GsClasses cls, int64_t nb_logical, const int32_t *__restrict__ idx,
+          T *__restrict__ w, const CgState *st) {
+    if (st && st->stop) return;
+    const int64_t b = logical_block(blockIdx.x, gridDim.x);
+    if (b < nb_logical) {
+        // size class of this block (uniform)
+        int c = 0;
+        while (c + 1 < cls.ncls && b >= cls.blk0[c + 1]) ++c;
         const int M = cls.M[c];
-        const int64_t g_first = (b - cls.blk0[c]) * kGsPerBlock;
+        const int64_t g0 = (b - cls.blk0[c]) * gs_per_block(M) + threadIdx.x;
         const int32_t *ib = idx + cls.io[c];
-#pragma unroll
-        for (int it = 0; it < kGsPerThread; ++it) {
-            const int64_t g = g_first + (int64_t)it * kGsThreads + threadIdx.x;
-            if (g < cls.ng[c]) {
-                const int32_t *gi = ib + g * M;
-                switch (M) {
-                    case 2: group_sum<T, 2>(gi, w, p, acc, FUSED); break;
-                    case 4: group_sum<T, 4>(gi, w, p, acc, FUSED); break;
-                    case 8: group_sum<T, 8>(gi, w, p, acc, FUSED); break;
-                    default: group_sum_any<T>(gi, M, w, p, acc, FUSED); break;
-                }
-            }
-        }
-    }
-    if constexpr (FUSED) {
-        __shared__ double red[16];
-        __shared__ int last_flag;
-        const double s = block_sum_f64(acc, red);
-        if (publish_partial(s, gs_partial, &st->cnt_gs, gridDim.x, &last_flag)) {
-            // <p, w, c> = interior part (from the Ax kernel) + shared part
-            const double a1 = sum_partials(ax_partial, n_ax_partial, red);
-            const double a2 = sum_partials(gs_partial, (int)gridDim.x, red);
-            if (threadIdx.x == 0) {
-                const double pw = a1 + a2;
-                const double alpha = st->rho / pw;
-                st->pw = pw;
-                st->alpha = alpha;
-                if (!(pw > 0.0) || !isfinite(alpha)) st->stop = 3;
-                const int i = st->iter + 1;
-                if (st->hist_alpha && i < st->hist_len) st->hist_alpha[i] = alpha;
-            }
+        const int64_t ng = cls.ng[c];
+        switch (M) {
+            case 2: gs_groups_fixed<T, 2>(ib, g0, ng, w); break;
+            case 4: gs_groups_fixed<T, 4>(ib, g0, ng, w); break;
+            case 8: gs_groups_fixed<T, 8>(ib, g0, ng, w); break;
+            default: gs_groups_any<T>(ib, M, g0, ng, w); break;
         }
     }
 }
@@ -110,18 +119,23 @@ __global__ void mask_kernel(const int32_t *__restrict__ dir, int64_t n_dir, T *_
 
 }  // namespace
 
+static int64_t gs_logical_blocks(const Mesh &m) {
+    const int c = m.gs.ncls - 1;
+    return c >= 0 ? m.gs.blk0[c] + (m.gs.ng[c] + gs_per_block(m.gs.M[c]) - 1) / gs_per_block(m.gs.M[c])
+                  : 0;
+}
+
+// physical grid: the logical block count rounded up to a multiple of the XCD count
 int gs_cg_blocks(const Mesh &m) {
-    int64_t b = m.gs.ncls > 0 ? m.gs.blk0[m.gs.ncls - 1] +
-                                    (m.gs.ng[m.gs.ncls - 1] + kGsPerBlock - 1) / kGsPerBlock
-                              : 0;
-    return (int)(b > 0 ? b : 1);
+    const int64_t b = gs_logical_blocks(m);
+    return (int)(b > 0 ? ((b + kXcds - 1) / kXcds) * kXcds : 1);
 }
 
 void gs_classes_finish(GsClasses &c) {
     int64_t blk = 0;
     for (int q = 0; q < c.ncls; ++q) {
         c.blk0[q] = blk;
-        blk += (c.ng[q] + kGsPerBlock - 1) / kGsPerBlock;
+        blk += (c.ng[q] + gs_per_block(c.M[q]) - 1) / gs_per_block(c.M[q]);
     }
 }
 
@@ -129,9 +143,8 @@ template <typename T>
 void launch_gs(const Mesh &m, T *w, hipStream_t s) {
     if (m.n_groups == 0) return;
     const int nb = gs_cg_blocks(m);
-    hipLaunchKernelGGL((gs_kernel<T, false>), dim3(nb), dim3(kGsThreads), 0, s, m.gs, m.gs_idx,
-                       w, (const T *)nullptr, (CgState *)nullptr, (const double *)nullptr, 0,
-                       (double *)nullptr);
+    hipLaunchKernelGGL((gs_kernel<T>), dim3(nb), dim3(kGsThreads), 0, s, m.gs,
+                       gs_logical_blocks(m), m.gs_idx, w, (const CgState *)nullptr);
     check_hip(hipGetLastError(), "gs kernel launch");
 }
 
@@ -144,21 +157,23 @@ void launch_mask(const Mesh &m, T *w, hipStream_t s) {
 }
 
 template <typename T>
-void launch_gs_cg(const Mesh &m, T *w, const T *p, CgState *st, const double *ax_partial,
-                  int n_ax_partial, double *gs_partial, hipStream_t s) {
-    const int nb = gs_cg_blocks(m);
-    hipLaunchKernelGGL((gs_kernel<T, true>), dim3(nb), dim3(kGsThreads), 0, s, m.gs, m.gs_idx, w,
-                       p, st, ax_partial, n_ax_partial, gs_partial);
-    check_hip(hipGetLastError(), "gs/cg kernel launch");
+void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, int n_ax_partial,
+                  hipStream_t s) {
+    if (m.n_groups > 0) {
+        hipLaunchKernelGGL((gs_kernel<T>), dim3(gs_cg_blocks(m)), dim3(kGsThreads), 0, s, m.gs,
+                           gs_logical_blocks(m), m.gs_idx, w, (const CgState *)st);
+        check_hip(hipGetLastError(), "gs/cg kernel launch");
+    }
+    launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
 }
 
 template void launch_gs<float>(const Mesh &, float *, hipStream_t);
 template void launch_gs<double>(const Mesh &, double *, hipStream_t);
 template void launch_mask<float>(const Mesh &, float *, hipStream_t);
 template void launch_mask<double>(const Mesh &, double *, hipStream_t);
-template void launch_gs_cg<float>(const Mesh &, float *, const float *, CgState *,
-                                  const double *, int, double *, hipStream_t);
-template void launch_gs_cg<double>(const Mesh &, double *, const double *, CgState *,
-                                   const double *, int, double *, hipStream_t);
+template void launch_gs_cg<float>(const Mesh &, float *, CgState *, const double *, int,
+                                  hipStream_t);
+template void launch_gs_cg<double>(const Mesh &, double *, CgState *, const double *, int,
+                                   hipStream_t);
 
 }  // namespace sem

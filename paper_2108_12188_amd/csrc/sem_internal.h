@@ -30,8 +30,8 @@ void check_hip(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------------------
 // Device-resident CG scalars of one solve (Algorithm 1: rho, alpha, beta).
-// Written only by the last block of a reduction kernel; read by every block
-// of the next kernel in stream order.
+// Written only by the one-block finalize kernels; read by every block of
+// the kernels that follow in stream order.
 // ---------------------------------------------------------------------------
 struct CgState {
     double rho;        // rho_{i-1}: <r, r, c> of the current residual
@@ -44,9 +44,6 @@ struct CgState {
     int max_iter;      // iteration cap
     int stop;          // 0 running, 1 converged, 2 cap reached, 3 breakdown
     int fixed;         // 1: no convergence test
-    unsigned int cnt_gs;   // completion counters of the last-block reductions
-    unsigned int cnt_upd;
-    unsigned int cnt_aux;
     int hist_len;      // capacity of the history arrays
     double *hist_rho;  // device history (may be null)
     double *hist_alpha;
@@ -137,7 +134,7 @@ struct AxArgs {
     const T *wq;                // [P]
     const uint8_t *mcode;       // CgFused: mask / interior weights
     CgState *st;                // CgFused: beta, stop flag
-    double *partial;            // CgFused: one FP64 partial of <p, w, c> per block
+    double *partial;            // CgFused: one FP64 partial of sum p w per block
 };
 
 // Launch configuration chosen for an order (threads, elements per block,
@@ -160,16 +157,18 @@ template <typename T>
 void launch_gs(const Mesh &m, T *w, hipStream_t s);
 template <typename T>
 void launch_mask(const Mesh &m, T *w, hipStream_t s);
+// CG step after the fused operator: gather-scatter, then alpha from the
+// operator kernel's partials of <p, w, c>
 template <typename T>
-void launch_gs_cg(const Mesh &m, T *w, const T *p, CgState *st, const double *ax_partial,
-                  int n_ax_partial, double *gs_partial, hipStream_t s);
+void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, int n_ax_partial,
+                  hipStream_t s);
 int gs_cg_blocks(const Mesh &m);
 
-// Algorithm 1 vector kernels (sem_vec.hip).  Reductions use one FP64
-// partial per block (`partial`, at least vec_blocks(n) entries) and the
-// completion counters inside `st`.
+// Algorithm 1 vector kernels (sem_vec.hip).  Reductions write one FP64
+// partial per block (`partial`, at least vec_blocks(n) entries) and a
+// one-block finalize kernel sums them in index order.
 int vec_blocks(int64_t n);
-// x += alpha p; r -= alpha w; rho = <r, r, c>; beta, convergence, history
+// x += alpha p; r -= alpha w; rho = <r, r, c>; then beta, convergence, history
 template <typename T>
 void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
                    double *partial, hipStream_t s);
@@ -179,11 +178,13 @@ void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *
                     double *partial, hipStream_t s);
 // *out = <a, b, c>
 template <typename T>
-void launch_dot(const Mesh &m, const T *a, const T *b, double *out, CgState *st,
-                double *partial, hipStream_t s);
+void launch_dot(const Mesh &m, const T *a, const T *b, double *out, double *partial,
+                hipStream_t s);
 // r = b - w and *out = <r, r, c>  (FP64 outer residual of the refinement)
 void launch_residual64(const Mesh &m, const double *b, const double *w, double *r, double *out,
-                       CgState *st, double *partial, hipStream_t s);
+                       double *partial, hipStream_t s);
+// alpha = rho / (sum of both partial sets)
+void launch_finalize_alpha(CgState *st, const double *part_ax, int64_t n_ax, hipStream_t s);
 // dst = (float)(src / sqrt(*nrm2))
 void launch_scale_to_f32(int64_t n, const double *src, const double *nrm2, float *dst,
                          hipStream_t s);

@@ -168,6 +168,8 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
             fail(SEM_EUNSUPPORTED, "more than 32 distinct multiplicities");
         const int c = cls.ncls++;
         cls.M[c] = msz;
+        // every class starts on a 32-byte boundary (vector index loads)
+        while (gs_idx.size() % 8) gs_idx.push_back(0);
         cls.io[c] = (int64_t)gs_idx.size();
         int64_t ng = 0;
         for (int64_t g = 0; g < G; ++g) {
@@ -179,6 +181,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         n_groups += ng;
         n_shared += ng * msz;
     }
+    while (gs_idx.size() % 8) gs_idx.push_back(0);
     gs_classes_finish(cls);
     m->gs = cls;
     m->n_groups = n_groups;

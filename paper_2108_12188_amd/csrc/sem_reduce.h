@@ -1,11 +1,15 @@
-// sem_reduce.h -- deterministic block and grid reductions used by the
-// reduction kernels (one FP64 partial per block, the last block to finish
-// sums the partials in index order).
+// sem_reduce.h -- deterministic reductions: every reduction kernel writes
+// one FP64 partial per block; a one-block finalize kernel that follows in
+// stream order sums the partials in index order.  (No grid-wide fences: on
+// a chip whose L2 caches are private to each XCD an agent-scope fence per
+// block costs an L2 write-back per block.)
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace sem {
+
+constexpr int kFinalizeThreads = 1024;
 
 // Sum of one double per thread in a fixed order; the result is valid in
 // thread 0 only.  Every thread of the block must call it.
@@ -24,33 +28,24 @@ __device__ __forceinline__ double block_sum_f64(double v, double *red /* >= 16 *
     return s;
 }
 
-// Publishes this block's partial and tells whether this block is the last
-// one of the grid to do so (then every partial is visible to it).  The
-// counter is reset by the last block, so the next launch starts from zero
-// without a memset.  Every thread of the block must call it.
-__device__ __forceinline__ bool publish_partial(double s, double *partial, unsigned int *counter,
-                                                unsigned int nblocks, int *flag_lds) {
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = s;
-        __threadfence();
-        const unsigned int prev = atomicAdd(counter, 1u);
-        *flag_lds = (prev == nblocks - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
-    return last;
-}
-
 // Fixed-order sum of partial[0..cnt) by one block: thread t sums the
 // entries t, t + blockDim, ... in order, then the block sums the threads.
-// The caller has executed the acquire fence of publish_partial.
-__device__ __forceinline__ double sum_partials(const double *partial, int cnt, double *red) {
+// The loads of a batch of kBatch entries are issued before they are added,
+// so the one block keeps many loads in flight.
+__device__ __forceinline__ double sum_partials(const double *partial, int64_t cnt, double *red) {
+    constexpr int kBatch = 8;
     double v = 0.0;
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) v += partial[q];
+    const int64_t step = (int64_t)blockDim.x * kBatch;
+    for (int64_t q0 = threadIdx.x; q0 < cnt; q0 += step) {
+        double t[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t q = q0 + (int64_t)u * blockDim.x;
+            t[u] = q < cnt ? partial[q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) v += t[u];
+    }
     return block_sum_f64(v, red);
 }
 

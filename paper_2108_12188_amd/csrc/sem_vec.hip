@@ -39,7 +39,6 @@ update_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restri
     if (st->stop) return;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
-    __shared__ int last_flag;
     weights_lds(cw);
     const T a = (T)st->alpha;
     double acc = 0.0;
@@ -69,19 +68,45 @@ update_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restri
         acc += (double)rn * (double)rn * cw[mcode[q]];
     }
     const double s = block_sum_f64(acc, red);
-    if (publish_partial(s, partial, &st->cnt_upd, gridDim.x, &last_flag)) {
-        const double rho = sum_partials(partial, (int)gridDim.x, red);
-        if (threadIdx.x == 0) {
-            const double beta = rho / st->rho;
-            st->beta = beta;
-            st->rho = rho;
-            const int it = st->iter + 1;
-            st->iter = it;
-            if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rho;
-            if (!isfinite(rho)) st->stop = 3;
-            else if (!st->fixed && rho <= st->thresh) st->stop = 1;
-            else if (it >= st->max_iter) st->stop = 2;
-        }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// rho_i = sum of the update partials; beta_i = rho_i / rho_{i-1}; the
+// iteration count, the history and the stopping test (Algorithm 1, last
+// two steps).  One block.
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_rho_kernel(CgState *st, const double *partial, int cnt) {
+    if (st->stop) return;
+    __shared__ double red[16];
+    const double rho = sum_partials(partial, cnt, red);
+    if (threadIdx.x == 0) {
+        const double beta = rho / st->rho;
+        st->beta = beta;
+        st->rho = rho;
+        const int it = st->iter + 1;
+        st->iter = it;
+        if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rho;
+        if (!isfinite(rho)) st->stop = 3;
+        else if (!st->fixed && rho <= st->thresh) st->stop = 1;
+        else if (it >= st->max_iter) st->stop = 2;
+    }
+}
+
+// alpha_i = rho_{i-1} / <p, w, c>, the inner product being the sum of the
+// operator kernel's partials (see the CgFused mode of the local operator).
+// One block.
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_alpha_kernel(CgState *st, const double *part_ax, int64_t n_ax) {
+    if (st->stop) return;
+    __shared__ double red[16];
+    const double pw = sum_partials(part_ax, n_ax, red);
+    if (threadIdx.x == 0) {
+        const double alpha = st->rho / pw;
+        st->pw = pw;
+        st->alpha = alpha;
+        if (!(pw > 0.0) || !isfinite(alpha)) st->stop = 3;
+        const int i = st->iter + 1;
+        if (st->hist_alpha && i < st->hist_len) st->hist_alpha[i] = alpha;
     }
 }
 
@@ -94,7 +119,6 @@ cg_init_kernel(int64_t n, const T *__restrict__ b, const T *__restrict__ w, T *_
                double *partial) {
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
-    __shared__ int last_flag;
     weights_lds(cw);
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -105,51 +129,49 @@ cg_init_kernel(int64_t n, const T *__restrict__ b, const T *__restrict__ w, T *_
         acc += (double)rv * (double)rv * cw[mcode[q]];
     }
     const double s = block_sum_f64(acc, red);
-    if (publish_partial(s, partial, &st->cnt_upd, gridDim.x, &last_flag)) {
-        const double rho0 = sum_partials(partial, (int)gridDim.x, red);
-        if (threadIdx.x == 0) {
-            st->rho = rho0;
-            st->rho0 = rho0;
-            st->thresh = st->thresh * rho0;
-            st->beta = 0.0;
-            st->alpha = 0.0;
-            st->iter = 0;
-            if (st->hist_rho && st->hist_len > 0) st->hist_rho[0] = rho0;
-            int stop = 0;
-            if (!isfinite(rho0)) stop = 3;
-            else if (rho0 == 0.0) stop = 1;
-            else if (st->max_iter <= 0) stop = 2;
-            st->stop = stop;
-        }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_init_kernel(CgState *st, const double *partial, int cnt) {
+    __shared__ double red[16];
+    const double rho0 = sum_partials(partial, cnt, red);
+    if (threadIdx.x == 0) {
+        st->rho = rho0;
+        st->rho0 = rho0;
+        st->thresh = st->thresh * rho0;
+        st->beta = 0.0;
+        st->alpha = 0.0;
+        st->iter = 0;
+        if (st->hist_rho && st->hist_len > 0) st->hist_rho[0] = rho0;
+        int stop = 0;
+        if (!isfinite(rho0)) stop = 3;
+        else if (rho0 == 0.0) stop = 1;
+        else if (st->max_iter <= 0) stop = 2;
+        st->stop = stop;
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
 dot_kernel(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
-           const uint8_t *__restrict__ mcode, double *out, CgState *st, double *partial) {
+           const uint8_t *__restrict__ mcode, double *partial) {
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
-    __shared__ int last_flag;
     weights_lds(cw);
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
         acc += (double)a[q] * (double)b[q] * cw[mcode[q]];
     const double s = block_sum_f64(acc, red);
-    if (publish_partial(s, partial, &st->cnt_aux, gridDim.x, &last_flag)) {
-        const double v = sum_partials(partial, (int)gridDim.x, red);
-        if (threadIdx.x == 0) *out = v;
-    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kVecThreads)
 residual64_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ w,
-                  double *__restrict__ r, const uint8_t *__restrict__ mcode, double *out,
-                  CgState *st, double *partial) {
+                  double *__restrict__ r, const uint8_t *__restrict__ mcode, double *partial) {
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
-    __shared__ int last_flag;
     weights_lds(cw);
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -159,10 +181,14 @@ residual64_kernel(int64_t n, const double *__restrict__ b, const double *__restr
         acc += rv * rv * cw[mcode[q]];
     }
     const double s = block_sum_f64(acc, red);
-    if (publish_partial(s, partial, &st->cnt_aux, gridDim.x, &last_flag)) {
-        const double v = sum_partials(partial, (int)gridDim.x, red);
-        if (threadIdx.x == 0) *out = v;
-    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_sum_kernel(double *out, const double *partial, int cnt) {
+    __shared__ double red[16];
+    const double v = sum_partials(partial, cnt, red);
+    if (threadIdx.x == 0) *out = v;
 }
 
 __global__ void scale_to_f32_kernel(int64_t n, const double *__restrict__ src,
@@ -212,31 +238,43 @@ int vec_blocks(int64_t n) {
 template <typename T>
 void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
                    double *partial, hipStream_t s) {
-    hipLaunchKernelGGL((update_kernel<T>), dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n, x,
-                       r, p, w, m.mcode, st, partial);
+    const int nb = vec_blocks(m.n);
+    hipLaunchKernelGGL((update_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, x, r, p, w,
+                       m.mcode, st, partial);
+    hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
+                       (const double *)partial, nb);
     check_hip(hipGetLastError(), "update kernel launch");
 }
 
 template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
                     double *partial, hipStream_t s) {
-    hipLaunchKernelGGL((cg_init_kernel<T>), dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n,
-                       b, w, r, p, m.mcode, st, partial);
+    const int nb = vec_blocks(m.n);
+    hipLaunchKernelGGL((cg_init_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, b, w, r, p,
+                       m.mcode, st, partial);
+    hipLaunchKernelGGL(finalize_init_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
+                       (const double *)partial, nb);
     check_hip(hipGetLastError(), "cg init kernel launch");
 }
 
 template <typename T>
-void launch_dot(const Mesh &m, const T *a, const T *b, double *out, CgState *st, double *partial,
+void launch_dot(const Mesh &m, const T *a, const T *b, double *out, double *partial,
                 hipStream_t s) {
-    hipLaunchKernelGGL((dot_kernel<T>), dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n, a,
-                       b, m.mcode, out, st, partial);
+    const int nb = vec_blocks(m.n);
+    hipLaunchKernelGGL((dot_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, a, b, m.mcode,
+                       partial);
+    hipLaunchKernelGGL(finalize_sum_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, out,
+                       (const double *)partial, nb);
     check_hip(hipGetLastError(), "dot kernel launch");
 }
 
 void launch_residual64(const Mesh &m, const double *b, const double *w, double *r, double *out,
-                       CgState *st, double *partial, hipStream_t s) {
-    hipLaunchKernelGGL(residual64_kernel, dim3(vec_blocks(m.n)), dim3(kVecThreads), 0, s, m.n, b,
-                       w, r, m.mcode, out, st, partial);
+                       double *partial, hipStream_t s) {
+    const int nb = vec_blocks(m.n);
+    hipLaunchKernelGGL(residual64_kernel, dim3(nb), dim3(kVecThreads), 0, s, m.n, b, w, r,
+                       m.mcode, partial);
+    hipLaunchKernelGGL(finalize_sum_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, out,
+                       (const double *)partial, nb);
     check_hip(hipGetLastError(), "residual kernel launch");
 }
 
@@ -274,10 +312,16 @@ template void launch_cg_init<float>(const Mesh &, const float *, const float *, 
                                     CgState *, double *, hipStream_t);
 template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,
                                      double *, CgState *, double *, hipStream_t);
-template void launch_dot<float>(const Mesh &, const float *, const float *, double *, CgState *,
-                                double *, hipStream_t);
+template void launch_dot<float>(const Mesh &, const float *, const float *, double *, double *,
+                                hipStream_t);
 template void launch_dot<double>(const Mesh &, const double *, const double *, double *,
-                                 CgState *, double *, hipStream_t);
+                                 double *, hipStream_t);
+
+void launch_finalize_alpha(CgState *st, const double *part_ax, int64_t n_ax, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_alpha_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st, part_ax,
+                       n_ax);
+    check_hip(hipGetLastError(), "finalize kernel launch");
+}
 template void launch_convert<float, double>(int64_t, const float *, double *, hipStream_t);
 template void launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);
 template void launch_convert<double, double>(int64_t, const double *, double *, hipStream_t);
