@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-__all__ = ["SemError", "Mesh", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
+__all__ = ["SemError", "Mesh", "Batch", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
            "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
@@ -264,3 +264,56 @@ class Mesh:
             return x, out
         _check(code)
         return x, out
+
+
+class Batch:
+    """Independent meshes solved together (one batched launch per kernel type
+    and CG iteration).  Each problem's result is bitwise that of its own
+    Mesh.cg_solve with the same options."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        arr = (C.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = C.c_void_p()
+        _check(lib().sem_batch_create(len(self.meshes), arr, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sem_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, xs=None, prec: int = MIXED, geom: int = PRECOMPUTED, tol: float = 1e-8,
+              max_iter: int = 100000, fixed_iters: int = 0, inner_tol: float = 0.0,
+              max_outer: int = 0, poll_every: int = 0, use_graph: bool = True, stream=None):
+        """Returns (xs, list of result dicts)."""
+        torch = _torch()
+        P = len(self.meshes)
+        if len(bs) != P:
+            raise ValueError("one right-hand side per mesh")
+        want = torch.float32 if prec == FP32 else torch.float64
+        if xs is None:
+            xs = [torch.zeros_like(b) for b in bs]
+        for m, b, x in zip(self.meshes, bs, xs):
+            if b.dtype != want or x.dtype != want:
+                raise TypeError("b and x must match the precision")
+            _dev_vec(b, m.n, "b")
+            _dev_vec(x, m.n, "x")
+        barr = (C.c_void_p * P)(*[b.data_ptr() for b in bs])
+        xarr = (C.c_void_p * P)(*[x.data_ptr() for x in xs])
+        res = (CgResult * P)()
+        opts = CgOpts(prec=prec, geom=geom, tol=tol, max_iter=max_iter, fixed_iters=fixed_iters,
+                      inner_tol=inner_tol, max_outer=max_outer, poll_every=poll_every,
+                      use_graph=1 if use_graph else 0, true_residual=0, hist_len=0)
+        code = lib().sem_batch_solve(self._h, C.byref(opts), barr, xarr, res, _stream(stream))
+        out = [r.as_dict() for r in res]
+        if code == -5:
+            return xs, out
+        _check(code)
+        return xs, out

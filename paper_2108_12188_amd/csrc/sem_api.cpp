@@ -40,6 +40,11 @@ void mesh_destroy(Mesh *m);
 sem_status cg_solve(Mesh &m, const sem_cg_opts &o, const void *b, void *x, sem_cg_result &res,
                     hipStream_t s);
 void api_apply_A64(const Mesh &m, const double *u, double *w, hipStream_t s);
+struct BatchImpl;
+BatchImpl *batch_new(int count, const sem_mesh_t *meshes);
+void batch_delete(BatchImpl *b);
+sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_dev,
+                       void *const *x_dev, sem_cg_result *res, hipStream_t user_s);
 
 template <typename F>
 static sem_status guarded(F &&f) {
@@ -258,25 +263,36 @@ sem_status sem_cg_solve(sem_mesh_t mesh, const sem_cg_opts *opts, const void *b_
 
 sem_status sem_batch_create(int count, const sem_mesh_t *meshes, sem_batch_t *out) {
     return guarded([&]() -> sem_status {
-        (void)count;
-        (void)meshes;
-        (void)out;
-        fail(SEM_EUNSUPPORTED, "batched solves are not built");
+        need(out, "out");
+        need(meshes, "meshes");
+        if (count <= 0) fail(SEM_EINVAL, "count must be positive");
+        DeviceGuard dg(as_mesh(meshes[0])->device);
+        *out = reinterpret_cast<sem_batch_t>(batch_new(count, meshes));
+        return SEM_OK;
     });
 }
 
-void sem_batch_destroy(sem_batch_t batch) { (void)batch; }
+void sem_batch_destroy(sem_batch_t batch) {
+    if (batch) batch_delete(reinterpret_cast<BatchImpl *>(batch));
+}
 
 sem_status sem_batch_solve(sem_batch_t batch, const sem_cg_opts *opts, const void *const *b_dev,
                            void *const *x_dev, sem_cg_result *results, void *hip_stream) {
     return guarded([&]() -> sem_status {
-        (void)batch;
-        (void)opts;
-        (void)b_dev;
-        (void)x_dev;
-        (void)results;
-        (void)hip_stream;
-        fail(SEM_EUNSUPPORTED, "batched solves are not built");
+        need(batch, "batch");
+        need(opts, "opts");
+        need(b_dev, "b_dev");
+        need(x_dev, "x_dev");
+        need(results, "results");
+        if (opts->fixed_iters <= 0 && !(opts->tol > 0.0))
+            fail(SEM_EINVAL, "tol must be positive unless fixed_iters > 0");
+        if (opts->geom != SEM_G_PRECOMPUTED && opts->geom != SEM_G_ON_THE_FLY)
+            fail(SEM_EINVAL, "unknown geometry form");
+        BatchImpl &B = *reinterpret_cast<BatchImpl *>(batch);
+        const sem_status st =
+            batch_solve(B, *opts, b_dev, x_dev, results, static_cast<hipStream_t>(hip_stream));
+        if (st == SEM_EBREAKDOWN) set_error("CG breakdown in at least one problem of the batch");
+        return st;
     });
 }
 

@@ -23,6 +23,29 @@ SEM_DECL_ORDER(10)
 SEM_DECL_ORDER(11)
 #undef SEM_DECL_ORDER
 
+#define SEM_DECL_BATCH(N)                                                                      \
+    void ax_batch_order_##N##_f32(bool, const AxArgs<float> *, const int2 *, int64_t, int,    \
+                                  const double *, const double *, const double *, hipStream_t);
+SEM_DECL_BATCH(1)
+SEM_DECL_BATCH(2)
+SEM_DECL_BATCH(3)
+SEM_DECL_BATCH(4)
+SEM_DECL_BATCH(5)
+SEM_DECL_BATCH(6)
+SEM_DECL_BATCH(7)
+SEM_DECL_BATCH(8)
+SEM_DECL_BATCH(9)
+SEM_DECL_BATCH(10)
+SEM_DECL_BATCH(11)
+#undef SEM_DECL_BATCH
+
+using FnB = void (*)(bool, const AxArgs<float> *, const int2 *, int64_t, int, const double *,
+                     const double *, const double *, hipStream_t);
+static const FnB kFnB[kMaxOrder + 1] = {
+    nullptr,           ax_batch_order_1_f32, ax_batch_order_2_f32, ax_batch_order_3_f32,
+    ax_batch_order_4_f32, ax_batch_order_5_f32, ax_batch_order_6_f32, ax_batch_order_7_f32,
+    ax_batch_order_8_f32, ax_batch_order_9_f32, ax_batch_order_10_f32, ax_batch_order_11_f32};
+
 using Fn32 = void (*)(bool, AxMode, const AxArgs<float> &, const double *, const double *,
                       const double *, int64_t, hipStream_t);
 using Fn64 = void (*)(bool, AxMode, const AxArgs<double> &, const double *, const double *,
@@ -106,6 +129,27 @@ void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, h
     const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
     kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), ax_grid(ntiles, mode), s);
     check_hip(hipGetLastError(), "ax kernel launch (fp64)");
+}
+
+void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
+    const AxShape sh = ax_shape(m.N, false, 0);
+    a.epb = sh.epb;
+    a.E = m.E;
+    a.D = m.b32.D;
+    a.Dt = m.b32.Dt;
+    a.xi = m.b32.xi;
+    a.wq = m.b32.w;
+    a.vert = m.vert32;
+    a.G = otf ? nullptr : m.G32;
+    a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused);
+}
+
+void launch_ax_batch(int N, bool otf, const AxArgs<float> *descs, const int2 *blk, int64_t nblk,
+                     int epb, const double *D, const double *xi, const double *w,
+                     hipStream_t s) {
+    if (nblk <= 0) return;
+    kFnB[N](otf, descs, blk, nblk, epb, D, xi, w, s);
+    check_hip(hipGetLastError(), "batched ax kernel launch");
 }
 
 int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override) {

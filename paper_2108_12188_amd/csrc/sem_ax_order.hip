@@ -142,9 +142,12 @@ __device__ __forceinline__ double block_sum(double v) {
 template <typename T>
 constexpr int ax_min_waves() { return (sizeof(T) == 4 && kP <= 8) ? 4 : 1; }
 
+// Tiles vb, vb + vgrid, vb + 2 vgrid, ... of one problem; in the fused mode
+// the block's partial goes to a.partial[vb].  Every thread of the block
+// calls it.
 template <typename T, bool OTF, bool FUSED>
-__global__ void __launch_bounds__(512, ax_min_waves<T>())
-ax_kernel(const AxArgs<T> a, const BasisK<T> bk, int64_t ntiles) {
+__device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk, int64_t ntiles,
+                                        int64_t vb, int64_t vgrid) {
     constexpr int P = kP, P2 = P * P, P3 = P2 * P;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *const sA = reinterpret_cast<T *>(lds_raw);
@@ -176,7 +179,7 @@ ax_kernel(const AxArgs<T> a, const BasisK<T> bk, int64_t ntiles) {
 
     double acc = 0.0;
     // a tile is `epb` consecutive elements; the grid strides over tiles
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = vb; tile < ntiles; tile += vgrid) {
         const int64_t e = tile * a.epb + el;
         const bool valid = (el < a.epb) && (e < a.E);
         const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
@@ -291,8 +294,27 @@ ax_kernel(const AxArgs<T> a, const BasisK<T> bk, int64_t ntiles) {
     }
     if constexpr (FUSED) {
         const double s = block_sum(acc);
-        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) a.partial[vb] = s;
     }
+}
+
+template <typename T, bool OTF, bool FUSED>
+__global__ void __launch_bounds__(512, ax_min_waves<T>())
+ax_kernel(const AxArgs<T> a, const BasisK<T> bk, int64_t ntiles) {
+    ax_body<T, OTF, FUSED>(a, bk, ntiles, blockIdx.x, gridDim.x);
+}
+
+// Many problems of this order in one launch: block b runs virtual block
+// blk[b].y of problem blk[b].x, exactly the block that problem's own launch
+// would run, so every problem's partials (and results) are bitwise those
+// of its solo solve.
+template <typename T, bool OTF>
+__global__ void __launch_bounds__(512, ax_min_waves<T>())
+ax_batch_kernel(const AxArgs<T> *__restrict__ descs, const int2 *__restrict__ blk,
+                const BasisK<T> bk) {
+    const int2 pv = blk[blockIdx.x];
+    const AxArgs<T> a = descs[pv.x];
+    ax_body<T, OTF, true>(a, bk, (a.E + a.epb - 1) / a.epb, pv.y, a.vgrid);
 }
 
 template <typename T>
@@ -333,6 +355,29 @@ static void ax_entry(bool otf, AxMode mode, const AxArgs<T> &a, const double *D,
         if (fused) launch<T, false, true>(a, bk, grid, s);
         else launch<T, false, false>(a, bk, grid, s);
     }
+}
+
+template <typename T>
+static void ax_batch_entry(bool otf, const AxArgs<T> *descs, const int2 *blk, int64_t nblk,
+                           int epb, const double *D, const double *xi, const double *w,
+                           hipStream_t s) {
+    constexpr int P3 = kP * kP * kP;
+    const BasisK<T> bk = make_basis<T>(D, xi, w);
+    const int threads = ((epb * kP * kP + 63) / 64) * 64;
+    const size_t lds = 2 * sizeof(T) * (size_t)epb * P3;
+    if (otf)
+        hipLaunchKernelGGL((ax_batch_kernel<T, true>), dim3((unsigned)nblk), dim3(threads), lds, s,
+                           descs, blk, bk);
+    else
+        hipLaunchKernelGGL((ax_batch_kernel<T, false>), dim3((unsigned)nblk), dim3(threads), lds, s,
+                           descs, blk, bk);
+}
+
+void SEM_CAT3(ax_batch_order_, SEM_ORDER, _f32)(bool otf, const AxArgs<float> *descs,
+                                                 const int2 *blk, int64_t nblk, int epb,
+                                                 const double *D, const double *xi,
+                                                 const double *w, hipStream_t s) {
+    ax_batch_entry<float>(otf, descs, blk, nblk, epb, D, xi, w, s);
 }
 
 void SEM_CAT3(ax_order_, SEM_ORDER, _f32)(bool otf, AxMode mode, const AxArgs<float> &a,

@@ -1,0 +1,503 @@
+// sem_batch.hip -- many independent meshes advanced together.
+//
+// One batched CG iteration is a fixed sequence of launches that each cover
+// every problem: the fused local operator once per polynomial order, then
+// the gather-scatter, the alpha finalize (one block per problem), the x/r
+// update and the rho finalize (one block per problem).  Block b of a
+// launch runs "virtual block" blk[b].y of problem blk[b].x -- exactly the
+// block that the problem's own single-mesh launch would run, with the same
+// tiles, the same grid stride and the same partial slot -- so every
+// problem's reductions happen in the same order as in its solo solve and
+// its result is bitwise identical.  Problems that have stopped exit at the
+// first instruction of their blocks.  The sequence is captured once in a
+// HIP graph and replayed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+
+#include "sem_cg_internal.h"
+#include "sem_gs_body.h"
+#include "sem_vec_body.h"
+
+namespace sem {
+namespace {
+
+struct GsBatchDesc {
+    const GsClasses *cls;
+    const int32_t *idx;
+    float *w;
+    const CgState *st;
+};
+
+struct UpdBatchDesc {
+    int64_t n;
+    float *x;
+    float *r;
+    const float *p;
+    const float *w;
+    const uint8_t *mcode;
+    CgState *st;
+    double *partial;
+    int64_t vgrid;
+};
+
+struct FinBatchDesc {
+    CgState *st;
+    const double *part_ax;
+    int64_t n_ax;
+    const double *part_vec;
+    int n_vec;
+};
+
+__global__ void __launch_bounds__(gsb::kGsThreads)
+gs_batch_kernel(const GsBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
+    const int2 pv = blk[blockIdx.x];
+    const GsBatchDesc g = d[pv.x];
+    if (g.st->stop) return;
+    gsb::gs_logical_block<float>(*g.cls, pv.y, g.idx, g.w);
+}
+
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_alpha_batch_kernel(const FinBatchDesc *__restrict__ d) {
+    const FinBatchDesc f = d[blockIdx.x];
+    vecb::finalize_alpha_body(f.st, f.part_ax, f.n_ax);
+}
+
+__global__ void __launch_bounds__(vecb::kVecThreads)
+update_batch_kernel(const UpdBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
+    const int2 pv = blk[blockIdx.x];
+    const UpdBatchDesc u = d[pv.x];
+    vecb::update_body<float>(u.n, u.x, u.r, u.p, u.w, u.mcode, u.st, u.partial, pv.y, u.vgrid);
+}
+
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_rho_batch_kernel(const FinBatchDesc *__restrict__ d) {
+    const FinBatchDesc f = d[blockIdx.x];
+    vecb::finalize_rho_body(f.st, f.part_vec, f.n_vec);
+}
+
+// (stop, iter) of every problem into one array for a single host read
+__global__ void gather_states_kernel(const FinBatchDesc *__restrict__ d, int count, int2 *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < count) out[q] = make_int2(d[q].st->stop, d[q].st->iter);
+}
+
+template <typename T>
+T *dalloc(size_t count, size_t &bytes) {
+    void *p = nullptr;
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SEM_ENOMEM, "batch allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes += b;
+    return static_cast<T *>(p);
+}
+
+template <typename T>
+void upload_sync(T *dst, const std::vector<T> &src) {
+    if (!src.empty())
+        SEM_HIP(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+struct BatchImpl {
+    int device = 0;
+    std::vector<Mesh *> meshes;
+    struct OrderGroup {
+        int N;
+        int epb;
+        int2 *blk = nullptr;
+        int64_t nblk = 0;
+    };
+    std::vector<OrderGroup> groups;
+    AxArgs<float> *d_ax[2] = {nullptr, nullptr};   // [precomputed, on the fly]
+    GsClasses *d_cls = nullptr;
+    GsBatchDesc *d_gs = nullptr;
+    int2 *d_gs_blk = nullptr;
+    int64_t n_gs_blk = 0;
+    UpdBatchDesc *d_upd = nullptr;
+    int2 *d_upd_blk = nullptr;
+    int64_t n_upd_blk = 0;
+    FinBatchDesc *d_fin = nullptr;
+    int2 *d_states = nullptr;
+    int2 *h_states = nullptr;                        // pinned
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    size_t bytes = 0;
+
+    ~BatchImpl() {
+        (void)hipDeviceSynchronize();
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto &g : groups)
+            if (g.blk) (void)hipFree(g.blk);
+        void *ptrs[] = {d_ax[0], d_ax[1], d_cls, d_gs, d_gs_blk, d_upd, d_upd_blk, d_fin,
+                        d_states};
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+        if (h_states) (void)hipHostFree(h_states);
+        if (ev) (void)hipEventDestroy(ev);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    int count() const { return (int)meshes.size(); }
+
+    // one batched CG iteration of every problem
+    void enqueue_iteration(bool otf, hipStream_t s) {
+        for (const auto &g : groups) {
+            launch_ax_batch(g.N, otf, d_ax[otf ? 1 : 0], g.blk, g.nblk, g.epb,
+                            order_D[g.N].data(), order_xi[g.N].data(), order_w[g.N].data(), s);
+        }
+        if (n_gs_blk > 0)
+            hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)n_gs_blk), dim3(gsb::kGsThreads), 0,
+                               s, d_gs, d_gs_blk);
+        hipLaunchKernelGGL(finalize_alpha_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0,
+                           s, d_fin);
+        hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)n_upd_blk), dim3(vecb::kVecThreads),
+                           0, s, d_upd, d_upd_blk);
+        hipLaunchKernelGGL(finalize_rho_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0, s,
+                           d_fin);
+        check_hip(hipGetLastError(), "batched iteration launch");
+    }
+
+    void run_chunk(bool otf, int chunk, bool use_graph) {
+        if (!use_graph) {
+            for (int c = 0; c < chunk; ++c) enqueue_iteration(otf, stream);
+            return;
+        }
+        const GraphKey key{otf, chunk};
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            hipGraph_t g = nullptr;
+            SEM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int c = 0; c < chunk; ++c) enqueue_iteration(otf, stream);
+            } catch (...) {
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(stream, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                throw;
+            }
+            SEM_HIP(hipStreamEndCapture(stream, &g));
+            hipGraphExec_t ge = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            check_hip(e, "hipGraphInstantiate (batch)");
+            it = graphs.emplace(key, ge).first;
+        }
+        SEM_HIP(hipGraphLaunch(it->second, stream));
+    }
+
+    // reads (stop, iter) of every problem
+    void read_states() {
+        hipLaunchKernelGGL(gather_states_kernel, dim3((count() + 255) / 256), dim3(256), 0, stream,
+                           d_fin, count(), d_states);
+        SEM_HIP(hipMemcpyAsync(h_states, d_states, sizeof(int2) * count(), hipMemcpyDeviceToHost,
+                               stream));
+        SEM_HIP(hipStreamSynchronize(stream));
+    }
+
+    // per order: host basis copies (FP64) for the kernel-argument basis
+    std::map<int, std::vector<double>> order_D, order_xi, order_w;
+};
+
+namespace {
+
+BatchImpl *batch_create(int count, const sem_mesh_t *handles) {
+    if (count <= 0) fail(SEM_EINVAL, "count must be positive");
+    if (!handles) fail(SEM_EINVAL, "meshes must not be NULL");
+    std::unique_ptr<BatchImpl> b(new BatchImpl());
+    for (int q = 0; q < count; ++q) {
+        Mesh *m = as_mesh(handles[q]);
+        for (Mesh *o : b->meshes)
+            if (o == m) fail(SEM_EINVAL, "a mesh appears twice in the batch");
+        b->meshes.push_back(m);
+    }
+    b->device = b->meshes[0]->device;
+    for (Mesh *m : b->meshes)
+        if (m->device != b->device) fail(SEM_EINVAL, "all meshes of a batch must share a device");
+    SEM_HIP(hipSetDevice(b->device));
+    SEM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    SEM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+    SEM_HIP(hipHostMalloc((void **)&b->h_states, sizeof(int2) * count));
+    b->d_states = dalloc<int2>(count, b->bytes);
+
+    // per-problem descriptors (each problem runs on its own FP32 workspace)
+    std::vector<AxArgs<float>> ax[2];
+    std::vector<GsClasses> cls;
+    std::vector<GsBatchDesc> gsd;
+    std::vector<UpdBatchDesc> upd;
+    std::vector<FinBatchDesc> fin;
+    std::vector<int2> gs_blk, upd_blk;
+    std::map<int, std::vector<int2>> order_blk;
+    std::map<int, int> order_epb;
+    b->d_cls = dalloc<GsClasses>(count, b->bytes);
+    for (int q = 0; q < count; ++q) {
+        Mesh &m = *b->meshes[q];
+        Workspace &ws = cg_workspace(m, false);
+        for (int otf = 0; otf < 2; ++otf) {
+            AxArgs<float> a{};
+            ax_batch_desc(m, otf != 0, a);
+            a.u = static_cast<float *>(ws.r);
+            a.p = static_cast<float *>(ws.p);
+            a.w = static_cast<float *>(ws.w);
+            a.mcode = m.mcode;
+            a.st = ws.st;
+            a.partial = ws.part_ax;
+            ax[otf].push_back(a);
+        }
+        const AxArgs<float> &a0 = ax[0].back();
+        order_epb[m.N] = a0.epb;
+        for (int64_t vb = 0; vb < a0.vgrid; ++vb) order_blk[m.N].push_back(make_int2(q, (int)vb));
+        if (!b->order_D.count(m.N)) {
+            b->order_D[m.N] = m.h_D;
+            b->order_xi[m.N] = m.h_xi;
+            b->order_w[m.N] = m.h_w;
+        }
+        cls.push_back(m.gs);
+        gsd.push_back({b->d_cls + q, m.gs_idx, static_cast<float *>(ws.w), ws.st});
+        const int64_t nlb = m.n_groups > 0 ? gs_logical_blocks(m) : 0;
+        for (int64_t lb = 0; lb < nlb; ++lb) gs_blk.push_back(make_int2(q, (int)lb));
+        const int nv = vec_blocks(m.n);
+        upd.push_back({m.n, static_cast<float *>(ws.x), static_cast<float *>(ws.r),
+                       static_cast<const float *>(ws.p), static_cast<const float *>(ws.w), m.mcode,
+                       ws.st, ws.part_vec, nv});
+        for (int vb = 0; vb < nv; ++vb) upd_blk.push_back(make_int2(q, vb));
+        fin.push_back({ws.st, ws.part_ax, a0.vgrid, ws.part_vec, nv});
+    }
+    for (int otf = 0; otf < 2; ++otf) {
+        b->d_ax[otf] = dalloc<AxArgs<float>>(count, b->bytes);
+        upload_sync(b->d_ax[otf], ax[otf]);
+    }
+    upload_sync(b->d_cls, cls);
+    b->d_gs = dalloc<GsBatchDesc>(count, b->bytes);
+    upload_sync(b->d_gs, gsd);
+    b->d_upd = dalloc<UpdBatchDesc>(count, b->bytes);
+    upload_sync(b->d_upd, upd);
+    b->d_fin = dalloc<FinBatchDesc>(count, b->bytes);
+    upload_sync(b->d_fin, fin);
+    b->n_gs_blk = (int64_t)gs_blk.size();
+    b->d_gs_blk = dalloc<int2>(gs_blk.size(), b->bytes);
+    upload_sync(b->d_gs_blk, gs_blk);
+    b->n_upd_blk = (int64_t)upd_blk.size();
+    b->d_upd_blk = dalloc<int2>(upd_blk.size(), b->bytes);
+    upload_sync(b->d_upd_blk, upd_blk);
+    for (auto &kv : order_blk) {
+        BatchImpl::OrderGroup g;
+        g.N = kv.first;
+        g.epb = order_epb[kv.first];
+        g.nblk = (int64_t)kv.second.size();
+        g.blk = dalloc<int2>(kv.second.size(), b->bytes);
+        upload_sync(g.blk, kv.second);
+        b->groups.push_back(g);
+    }
+    return b.release();
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Sets the FP32 CG state of problem q: fresh solve (todo) or stopped.
+void set_state(Mesh &m, bool active, double tol, int max_iter, int fixed, hipStream_t s) {
+    Workspace &ws = cg_workspace(m, false);
+    CgState h{};
+    h.thresh = tol * tol;
+    h.max_iter = fixed > 0 ? fixed : max_iter;
+    h.fixed = fixed > 0 ? 1 : 0;
+    h.stop = active ? 0 : 1;
+    SEM_HIP(hipStreamSynchronize(s));
+    *ws.h_st = h;
+    SEM_HIP(hipMemcpyAsync(ws.st, ws.h_st, sizeof(CgState), hipMemcpyHostToDevice, s));
+}
+
+// Batched FP32 iterations until every problem has stopped.
+void iterate_all(BatchImpl &B, bool otf, int chunk, bool use_graph, int max_iter) {
+    int64_t last_sum = -1;
+    const int64_t guard = (int64_t)max_iter / std::max(chunk, 1) + 8;
+    for (int64_t round = 0;; ++round) {
+        B.read_states();
+        bool any = false;
+        int64_t sum = 0;
+        for (int q = 0; q < B.count(); ++q) {
+            any |= B.h_states[q].x == 0;
+            sum += B.h_states[q].y;
+        }
+        if (!any) break;
+        if (sum <= last_sum || round > guard)
+            fail(SEM_EDEVICE, "batched CG state did not advance");
+        last_sum = sum;
+        B.run_chunk(otf, chunk, use_graph);
+    }
+}
+
+}  // namespace
+
+sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_dev,
+                       void *const *x_dev, sem_cg_result *res, hipStream_t user_s) {
+    const double t0 = now_s();
+    const bool otf = o.geom == SEM_G_ON_THE_FLY;
+    const int P = B.count();
+    for (int q = 0; q < P; ++q) {
+        if (!b_dev[q] || !x_dev[q]) fail(SEM_EINVAL, "b and x of every problem must be set");
+        if (!otf && !B.meshes[q]->G32)
+            fail(SEM_EUNSUPPORTED, "precomputed FP32 G was not built for a mesh of the batch");
+    }
+    if (o.kernel_ms || o.hist_rho || o.hist_alpha)
+        fail(SEM_EUNSUPPORTED, "histories and kernel timing are single-mesh options");
+    hipStream_t s = B.stream;
+    SEM_HIP(hipEventRecord(B.ev, user_s));
+    SEM_HIP(hipStreamWaitEvent(s, B.ev, 0));
+    int64_t nmax = 0;
+    for (Mesh *m : B.meshes) nmax = std::max(nmax, m->n);
+    const int chunk = o.poll_every > 0 ? o.poll_every : cg_auto_chunk(nmax, o.fixed_iters);
+    const bool graph = o.use_graph != 0;
+    bool breakdown = false;
+
+    if (o.prec == SEM_FP32) {
+        for (int q = 0; q < P; ++q) {
+            Mesh &m = *B.meshes[q];
+            Workspace &ws = cg_workspace(m, false);
+            set_state(m, true, o.tol, o.max_iter, o.fixed_iters, s);
+            SEM_HIP(hipMemcpyAsync(ws.x, x_dev[q], sizeof(float) * m.n, hipMemcpyDeviceToDevice, s));
+            launch_mask<float>(m, static_cast<float *>(ws.x), s);
+            AxArgs<float> a{};
+            a.u = static_cast<const float *>(ws.x);
+            a.w = static_cast<float *>(ws.w);
+            launch_ax<float>(m, otf, AxMode::Plain, a, s);
+            launch_gs<float>(m, static_cast<float *>(ws.w), s);
+            launch_mask<float>(m, static_cast<float *>(ws.w), s);
+            launch_cg_init<float>(m, static_cast<const float *>(b_dev[q]),
+                                  static_cast<const float *>(ws.w), static_cast<float *>(ws.r),
+                                  static_cast<float *>(ws.p), ws.st, ws.part_vec, s);
+        }
+        iterate_all(B, otf, chunk, graph, o.fixed_iters > 0 ? o.fixed_iters : o.max_iter);
+        for (int q = 0; q < P; ++q) {
+            Mesh &m = *B.meshes[q];
+            Workspace &ws = cg_workspace(m, false);
+            SEM_HIP(hipMemcpyAsync(x_dev[q], ws.x, sizeof(float) * m.n, hipMemcpyDeviceToDevice, s));
+            SEM_HIP(hipMemcpyAsync(ws.h_st, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            SEM_HIP(hipStreamSynchronize(s));
+            const CgState &h = *ws.h_st;
+            res[q] = sem_cg_result{};
+            res[q].iters = h.iter;
+            res[q].status = h.stop;
+            res[q].converged = h.stop == 1;
+            res[q].rel_res_recursive = h.rho0 > 0 ? std::sqrt(h.rho / h.rho0) : 0.0;
+            res[q].rel_res_true = -1.0;
+            breakdown |= h.stop == 3;
+        }
+    } else if (o.prec == SEM_MIXED) {
+        const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+        const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+        const int inner_cap = o.max_iter > 0 ? o.max_iter : 100000;
+        std::vector<int> outer(P, 0), total(P, 0), done(P, 0), last_stop(P, 0);
+        std::vector<double> rel(P, 0.0), inner_rel(P, 0.0);
+        for (int q = 0; q < P; ++q) {
+            Mesh &m = *B.meshes[q];
+            Workspace &w64 = cg_workspace(m, true);
+            double *x64 = static_cast<double *>(w64.x);
+            SEM_HIP(hipMemcpyAsync(x64, x_dev[q], sizeof(double) * m.n, hipMemcpyDeviceToDevice, s));
+            launch_mask<double>(m, x64, s);
+            launch_dot<double>(m, static_cast<const double *>(b_dev[q]),
+                               static_cast<const double *>(b_dev[q]), w64.dval + 1, w64.part_vec, s);
+        }
+        for (;;) {
+            // outer FP64 residuals of the problems still running
+            for (int q = 0; q < P; ++q) {
+                if (done[q]) continue;
+                Mesh &m = *B.meshes[q];
+                Workspace &w64 = cg_workspace(m, true);
+                api_apply_A64(m, static_cast<const double *>(w64.x), static_cast<double *>(w64.w), s);
+                launch_residual64(m, static_cast<const double *>(b_dev[q]),
+                                  static_cast<const double *>(w64.w), static_cast<double *>(w64.r),
+                                  w64.dval + 0, w64.part_vec, s);
+                SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double),
+                                       hipMemcpyDeviceToHost, s));
+            }
+            SEM_HIP(hipStreamSynchronize(s));
+            std::vector<int> todo(P, 0);
+            int ntodo = 0;
+            for (int q = 0; q < P; ++q) {
+                if (done[q]) continue;
+                Workspace &w64 = cg_workspace(*B.meshes[q], true);
+                const double rr = w64.h_val[0], bb = w64.h_val[1];
+                rel[q] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+                if (!std::isfinite(rel[q])) {
+                    done[q] = 3;
+                } else if (rel[q] <= o.tol || rr == 0.0) {
+                    done[q] = 1;
+                } else if (outer[q] >= max_outer) {
+                    done[q] = 2;
+                } else {
+                    todo[q] = 1;
+                    ++ntodo;
+                }
+            }
+            if (ntodo == 0) break;
+            for (int q = 0; q < P; ++q) {
+                Mesh &m = *B.meshes[q];
+                Workspace &w32 = cg_workspace(m, false);
+                if (!todo[q]) {
+                    set_state(m, false, inner_tol, inner_cap, 0, s);
+                    continue;
+                }
+                Workspace &w64 = cg_workspace(m, true);
+                float *b32 = static_cast<float *>(w32.b);
+                launch_scale_to_f32(m.n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
+                set_state(m, true, inner_tol, inner_cap, 0, s);
+                SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * m.n, s));
+                launch_cg_init<float>(m, b32, nullptr, static_cast<float *>(w32.r),
+                                      static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
+            }
+            iterate_all(B, otf, chunk, graph, inner_cap);
+            for (int q = 0; q < P; ++q) {
+                if (!todo[q]) continue;
+                Mesh &m = *B.meshes[q];
+                Workspace &w32 = cg_workspace(m, false);
+                Workspace &w64 = cg_workspace(m, true);
+                SEM_HIP(hipMemcpyAsync(w32.h_st, w32.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+                SEM_HIP(hipStreamSynchronize(s));
+                const CgState &h = *w32.h_st;
+                total[q] += h.iter;
+                last_stop[q] = h.stop;
+                inner_rel[q] = h.rho0 > 0 ? std::sqrt(h.rho / h.rho0) : 0.0;
+                if (h.stop == 3) {
+                    done[q] = 3;
+                    continue;
+                }
+                launch_axpy_from_f32(m.n, static_cast<double *>(w64.x), w64.dval + 0,
+                                     static_cast<const float *>(w32.x), s);
+                ++outer[q];
+            }
+        }
+        for (int q = 0; q < P; ++q) {
+            Mesh &m = *B.meshes[q];
+            Workspace &w64 = cg_workspace(m, true);
+            SEM_HIP(hipMemcpyAsync(x_dev[q], w64.x, sizeof(double) * m.n, hipMemcpyDeviceToDevice, s));
+            res[q] = sem_cg_result{};
+            res[q].iters = total[q];
+            res[q].outer = outer[q];
+            res[q].converged = done[q] == 1;
+            res[q].status = done[q] == 1 ? 1 : (done[q] == 3 ? 3 : (last_stop[q] ? last_stop[q] : 2));
+            res[q].rel_res_recursive = inner_rel[q];
+            res[q].rel_res_true = rel[q];
+            breakdown |= done[q] == 3;
+        }
+        SEM_HIP(hipStreamSynchronize(s));
+    } else {
+        fail(SEM_EUNSUPPORTED, "batched solves run in SEM_FP32 or SEM_MIXED");
+    }
+    const double dt = now_s() - t0;
+    for (int q = 0; q < P; ++q) res[q].seconds = dt;
+    return breakdown ? SEM_EBREAKDOWN : SEM_OK;
+}
+
+BatchImpl *batch_new(int count, const sem_mesh_t *meshes) { return batch_create(count, meshes); }
+void batch_delete(BatchImpl *b) { delete b; }
+
+}  // namespace sem

@@ -17,38 +17,9 @@
 #include <cstring>
 #include <map>
 
-#include "sem_internal.h"
+#include "sem_cg_internal.h"
 
 namespace sem {
-
-struct GraphKey {
-    bool otf;
-    int chunk;
-    bool operator<(const GraphKey &o) const {
-        return otf != o.otf ? otf < o.otf : chunk < o.chunk;
-    }
-};
-
-struct Workspace {
-    bool fp64 = false;
-    int64_t n = 0;
-    int device = 0;
-    void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *b = nullptr;
-    double *part_ax = nullptr, *part_vec = nullptr;
-    int64_t cap_ax = 0;
-    int cap_vec = 0;
-    CgState *st = nullptr;          // device state of this workspace's solves
-    CgState *h_st = nullptr;        // pinned mirror
-    double *hist = nullptr;         // device histories: rho [cap], alpha [cap]
-    int hist_cap = 0;
-    double *dval = nullptr;         // device scalars
-    double *h_val = nullptr;        // pinned mirror (8 doubles)
-    hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    std::vector<hipEvent_t> tev;    // per-kernel timing events (4 per iteration)
-    std::map<GraphKey, hipGraphExec_t> graphs;
-    size_t bytes = 0;
-};
 
 namespace {
 
@@ -484,9 +455,11 @@ sem_status cg_solve(Mesh &m, const sem_cg_opts &o, const void *b, void *x, sem_c
     return st;
 }
 
-// FP64 operator and helpers for the API layer
+// FP64 operator and helpers for the API layer and the batched driver
 void api_apply_A64(const Mesh &m, const double *u, double *w, hipStream_t s) {
     apply_A64(m, u, w, s);
 }
+Workspace &cg_workspace(Mesh &m, bool fp64) { return get_ws(m, fp64); }
+int cg_auto_chunk(int64_t n, int fixed) { return auto_chunk(n, fixed); }
 
 }  // namespace sem

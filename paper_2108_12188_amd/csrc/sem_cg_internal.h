@@ -1,0 +1,47 @@
+// sem_cg_internal.h -- CG work vectors of a mesh, shared by the
+// single-mesh and the batched drivers.
+#pragma once
+
+#include <map>
+#include <vector>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+struct GraphKey {
+    bool otf;
+    int chunk;
+    bool operator<(const GraphKey &o) const {
+        return otf != o.otf ? otf < o.otf : chunk < o.chunk;
+    }
+};
+
+struct Workspace {
+    bool fp64 = false;
+    int64_t n = 0;
+    int device = 0;
+    void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *b = nullptr;
+    double *part_ax = nullptr, *part_vec = nullptr;
+    int64_t cap_ax = 0;
+    int cap_vec = 0;
+    CgState *st = nullptr;          // device state of this workspace's solves
+    CgState *h_st = nullptr;        // pinned mirror
+    double *hist = nullptr;         // device histories: rho [cap], alpha [cap]
+    int hist_cap = 0;
+    double *dval = nullptr;         // device scalars
+    double *h_val = nullptr;        // pinned mirror (8 doubles)
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<hipEvent_t> tev;    // per-kernel timing events (4 per iteration)
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    size_t bytes = 0;
+};
+
+// the mesh's workspace of one precision (created on first use)
+Workspace &cg_workspace(Mesh &m, bool fp64);
+int cg_auto_chunk(int64_t n, int fixed);
+// w = mask(QQ^T A_L u) in FP64 (precomputed G64 if present, else on the fly)
+void api_apply_A64(const Mesh &m, const double *u, double *w, hipStream_t s);
+
+}  // namespace sem

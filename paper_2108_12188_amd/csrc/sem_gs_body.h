@@ -1,0 +1,97 @@
+// sem_gs_body.h -- device code of the gather-scatter shared by the
+// single-mesh and the batched kernels.
+#pragma once
+
+#include "sem_internal.h"
+
+namespace sem {
+namespace gsb {
+
+constexpr int kGsThreads = 256;
+constexpr int kXcds = 8;                          // MI355X: 8 XCDs, blocks dealt round-robin
+
+// groups per thread for a group size: about 8 copies per thread in flight
+__host__ __device__ constexpr int gs_per_thread(int M) { return M >= 8 ? 1 : (M >= 4 ? 2 : 4); }
+__host__ __device__ constexpr int64_t gs_per_block(int M) {
+    return (int64_t)kGsThreads * gs_per_thread(M);
+}
+
+template <int M>
+struct alignas(M * 4 <= 16 ? M * 4 : 16) IdxVec {
+    int32_t v[M];
+};
+
+// Groups of a compile-time size M: every lane first issues the index loads
+// of all its groups, then all value loads, so each lane keeps
+// kGsPerThread * M independent loads in flight (groups are disjoint, so the
+// stores of one group never alias the loads of another).
+template <typename T, int M>
+__device__ __forceinline__ void gs_groups_fixed(const int32_t *__restrict__ ib, int64_t g0,
+                                                int64_t ng, T *__restrict__ w) {
+    constexpr int kGsPerThread = gs_per_thread(M);
+    int32_t q[kGsPerThread][M];
+    bool ok[kGsPerThread];
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it) {
+        const int64_t g = g0 + (int64_t)it * kGsThreads;
+        ok[it] = g < ng;
+        if (ok[it]) {
+            const IdxVec<M> *src = reinterpret_cast<const IdxVec<M> *>(ib + g * M);
+            const IdxVec<M> iv = *src;
+#pragma unroll
+            for (int t = 0; t < M; ++t) q[it][t] = iv.v[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < M; ++t) q[it][t] = 0;
+        }
+    }
+    T v[kGsPerThread][M];
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it)
+#pragma unroll
+        for (int t = 0; t < M; ++t) v[it][t] = ok[it] ? w[q[it][t]] : T(0);
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it) {
+        if (!ok[it]) continue;
+        T s = v[it][0];
+#pragma unroll
+        for (int t = 1; t < M; ++t) s += v[it][t];
+#pragma unroll
+        for (int t = 0; t < M; ++t) w[q[it][t]] = s;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gs_groups_any(const int32_t *__restrict__ ib, int M, int64_t g0,
+                                              int64_t ng, T *__restrict__ w) {
+    for (int it = 0; it < gs_per_thread(M); ++it) {
+        const int64_t g = g0 + (int64_t)it * kGsThreads;
+        if (g >= ng) break;
+        const int32_t *gi = ib + g * M;
+        T s = w[gi[0]];
+        for (int t = 1; t < M; ++t) s += w[gi[t]];
+        for (int t = 0; t < M; ++t) w[gi[t]] = s;
+    }
+}
+
+// One logical block lb of a mesh's gather-scatter (uniform across the block).
+template <typename T>
+__device__ __forceinline__ void gs_logical_block(const GsClasses &cls, int64_t lb,
+                                                 const int32_t *__restrict__ idx,
+                                                 T *__restrict__ w) {
+    int c = 0;
+    while (c + 1 < cls.ncls && lb >= cls.blk0[c + 1]) ++c;
+    const int M = cls.M[c];
+    const int64_t g0 = (lb - cls.blk0[c]) * gs_per_block(M) + threadIdx.x;
+    const int32_t *ib = idx + cls.io[c];
+    const int64_t ng = cls.ng[c];
+    switch (M) {
+        case 2: gs_groups_fixed<T, 2>(ib, g0, ng, w); break;
+        case 4: gs_groups_fixed<T, 4>(ib, g0, ng, w); break;
+        case 8: gs_groups_fixed<T, 8>(ib, g0, ng, w); break;
+        default: gs_groups_any<T>(ib, M, g0, ng, w); break;
+    }
+}
+
+}  // namespace gsb
+}  // namespace sem

@@ -135,6 +135,7 @@ struct AxArgs {
     const uint8_t *mcode;       // CgFused: mask / interior weights
     CgState *st;                // CgFused: beta, stop flag
     double *partial;            // CgFused: one FP64 partial of sum p w per block
+    int64_t vgrid;              // batched launches: this problem's own grid size
 };
 
 // Launch configuration chosen for an order (threads, elements per block,
@@ -151,6 +152,13 @@ AxShape ax_shape(int N, bool fp64, int epb_override);
 template <typename T>
 void launch_ax(const Mesh &m, bool otf, AxMode mode, AxArgs<T> a, hipStream_t s);
 int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override);
+// Fills `a` (basis, geometry, epb, vgrid) for a batched FP32 launch of mesh m.
+void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a);
+// One FP32 CG-fused operator launch over many problems of order N:
+// blk[b] = (descriptor index, virtual block).
+void launch_ax_batch(int N, bool otf, const AxArgs<float> *descs, const int2 *blk, int64_t nblk,
+                     int epb, const double *D, const double *xi, const double *w,
+                     hipStream_t s);
 
 // gather-scatter / mask / vector kernels (sem_gs.hip, sem_vec.hip)
 template <typename T>
@@ -163,6 +171,7 @@ template <typename T>
 void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, int n_ax_partial,
                   hipStream_t s);
 int gs_cg_blocks(const Mesh &m);
+int64_t gs_logical_blocks(const Mesh &m);
 
 // Algorithm 1 vector kernels (sem_vec.hip).  Reductions write one FP64
 // partial per block (`partial`, at least vec_blocks(n) entries) and a

@@ -1,0 +1,97 @@
+"""Batched solves: every problem of a batch (mixed element counts and
+orders, one launch per kernel type per iteration) ends bitwise equal to its
+own single-mesh solve, and meets its tolerance against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import rel_norm, say, to_dev, to_host
+from seminputs import box_mesh, random_global_rhs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [((3, 2, 2), 5), ((4, 3, 2), 7), ((2, 2, 2), 9), ((5, 4, 3), 3), ((2, 3, 2), 7)]
+
+
+def _meshes(sem, g_fp32=True):
+    boxes = [box_mesh(*sh, N, perturb=0.1, seed=40 + q, reorient=True, permute=True)
+             for q, (sh, N) in enumerate(SHAPES)]
+    return boxes, [sem.Mesh.from_box(b, g_fp32=g_fp32) for b in boxes]
+
+
+def _manufactured(gm):
+    import torch
+    xyz = gm.coords()
+    f = 3 * math.pi ** 2 * torch.sin(math.pi * xyz[0]) * torch.sin(math.pi * xyz[1]) \
+        * torch.sin(math.pi * xyz[2])
+    return f.contiguous()
+
+
+@pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
+def test_batch_fp32_fixed_equals_solo(geom):
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"batch fp32 fixed geom={geom}")
+    boxes, gms = _meshes(sem)
+    bs = [to_dev(random_global_rhs(b, seed=7 + q), torch.float32) for q, b in enumerate(boxes)]
+    batch = sem.Batch(gms)
+    xs, res = batch.solve(bs, prec=sem.FP32, geom=geom, fixed_iters=23)
+    for q, gm in enumerate(gms):
+        xq, rq = gm.cg_solve(bs[q], prec=sem.FP32, geom=geom, fixed_iters=23)
+        assert res[q]["iters"] == 23 == rq["iters"]
+        assert torch.equal(xs[q], xq), q
+    batch.close()
+
+
+def test_batch_fp32_tolerance_equals_solo_and_oracle():
+    import torch
+    import paper_2108_12188_amd as sem
+    boxes, gms = _meshes(sem)
+    bs = [to_dev(random_global_rhs(b, seed=3 + q), torch.float32) for q, b in enumerate(boxes)]
+    batch = sem.Batch(gms)
+    xs, res = batch.solve(bs, prec=sem.FP32, tol=1e-5, max_iter=5000)
+    for q, gm in enumerate(gms):
+        xq, rq = gm.cg_solve(bs[q], prec=sem.FP32, tol=1e-5, max_iter=5000)
+        assert res[q]["iters"] == rq["iters"] and res[q]["converged"] == 1
+        assert torch.equal(xs[q], xq)
+    # one problem against the oracle's converged solution
+    pr = oracle.Problem(boxes[1])
+    xo, _, _ = pr.cg(to_host(bs[1]), tol=1e-12, max_iter=20000)
+    assert rel_norm(to_host(xs[1]), xo) < 1e-4
+    batch.close()
+
+
+@pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
+def test_batch_mixed_equals_solo(geom):
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"batch mixed geom={geom}")
+    boxes, gms = _meshes(sem)
+    bs = [gm.rhs(_manufactured(gm), prec=sem.FP64) for gm in gms]
+    batch = sem.Batch(gms)
+    xs, res = batch.solve(bs, prec=sem.MIXED, geom=geom, tol=1e-8, inner_tol=1e-5)
+    for q, gm in enumerate(gms):
+        xq, rq = gm.cg_solve(bs[q], prec=sem.MIXED, geom=geom, tol=1e-8, inner_tol=1e-5)
+        assert res[q]["converged"] == 1 and rq["converged"] == 1
+        assert (res[q]["iters"], res[q]["outer"]) == (rq["iters"], rq["outer"])
+        assert torch.equal(xs[q], xq), q
+        assert res[q]["rel_res_true"] <= 1e-8
+    pr = oracle.Problem(boxes[2])
+    assert pr.true_rel_residual(to_host(bs[2]), to_host(xs[2])) < 1.1e-8
+    batch.close()
+
+
+def test_batch_errors():
+    import torch
+    import paper_2108_12188_amd as sem
+    boxes, gms = _meshes(sem)
+    with pytest.raises(sem.SemError):
+        sem.Batch([gms[0], gms[0]])
+    batch = sem.Batch(gms[:2])
+    bs = [torch.zeros(g.n, dtype=torch.float64, device="cuda") for g in gms[:2]]
+    with pytest.raises(sem.SemError) as ei:
+        batch.solve(bs, prec=sem.FP64, tol=1e-8)
+    assert ei.value.code == -6
+    batch.close()
