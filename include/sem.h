@@ -96,7 +96,7 @@ typedef struct {
     int64_t n_shared;      /* local points with multiplicity > 1 */
     int64_t n_groups;      /* global points with multiplicity > 1 */
     int64_t n_dirichlet;   /* local points on the Dirichlet boundary */
-    size_t device_bytes;   /* device memory held by the handle */
+    size_t device_bytes;   /* device memory held by the handle (mesh arrays and work vectors) */
 } sem_mesh_info_t;
 
 sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);
@@ -206,6 +206,33 @@ void sem_batch_destroy(sem_batch_t batch);
 sem_status sem_batch_solve(sem_batch_t batch, const sem_cg_opts *opts,
                            const void *const *b_dev, void *const *x_dev,
                            sem_cg_result *results, void *hip_stream);
+
+/*
+ * Continuous-batching server (mixed precision only: opts->prec = SEM_MIXED).
+ * Requests join and leave at round boundaries; every request runs the
+ * refinement of sem_cg_solve(SEM_MIXED) and the inner FP32 iterations of
+ * all requests advance together in batched launches (round_iters per
+ * round).  A request's result is bitwise that of its own sem_cg_solve.
+ * sem_server_add: b_dev / x_dev are DEVICE double [n_local] of the mesh and
+ * must stay valid until the request is reported done; x holds the initial
+ * guess.  One request per mesh at a time.
+ * sem_server_step: runs one round on the server's own stream, blocks until
+ * it is done, writes up to cap finished requests (their tags and results;
+ * their x is final), and the number of requests still held.
+ */
+typedef struct sem_server_s *sem_server_t;
+sem_status sem_server_create(const sem_cg_opts *opts, int round_iters, sem_server_t *out);
+void sem_server_destroy(sem_server_t server);
+sem_status sem_server_add(sem_server_t server, sem_mesh_t mesh, const void *b_dev, void *x_dev,
+                          int64_t tag);
+sem_status sem_server_step(sem_server_t server, int64_t *done_tags, sem_cg_result *done_results,
+                           int cap, int *n_done, int *n_active);
+
+/* Upper bound of the device bytes of a mesh of n_elem elements of order N
+ * created with `flags`, plus the work vectors of a solve in `prec` (admission
+ * by memory footprint). */
+sem_status sem_mesh_footprint(int64_t n_elem, int order_N, uint32_t flags, sem_precision prec,
+                              size_t *bytes);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *sem_last_error(void);

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-__all__ = ["SemError", "Mesh", "Batch", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
+__all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
            "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
@@ -56,7 +56,9 @@ class MeshInfo(C.Structure):
 _lib = None
 EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "sem_gs",
            "sem_dot", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
-           "sem_batch_destroy", "sem_batch_solve", "sem_last_error", "sem_version"]
+           "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
+           "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_last_error",
+           "sem_version"]
 
 
 def library_path() -> str:
@@ -87,12 +89,19 @@ def lib():
     L.sem_batch_destroy.argtypes = [vp]
     L.sem_batch_destroy.restype = None
     L.sem_batch_solve.argtypes = [vp, C.POINTER(CgOpts), vp, vp, vp, vp]
+    L.sem_server_create.argtypes = [C.POINTER(CgOpts), i32, C.POINTER(vp)]
+    L.sem_server_destroy.argtypes = [vp]
+    L.sem_server_destroy.restype = None
+    L.sem_server_add.argtypes = [vp, vp, vp, vp, i64]
+    L.sem_server_step.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.sem_mesh_footprint.argtypes = [i64, i32, u32, i32, C.POINTER(C.c_size_t)]
     L.sem_last_error.restype = C.c_char_p
     L.sem_last_error.argtypes = []
     L.sem_version.restype = C.c_char_p
     L.sem_version.argtypes = []
     for name in ("sem_mesh_create", "sem_mesh_info", "sem_ax", "sem_gs", "sem_dot",
-                 "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve"):
+                 "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve",
+                 "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -317,3 +326,59 @@ class Batch:
             return xs, out
         _check(code)
         return xs, out
+
+
+def mesh_footprint(n_elem: int, N: int, g_fp32: bool = True, g_fp64: bool = False,
+                   prec: int = MIXED) -> int:
+    """Upper bound of the device bytes of a mesh plus the work vectors of a solve."""
+    out = C.c_size_t()
+    flags = (G_FP32 if g_fp32 else 0) | (G_FP64 if g_fp64 else 0)
+    _check(lib().sem_mesh_footprint(n_elem, N, flags, prec, C.byref(out)))
+    return int(out.value)
+
+
+class Server:
+    """Continuous-batching mixed-precision solver (see sem_server_* in sem.h)."""
+
+    def __init__(self, tol: float = 1e-8, geom: int = PRECOMPUTED, inner_tol: float = 0.0,
+                 max_outer: int = 0, max_iter: int = 0, round_iters: int = 16):
+        _torch()
+        opts = CgOpts(prec=MIXED, geom=geom, tol=tol, max_iter=max_iter, fixed_iters=0,
+                      inner_tol=inner_tol, max_outer=max_outer, poll_every=0, use_graph=0,
+                      true_residual=0, hist_len=0)
+        h = C.c_void_p()
+        _check(lib().sem_server_create(C.byref(opts), round_iters, C.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def add(self, mesh: "Mesh", b, x, tag: int):
+        _dev_vec(b, mesh.n, "b")
+        _dev_vec(x, mesh.n, "x")
+        _check(lib().sem_server_add(self._h, mesh.handle, C.c_void_p(b.data_ptr()),
+                                    C.c_void_p(x.data_ptr()), tag))
+        self._held[tag] = (mesh, b, x)
+
+    def step(self, cap: int = 256):
+        """One round; returns (list of (tag, result dict), requests still held)."""
+        tags = (C.c_int64 * cap)()
+        res = (CgResult * cap)()
+        nd = C.c_int()
+        na = C.c_int()
+        _check(lib().sem_server_step(self._h, tags, res, cap, C.byref(nd), C.byref(na)))
+        done = []
+        for q in range(nd.value):
+            t = int(tags[q])
+            self._held.pop(t, None)
+            done.append((t, res[q].as_dict()))
+        return done, na.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sem_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

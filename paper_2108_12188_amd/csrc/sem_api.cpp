@@ -45,6 +45,13 @@ BatchImpl *batch_new(int count, const sem_mesh_t *meshes);
 void batch_delete(BatchImpl *b);
 sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_dev,
                        void *const *x_dev, sem_cg_result *res, hipStream_t user_s);
+struct ServerImpl;
+ServerImpl *server_new(const sem_cg_opts &o, int round_iters);
+void server_delete(ServerImpl *sv);
+void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag);
+int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, int *n_done);
+size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec);
+size_t workspace_bytes(const Mesh &m);
 
 template <typename F>
 static sem_status guarded(F &&f) {
@@ -117,7 +124,7 @@ sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info) {
         info->n_shared = m->n_shared;
         info->n_groups = m->n_groups;
         info->n_dirichlet = m->n_dir;
-        info->device_bytes = m->device_bytes;
+        info->device_bytes = m->device_bytes + workspace_bytes(*m);
         return SEM_OK;
     });
 }
@@ -293,6 +300,58 @@ sem_status sem_batch_solve(sem_batch_t batch, const sem_cg_opts *opts, const voi
             batch_solve(B, *opts, b_dev, x_dev, results, static_cast<hipStream_t>(hip_stream));
         if (st == SEM_EBREAKDOWN) set_error("CG breakdown in at least one problem of the batch");
         return st;
+    });
+}
+
+sem_status sem_server_create(const sem_cg_opts *opts, int round_iters, sem_server_t *out) {
+    return guarded([&]() -> sem_status {
+        need(opts, "opts");
+        need(out, "out");
+        *out = reinterpret_cast<sem_server_t>(server_new(*opts, round_iters));
+        return SEM_OK;
+    });
+}
+
+void sem_server_destroy(sem_server_t server) {
+    if (server) server_delete(reinterpret_cast<ServerImpl *>(server));
+}
+
+sem_status sem_server_add(sem_server_t server, sem_mesh_t mesh, const void *b_dev, void *x_dev,
+                          int64_t tag) {
+    return guarded([&]() -> sem_status {
+        need(server, "server");
+        Mesh *m = as_mesh(mesh);
+        DeviceGuard dg(m->device);
+        server_add(*reinterpret_cast<ServerImpl *>(server), m, static_cast<const double *>(b_dev),
+                   static_cast<double *>(x_dev), tag);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_server_step(sem_server_t server, int64_t *done_tags, sem_cg_result *done_results,
+                           int cap, int *n_done, int *n_active) {
+    return guarded([&]() -> sem_status {
+        need(server, "server");
+        need(n_done, "n_done");
+        if (cap > 0) {
+            need(done_tags, "done_tags");
+            need(done_results, "done_results");
+        }
+        const int left = server_step(*reinterpret_cast<ServerImpl *>(server), done_tags,
+                                     done_results, cap, n_done);
+        if (n_active) *n_active = left;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_mesh_footprint(int64_t n_elem, int order_N, uint32_t flags, sem_precision prec,
+                              size_t *bytes) {
+    return guarded([&]() -> sem_status {
+        need(bytes, "bytes");
+        if (n_elem <= 0) fail(SEM_EINVAL, "n_elem must be positive");
+        if (order_N < 1 || order_N > kMaxOrder) fail(SEM_EUNSUPPORTED, "order not built");
+        *bytes = mesh_footprint(n_elem, order_N, flags, prec);
+        return SEM_OK;
     });
 }
 

@@ -124,6 +124,8 @@ struct BatchImpl {
     FinBatchDesc *d_fin = nullptr;
     int2 *d_states = nullptr;
     int2 *h_states = nullptr;                        // pinned
+    size_t cap_ax[2] = {0, 0}, cap_cls = 0, cap_gs = 0, cap_gs_blk = 0, cap_upd = 0,
+           cap_upd_blk = 0, cap_fin = 0, cap_states = 0, cap_h_states = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -145,8 +147,11 @@ struct BatchImpl {
 
     int count() const { return (int)meshes.size(); }
 
+    void rebuild(const std::vector<Mesh *> &ms);
+
     // one batched CG iteration of every problem
     void enqueue_iteration(bool otf, hipStream_t s) {
+        if (count() == 0) return;
         for (const auto &g : groups) {
             launch_ax_batch(g.N, otf, d_ax[otf ? 1 : 0], g.blk, g.nblk, g.epb,
                             order_D[g.N].data(), order_xi[g.N].data(), order_w[g.N].data(), s);
@@ -206,26 +211,48 @@ struct BatchImpl {
 
 namespace {
 
+// Device array with a capacity; grows (and drops its contents) on demand.
+template <typename T>
+void ensure_cap(T *&ptr, size_t &cap, size_t need, size_t &bytes) {
+    if (need <= cap && ptr) return;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    ptr = dalloc<T>(need, bytes);
+    cap = std::max<size_t>(need, 1);
+}
+
 BatchImpl *batch_create(int count, const sem_mesh_t *handles) {
     if (count <= 0) fail(SEM_EINVAL, "count must be positive");
     if (!handles) fail(SEM_EINVAL, "meshes must not be NULL");
-    std::unique_ptr<BatchImpl> b(new BatchImpl());
+    std::vector<Mesh *> ms;
     for (int q = 0; q < count; ++q) {
         Mesh *m = as_mesh(handles[q]);
-        for (Mesh *o : b->meshes)
+        for (Mesh *o : ms)
             if (o == m) fail(SEM_EINVAL, "a mesh appears twice in the batch");
-        b->meshes.push_back(m);
+        ms.push_back(m);
     }
-    b->device = b->meshes[0]->device;
-    for (Mesh *m : b->meshes)
-        if (m->device != b->device) fail(SEM_EINVAL, "all meshes of a batch must share a device");
+    for (Mesh *m : ms)
+        if (m->device != ms[0]->device) fail(SEM_EINVAL, "all meshes of a batch must share a device");
+    std::unique_ptr<BatchImpl> b(new BatchImpl());
+    b->device = ms[0]->device;
     SEM_HIP(hipSetDevice(b->device));
     SEM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     SEM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
-    SEM_HIP(hipHostMalloc((void **)&b->h_states, sizeof(int2) * count));
-    b->d_states = dalloc<int2>(count, b->bytes);
+    b->rebuild(ms);
+    return b.release();
+}
 
-    // per-problem descriptors (each problem runs on its own FP32 workspace)
+}  // namespace
+
+// Rebuilds every descriptor and block table for a new member list (the
+// captured graphs refer to the old tables and are dropped).
+void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
+    SEM_HIP(hipStreamSynchronize(stream));
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    meshes = ms;
+    const int count = (int)ms.size();
     std::vector<AxArgs<float>> ax[2];
     std::vector<GsClasses> cls;
     std::vector<GsBatchDesc> gsd;
@@ -234,9 +261,9 @@ BatchImpl *batch_create(int count, const sem_mesh_t *handles) {
     std::vector<int2> gs_blk, upd_blk;
     std::map<int, std::vector<int2>> order_blk;
     std::map<int, int> order_epb;
-    b->d_cls = dalloc<GsClasses>(count, b->bytes);
+    ensure_cap(d_cls, cap_cls, count, bytes);
     for (int q = 0; q < count; ++q) {
-        Mesh &m = *b->meshes[q];
+        Mesh &m = *ms[q];
         Workspace &ws = cg_workspace(m, false);
         for (int otf = 0; otf < 2; ++otf) {
             AxArgs<float> a{};
@@ -252,13 +279,13 @@ BatchImpl *batch_create(int count, const sem_mesh_t *handles) {
         const AxArgs<float> &a0 = ax[0].back();
         order_epb[m.N] = a0.epb;
         for (int64_t vb = 0; vb < a0.vgrid; ++vb) order_blk[m.N].push_back(make_int2(q, (int)vb));
-        if (!b->order_D.count(m.N)) {
-            b->order_D[m.N] = m.h_D;
-            b->order_xi[m.N] = m.h_xi;
-            b->order_w[m.N] = m.h_w;
+        if (!order_D.count(m.N)) {
+            order_D[m.N] = m.h_D;
+            order_xi[m.N] = m.h_xi;
+            order_w[m.N] = m.h_w;
         }
         cls.push_back(m.gs);
-        gsd.push_back({b->d_cls + q, m.gs_idx, static_cast<float *>(ws.w), ws.st});
+        gsd.push_back({d_cls + q, m.gs_idx, static_cast<float *>(ws.w), ws.st});
         const int64_t nlb = m.n_groups > 0 ? gs_logical_blocks(m) : 0;
         for (int64_t lb = 0; lb < nlb; ++lb) gs_blk.push_back(make_int2(q, (int)lb));
         const int nv = vec_blocks(m.n);
@@ -269,33 +296,44 @@ BatchImpl *batch_create(int count, const sem_mesh_t *handles) {
         fin.push_back({ws.st, ws.part_ax, a0.vgrid, ws.part_vec, nv});
     }
     for (int otf = 0; otf < 2; ++otf) {
-        b->d_ax[otf] = dalloc<AxArgs<float>>(count, b->bytes);
-        upload_sync(b->d_ax[otf], ax[otf]);
+        ensure_cap(d_ax[otf], cap_ax[otf], count, bytes);
+        upload_sync(d_ax[otf], ax[otf]);
     }
-    upload_sync(b->d_cls, cls);
-    b->d_gs = dalloc<GsBatchDesc>(count, b->bytes);
-    upload_sync(b->d_gs, gsd);
-    b->d_upd = dalloc<UpdBatchDesc>(count, b->bytes);
-    upload_sync(b->d_upd, upd);
-    b->d_fin = dalloc<FinBatchDesc>(count, b->bytes);
-    upload_sync(b->d_fin, fin);
-    b->n_gs_blk = (int64_t)gs_blk.size();
-    b->d_gs_blk = dalloc<int2>(gs_blk.size(), b->bytes);
-    upload_sync(b->d_gs_blk, gs_blk);
-    b->n_upd_blk = (int64_t)upd_blk.size();
-    b->d_upd_blk = dalloc<int2>(upd_blk.size(), b->bytes);
-    upload_sync(b->d_upd_blk, upd_blk);
+    upload_sync(d_cls, cls);
+    ensure_cap(d_gs, cap_gs, count, bytes);
+    upload_sync(d_gs, gsd);
+    ensure_cap(d_upd, cap_upd, count, bytes);
+    upload_sync(d_upd, upd);
+    ensure_cap(d_fin, cap_fin, count, bytes);
+    upload_sync(d_fin, fin);
+    ensure_cap(d_states, cap_states, count, bytes);
+    if (cap_h_states < (size_t)count) {
+        if (h_states) (void)hipHostFree(h_states);
+        h_states = nullptr;
+        SEM_HIP(hipHostMalloc((void **)&h_states, sizeof(int2) * std::max(count, 1)));
+        cap_h_states = std::max(count, 1);
+    }
+    n_gs_blk = (int64_t)gs_blk.size();
+    ensure_cap(d_gs_blk, cap_gs_blk, gs_blk.size(), bytes);
+    upload_sync(d_gs_blk, gs_blk);
+    n_upd_blk = (int64_t)upd_blk.size();
+    ensure_cap(d_upd_blk, cap_upd_blk, upd_blk.size(), bytes);
+    upload_sync(d_upd_blk, upd_blk);
+    for (auto &g : groups)
+        if (g.blk) (void)hipFree(g.blk);
+    groups.clear();
     for (auto &kv : order_blk) {
-        BatchImpl::OrderGroup g;
+        OrderGroup g;
         g.N = kv.first;
         g.epb = order_epb[kv.first];
         g.nblk = (int64_t)kv.second.size();
-        g.blk = dalloc<int2>(kv.second.size(), b->bytes);
+        g.blk = dalloc<int2>(kv.second.size(), bytes);
         upload_sync(g.blk, kv.second);
-        b->groups.push_back(g);
+        groups.push_back(g);
     }
-    return b.release();
 }
+
+namespace {
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -499,5 +537,176 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
 
 BatchImpl *batch_new(int count, const sem_mesh_t *meshes) { return batch_create(count, meshes); }
 void batch_delete(BatchImpl *b) { delete b; }
+
+}  // namespace sem
+
+// ---------------------------------------------------------------------------
+// Continuous-batching server: requests join and leave at round boundaries.
+// Every request runs the mixed-precision refinement of sem_cg_solve (FP64
+// outer residual per request, FP32 inner CG); the inner iterations of all
+// requests that are in their inner phase advance together in batched
+// launches.  A request's arithmetic and reduction order do not depend on
+// which other requests share its launches, so its result is bitwise that of
+// its own sem_cg_solve.
+// ---------------------------------------------------------------------------
+namespace sem {
+
+struct ServerReq {
+    Mesh *m = nullptr;
+    const double *b = nullptr;
+    double *x = nullptr;
+    int64_t tag = 0;
+    int phase = 0;          // 0: outer residual pending; 1: inner CG running
+    int outer = 0, total = 0, last_stop = 0;
+    bool broken = false;    // the inner CG broke down
+    double rel = 0.0, inner_rel = 0.0;
+};
+
+struct ServerImpl {
+    sem_cg_opts o{};
+    int round_iters = 16;
+    BatchImpl batch;
+    std::vector<ServerReq> reqs;
+    double inner_tol = 1e-5;
+    int max_outer = 20, inner_cap = 100000;
+};
+
+ServerImpl *server_new(const sem_cg_opts &o, int round_iters) {
+    if (o.prec != SEM_MIXED) fail(SEM_EUNSUPPORTED, "the server runs SEM_MIXED solves");
+    if (!(o.tol > 0)) fail(SEM_EINVAL, "tol must be positive");
+    if (o.geom != SEM_G_PRECOMPUTED && o.geom != SEM_G_ON_THE_FLY)
+        fail(SEM_EINVAL, "unknown geometry form");
+    std::unique_ptr<ServerImpl> sv(new ServerImpl());
+    sv->o = o;
+    sv->round_iters = round_iters > 0 ? round_iters : 16;
+    sv->inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    sv->max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    sv->inner_cap = o.max_iter > 0 ? o.max_iter : 100000;
+    SEM_HIP(hipGetDevice(&sv->batch.device));
+    SEM_HIP(hipStreamCreateWithFlags(&sv->batch.stream, hipStreamNonBlocking));
+    SEM_HIP(hipEventCreateWithFlags(&sv->batch.ev, hipEventDisableTiming));
+    sv->batch.rebuild({});
+    return sv.release();
+}
+
+void server_delete(ServerImpl *sv) { delete sv; }
+
+void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag) {
+    if (!b || !x) fail(SEM_EINVAL, "b and x must not be NULL");
+    for (const ServerReq &r : sv.reqs)
+        if (r.m == m) fail(SEM_EINVAL, "the mesh already has a request in the server");
+    if (m->device != sv.batch.device) fail(SEM_EINVAL, "the mesh lives on another device");
+    if (sv.o.geom == SEM_G_PRECOMPUTED && !m->G32)
+        fail(SEM_EUNSUPPORTED, "precomputed FP32 G was not built for the mesh");
+    hipStream_t s = sv.batch.stream;
+    Workspace &w64 = cg_workspace(*m, true);
+    (void)cg_workspace(*m, false);
+    double *x64 = static_cast<double *>(w64.x);
+    SEM_HIP(hipMemcpyAsync(x64, x, sizeof(double) * m->n, hipMemcpyDeviceToDevice, s));
+    launch_mask<double>(*m, x64, s);
+    launch_dot<double>(*m, b, b, w64.dval + 1, w64.part_vec, s);
+    ServerReq r;
+    r.m = m;
+    r.b = b;
+    r.x = x;
+    r.tag = tag;
+    sv.reqs.push_back(r);
+}
+
+// One round.  Returns the number of requests still in the server; finished
+// requests are written to (tags, results) up to cap (the rest stay queued
+// as finished and are returned by the next call).
+int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, int *n_done) {
+    hipStream_t s = sv.batch.stream;
+    const bool otf = sv.o.geom == SEM_G_ON_THE_FLY;
+    *n_done = 0;
+    // 1. outer residuals of the requests whose inner solve finished (or new)
+    bool any_outer = false;
+    for (ServerReq &r : sv.reqs) {
+        if (r.phase != 0) continue;
+        any_outer = true;
+        Workspace &w64 = cg_workspace(*r.m, true);
+        api_apply_A64(*r.m, static_cast<const double *>(w64.x), static_cast<double *>(w64.w), s);
+        launch_residual64(*r.m, r.b, static_cast<const double *>(w64.w),
+                          static_cast<double *>(w64.r), w64.dval + 0, w64.part_vec, s);
+        SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (any_outer) SEM_HIP(hipStreamSynchronize(s));
+    std::vector<ServerReq> keep;
+    for (ServerReq &r : sv.reqs) {
+        if (r.phase == 0) {
+            Workspace &w64 = cg_workspace(*r.m, true);
+            const double rr = w64.h_val[0], bb = w64.h_val[1];
+            r.rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+            int done = 0;
+            if (r.broken || !std::isfinite(r.rel)) done = 3;
+            else if (r.rel <= sv.o.tol || rr == 0.0) done = 1;
+            else if (r.outer >= sv.max_outer) done = 2;
+            if (done && *n_done < cap) {
+                SEM_HIP(hipMemcpyAsync(r.x, w64.x, sizeof(double) * r.m->n,
+                                       hipMemcpyDeviceToDevice, s));
+                sem_cg_result &o = results[*n_done];
+                o = sem_cg_result{};
+                o.iters = r.total;
+                o.outer = r.outer;
+                o.converged = done == 1;
+                o.status = done == 1 ? 1 : (done == 3 ? 3 : (r.last_stop ? r.last_stop : 2));
+                o.rel_res_recursive = r.inner_rel;
+                o.rel_res_true = r.rel;
+                tags[*n_done] = r.tag;
+                ++*n_done;
+                continue;
+            }
+            if (done) {          // no room to report it: keep it for the next call
+                keep.push_back(r);
+                continue;
+            }
+            // start the inner FP32 solve of A d = r / ||r||_c
+            Workspace &w32 = cg_workspace(*r.m, false);
+            float *b32 = static_cast<float *>(w32.b);
+            launch_scale_to_f32(r.m->n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
+            set_state(*r.m, true, sv.inner_tol, sv.inner_cap, 0, s);
+            SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * r.m->n, s));
+            launch_cg_init<float>(*r.m, b32, nullptr, static_cast<float *>(w32.r),
+                                  static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
+            r.phase = 1;
+        }
+        keep.push_back(r);
+    }
+    sv.reqs.swap(keep);
+    // 2. a round of batched inner iterations
+    std::vector<Mesh *> inner;
+    for (ServerReq &r : sv.reqs)
+        if (r.phase == 1) inner.push_back(r.m);
+    if (!inner.empty()) {
+        if (inner != sv.batch.meshes) sv.batch.rebuild(inner);
+        for (int c = 0; c < sv.round_iters; ++c) sv.batch.enqueue_iteration(otf, s);
+        sv.batch.read_states();
+        int q = 0;
+        for (ServerReq &r : sv.reqs) {
+            if (r.phase != 1) continue;
+            const int stop = sv.batch.h_states[q++].x;
+            if (!stop) continue;
+            Workspace &w32 = cg_workspace(*r.m, false);
+            Workspace &w64 = cg_workspace(*r.m, true);
+            SEM_HIP(hipMemcpyAsync(w32.h_st, w32.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            SEM_HIP(hipStreamSynchronize(s));
+            const CgState &h = *w32.h_st;
+            r.total += h.iter;
+            r.last_stop = h.stop;
+            r.inner_rel = h.rho0 > 0 ? std::sqrt(h.rho / h.rho0) : 0.0;
+            if (h.stop == 3) {
+                r.broken = true;
+            } else {
+                launch_axpy_from_f32(r.m->n, static_cast<double *>(w64.x), w64.dval + 0,
+                                     static_cast<const float *>(w32.x), s);
+                ++r.outer;
+            }
+            r.phase = 0;   // next round: outer residual and the stopping test
+        }
+    }
+    SEM_HIP(hipStreamSynchronize(s));
+    return (int)sv.reqs.size();
+}
 
 }  // namespace sem

@@ -460,6 +460,9 @@ void api_apply_A64(const Mesh &m, const double *u, double *w, hipStream_t s) {
     apply_A64(m, u, w, s);
 }
 Workspace &cg_workspace(Mesh &m, bool fp64) { return get_ws(m, fp64); }
+size_t workspace_bytes(const Mesh &m) {
+    return (m.ws32 ? m.ws32->bytes : 0) + (m.ws64 ? m.ws64->bytes : 0);
+}
 int cg_auto_chunk(int64_t n, int fixed) { return auto_chunk(n, fixed); }
 
 }  // namespace sem

@@ -59,6 +59,26 @@ void mesh_destroy(Mesh *m) {
     delete m;
 }
 
+// Upper bound of the device bytes a mesh and the work vectors of a solve in
+// precision prec will hold (for admission by memory footprint).
+size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec) {
+    const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
+    const size_t n = (size_t)E * P3;
+    size_t b = (size_t)E * 24 * (8 + 4);          // vertices, FP64 and FP32
+    b += n * 8;                                    // mass
+    b += n * 1;                                    // point codes
+    b += n * 4 * 2;                                // group index list and Dirichlet list (bounds)
+    if (flags & SEM_MESH_G_FP32) b += n * 24;
+    if (flags & SEM_MESH_G_FP64) b += n * 48;
+    b += ((size_t)vec_blocks((int64_t)n) + 16) * 8 + sizeof(CgState) + 4096;
+    const size_t ws32 = n * 4 * 5 + (size_t)E * 8 + (size_t)vec_blocks((int64_t)n) * 8 + 1024;
+    const size_t ws64 = n * 8 * 5 + (size_t)E * 8 + (size_t)vec_blocks((int64_t)n) * 8 + 1024;
+    if (prec == SEM_FP32) b += ws32;
+    else if (prec == SEM_FP64) b += ws64;
+    else b += ws32 + ws64;
+    return b;
+}
+
 Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, const uint8_t *dir,
                   uint32_t flags, hipStream_t s) {
     if (E <= 0) fail(SEM_EINVAL, "n_elem must be positive");

@@ -1,0 +1,209 @@
+"""Continuous-batching serving loop for Poisson solves.
+
+Requests (a mesh and a forcing each) arrive over time.  The scheduler admits
+them in arrival order while a slot is free and their device-memory
+footprint fits in the budget, hands them to the engine, and steps the
+engine one round at a time; requests that arrive while others run join at
+the next round boundary, and finished ones leave and free their memory.
+The GPU engine drives the native continuous-batching server of libsem
+(``sem_server_*``): all admitted solves advance together in batched
+launches, and each result is bitwise the one the request would get alone.
+
+Host side only: the scheduler holds no arithmetic of the method.  Mesh
+preparation for newly admitted requests runs on a worker thread so that it
+overlaps the device work of the requests already running.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import math
+import time
+from dataclasses import dataclass, field
+
+__all__ = ["Request", "Scheduler", "GpuEngine", "summarize"]
+
+
+@dataclass
+class Request:
+    tag: int
+    arrival: float          # seconds after the start of the run
+    n_elem: int
+    order: int
+    payload: dict = field(default_factory=dict)
+    # filled in by the scheduler
+    admitted: float = -1.0
+    done: float = -1.0
+    status: str = "waiting"
+    result: dict | None = None
+
+
+class Scheduler:
+    """Admission by slot and memory footprint, FIFO (optionally with
+    backfilling of smaller requests behind a blocked head)."""
+
+    def __init__(self, engine, budget_bytes: int, max_slots: int = 64, backfill: bool = False):
+        self.engine = engine
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.backfill = backfill
+        self.used = 0
+        self.peak_used = 0
+        self.active: dict[int, int] = {}
+        self.log: list[tuple] = []
+
+    def _try_admit(self, waiting: collections.deque, now: float):
+        while waiting and len(self.active) < self.max_slots:
+            admitted_one = False
+            for k, r in enumerate(waiting):
+                fp = self.engine.footprint(r)
+                if fp > self.budget:
+                    r.status = "rejected"
+                    r.done = now
+                    del waiting[k]
+                    self.log.append(("reject", r.tag, now))
+                    admitted_one = True
+                    break
+                if self.used + fp <= self.budget:
+                    del waiting[k]
+                    r.status = "running"
+                    r.admitted = now
+                    self.active[r.tag] = fp
+                    self.used += fp
+                    self.peak_used = max(self.peak_used, self.used)
+                    self.engine.admit(r)
+                    self.log.append(("admit", r.tag, now))
+                    admitted_one = True
+                    break
+                if not self.backfill:
+                    break
+            if not admitted_one:
+                break
+
+    def run(self, requests):
+        pending = sorted(requests, key=lambda r: (r.arrival, r.tag))
+        by_tag = {r.tag: r for r in pending}
+        waiting: collections.deque = collections.deque()
+        i = 0
+        while i < len(pending) or waiting or self.active:
+            now = self.engine.now()
+            while i < len(pending) and pending[i].arrival <= now:
+                waiting.append(pending[i])
+                i += 1
+            self._try_admit(waiting, now)
+            if not self.active:
+                if i < len(pending):
+                    self.engine.wait_until(pending[i].arrival)
+                    continue
+                if waiting:          # only possible if the head can never fit
+                    r = waiting.popleft()
+                    r.status = "rejected"
+                    continue
+                break
+            for tag, res in self.engine.step():
+                r = by_tag[tag]
+                r.done = self.engine.now()
+                r.status = "done" if res.get("converged") else "failed"
+                r.result = res
+                self.used -= self.active.pop(tag)
+                self.engine.release(tag)
+                self.log.append(("done", tag, r.done))
+        return pending
+
+
+def summarize(requests) -> dict:
+    done = [r for r in requests if r.status in ("done", "failed")]
+    lat = sorted(r.done - r.arrival for r in done)
+
+    def pct(p):
+        if not lat:
+            return None
+        k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+        return lat[k]
+
+    span = (max(r.done for r in done) - min(r.arrival for r in requests)) if done else 0.0
+    return {"requests": len(requests), "completed": len(done),
+            "converged": sum(1 for r in done if r.status == "done"),
+            "rejected": sum(1 for r in requests if r.status == "rejected"),
+            "p50_s": pct(50), "p99_s": pct(99), "mean_s": (sum(lat) / len(lat)) if lat else None,
+            "solves_per_s": (len(done) / span) if span > 0 else None, "span_s": span}
+
+
+class GpuEngine:
+    """Engine on the native server.  `make_problem(request)` returns
+    (vert, glob_id, dirichlet, N, forcing) where forcing(xyz) maps the
+    device coordinates [3][n] of the mesh's GLL points to the source f."""
+
+    def __init__(self, make_problem, tol: float = 1e-8, geom: int = 0, inner_tol: float = 0.0,
+                 round_iters: int = 16, prep_workers: int = 1, keep_results: bool = False):
+        import torch
+
+        from . import MIXED, PRECOMPUTED, Mesh, Server, mesh_footprint
+        self._torch = torch
+        self._Mesh = Mesh
+        self._fp = mesh_footprint
+        self._mixed = MIXED
+        self.geom = geom
+        self.g_fp32 = geom == PRECOMPUTED
+        self.server = Server(tol=tol, geom=geom, inner_tol=inner_tol, round_iters=round_iters)
+        self.make_problem = make_problem
+        self.pool = cf.ThreadPoolExecutor(max_workers=prep_workers)
+        self.preparing: dict[int, cf.Future] = {}
+        self.held: dict[int, tuple] = {}
+        self.keep_results = keep_results
+        self.results: dict[int, object] = {}
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t: float):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(dt)
+
+    def footprint(self, r: Request) -> int:
+        return self._fp(r.n_elem, r.order, g_fp32=self.g_fp32, prec=self._mixed)
+
+    def _prepare(self, r: Request):
+        torch = self._torch
+        vert, gid, dirichlet, N, forcing = self.make_problem(r)
+        mesh = self._Mesh(vert, gid, dirichlet, N, g_fp32=self.g_fp32)
+        f = forcing(mesh.coords())
+        b = mesh.rhs(f.contiguous(), prec=self._mixed)
+        x = torch.zeros_like(b)
+        torch.cuda.current_stream().synchronize()
+        return mesh, b, x
+
+    def admit(self, r: Request):
+        self.preparing[r.tag] = self.pool.submit(self._prepare, r)
+
+    def _add_ready(self, block: bool):
+        ready = [t for t, f in self.preparing.items() if f.done()]
+        if not ready and block and self.preparing:
+            t = min(self.preparing)
+            self.preparing[t].result()
+            ready = [t]
+        for t in ready:
+            mesh, b, x = self.preparing.pop(t).result()
+            self.server.add(mesh, b, x, t)
+            self.held[t] = (mesh, b, x)
+
+    def step(self):
+        self._add_ready(block=not self.held)
+        if not self.held:
+            return []
+        done, _ = self.server.step()
+        return done
+
+    def release(self, tag: int):
+        mesh, b, x = self.held.pop(tag)
+        if self.keep_results:
+            self.results[tag] = x
+        mesh.close()
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+        for t in list(self.held):
+            self.release(t)
+        self.server.close()
