@@ -131,8 +131,15 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--geom", choices=["pre", "otf"], default="pre",
+    ap.add_argument("--geom", choices=["pre", "otf"], default="otf",
                     help="geometric-factor form of the timed solver")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="2: the headline FP32 CG throughput line; 1, 3, 4, 5: the other "
+                         "workloads (FP64 latency, mixed vs FP64, batched, serving)")
+    ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
+                    "(0: 0.8 x the measured batched capacity)")
+    ap.add_argument("--no-tune", action="store_true", help="ignore the tuned tile shapes")
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--nel", type=int, default=32, help="elements per direction")
     ap.add_argument("--order", type=int, default=7)
@@ -156,6 +163,11 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if not args.no_tune:
+        from paper_2108_12188_amd import tune
+        log(f"bench: {tune.apply()} tuned tile shapes applied")
+    if args.config != 2:
+        return SUITES[args.config](args)
     nel, N, iters = args.nel, args.order, args.iters
     log(f"bench: mesh {nel}^3 N={N}")
     mesh = box_mesh(nel, nel, nel, N, perturb=0.1, seed=MESH_SEED_BASE + 2)
@@ -274,6 +286,217 @@ def main(argv=None):
     print(json.dumps(out), flush=True)
     gm.close()
     return 0
+
+
+# ---------------------------------------------------------------------------
+# The other workloads (each prints one JSON line of its own)
+# ---------------------------------------------------------------------------
+def _forcing(xyz):
+    """f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) (manufactured u = sin sin sin)."""
+    import torch
+    return (3 * math.pi ** 2 * torch.sin(math.pi * xyz[0]) * torch.sin(math.pi * xyz[1])
+            * torch.sin(math.pi * xyz[2])).contiguous()
+
+
+def _exact(xyz):
+    import torch
+    return torch.sin(math.pi * xyz[0]) * torch.sin(math.pi * xyz[1]) * torch.sin(math.pi * xyz[2])
+
+
+def _pct(v, p):
+    v = sorted(v)
+    k = min(len(v) - 1, max(0, int(math.ceil(p / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+def _emit(d):
+    print(json.dumps(d), flush=True)
+    return 0
+
+
+def run_config1(args):
+    """Plain FP64 CG, 4^3 affine elements, N = 7, manufactured forcing, 1e-8:
+    latency per solve (p50/p99 over 50 solves) and per iteration."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2108_12188_amd as sem
+    from seminputs import box_mesh
+    mesh = box_mesh(4, 4, 4, 7)
+    gm = sem.Mesh.from_box(mesh, g_fp32=False, g_fp64=True)
+    xyz = gm.coords()
+    b = gm.rhs(_forcing(xyz), prec=sem.FP64)
+    geom = sem.PRECOMPUTED if args.geom == "pre" else sem.ON_THE_FLY
+    for _ in range(5):
+        gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8)
+    torch.cuda.synchronize()
+    times, res = [], None
+    for _ in range(50):
+        t0 = time.perf_counter()
+        x, res = gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8)
+        times.append(time.perf_counter() - t0)
+    x, res_t = gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8, true_residual=True)
+    err = float((x - _exact(xyz)).abs().max())
+    pr = oracle.Problem(mesh)
+    bh = b.cpu().numpy()
+    t0 = time.perf_counter()
+    xo, it_o, _ = pr.cg(bh, tol=1e-8, max_iter=5000, history=False)
+    t_cpu = time.perf_counter() - t0
+    xd = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+    p50 = _pct(times, 50)
+    return _emit({"metric": "FP64 CG solve latency, 4^3 affine hexahedra, N=7, tol 1e-8",
+                  "value": p50 * 1e3, "unit": "ms", "higher_is_better": False,
+                  "p50_ms": p50 * 1e3, "p99_ms": _pct(times, 99) * 1e3,
+                  "iters": res["iters"], "us_per_iter": p50 / res["iters"] * 1e6,
+                  "rel_res_true": res_t["rel_res_true"], "max_err_vs_exact_u": err,
+                  "oracle_iters": it_o, "rel_diff_vs_oracle_x": xd, "geom": args.geom,
+                  "cpu_baseline": {"value": t_cpu * 1e3, "unit": "ms per solve",
+                                   "cores": oracle.num_threads(), "kind": "oracle",
+                                   "sample": "one full FP64 oracle solve of the same problem"},
+                  "dtype": "f64", "data": "synthetic", "config": {"workload": "4^3 N=7 FP64 CG"}})
+
+
+def run_config3(args):
+    """Mixed precision (FP32 inner CG, FP64 outer refinement) against plain
+    FP64 CG, both to a true relative residual of 1e-10, 24^3 deformed
+    hexahedra, N = 9, manufactured forcing."""
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, box_mesh
+    nel = args.nel if args.nel != 32 else 24
+    mesh = box_mesh(nel, nel, nel, 9, perturb=0.1, seed=MESH_SEED_BASE + 3)
+    gm = sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True)
+    n = mesh.n_local
+    xyz = gm.coords()
+    b = gm.rhs(_forcing(xyz), prec=sem.FP64)
+    u = _exact(xyz)
+    out = {}
+    for label, prec, geom in (("mixed_otf", sem.MIXED, sem.ON_THE_FLY),
+                              ("mixed_pre", sem.MIXED, sem.PRECOMPUTED),
+                              ("fp64_pre", sem.FP64, sem.PRECOMPUTED)):
+        gm.cg_solve(b, prec=prec, geom=geom, tol=1e-3, max_iter=50)      # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, r = gm.cg_solve(b, prec=prec, geom=geom, tol=1e-10, max_iter=100000,
+                           true_residual=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[label] = {"seconds": dt, "iters": r["iters"], "outer": r["outer"],
+                      "rel_res_true": r["rel_res_true"], "converged": r["converged"],
+                      "gdof_iter_per_s": n * r["iters"] / dt / 1e9,
+                      "max_err_vs_exact_u": float((x - u).abs().max())}
+        out[label]["x"] = x
+    xf = out["fp64_pre"].pop("x")
+    for k in ("mixed_otf", "mixed_pre"):
+        xm = out[k].pop("x")
+        out[k]["rel_diff_vs_fp64_x"] = gm.dot(xm - xf, xm - xf) ** 0.5 / gm.dot(xf, xf) ** 0.5
+    best = min(out["mixed_otf"]["seconds"], out["mixed_pre"]["seconds"])
+    return _emit({"metric": "time to 1e-10 true residual, 24^3 deformed N=9: mixed vs FP64",
+                  "value": best, "unit": "s", "higher_is_better": False,
+                  "speedup_vs_fp64": out["fp64_pre"]["seconds"] / best, "runs": out,
+                  "n_local": n, "dtype": "f32+f64", "data": "synthetic",
+                  "config": {"workload": f"{nel}^3 N=9 +-10% deformed, manufactured, 1e-10"}})
+
+
+def _batch_problems(count, seed):
+    from seminputs import batch_problems, box_mesh
+    out = []
+    for spec in batch_problems(count, seed=seed):
+        out.append(box_mesh(spec["nx"], spec["ny"], spec["nz"], spec["N"], perturb=0.1,
+                            seed=spec["seed"]))
+    return out
+
+
+def run_config4(args):
+    """64 independent problems (element counts log-uniform 8^3..20^3, N in
+    {5, 7, 9}, deformed), mixed precision to 1e-8 in one batch, against the
+    same problems solved one after the other (mixed, and plain FP64 to
+    1e-10)."""
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE
+    geom = sem.PRECOMPUTED if args.geom == "pre" else sem.ON_THE_FLY
+    boxes = _batch_problems(64, MESH_SEED_BASE + 4)
+    meshes = [sem.Mesh.from_box(bx, g_fp32=True, g_fp64=True) for bx in boxes]
+    bs = [m.rhs(_forcing(m.coords()), prec=sem.FP64) for m in meshes]
+    n_tot = sum(m.n for m in meshes)
+    batch = sem.Batch(meshes)
+    batch.solve(bs, prec=sem.MIXED, geom=geom, tol=1e-3)       # warm: graphs, workspaces
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, res = batch.solve(bs, prec=sem.MIXED, geom=geom, tol=1e-8)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    work = sum(m.n * r["iters"] for m, r in zip(meshes, res))
+    seq_mixed, seq_fp64, lat = 0.0, 0.0, []
+    for m, b in zip(meshes, bs):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.cg_solve(b, prec=sem.MIXED, geom=geom, tol=1e-8)
+        torch.cuda.synchronize()
+        seq_mixed += time.perf_counter() - t1
+        lat.append(time.perf_counter() - t1)
+        t1 = time.perf_counter()
+        m.cg_solve(b, prec=sem.FP64, geom=sem.PRECOMPUTED, tol=1e-10)
+        torch.cuda.synchronize()
+        seq_fp64 += time.perf_counter() - t1
+    batch.close()
+    return _emit({"metric": "batched mixed-precision CG, 64 problems, GDOF*iter/s",
+                  "value": work / t_batch / 1e9, "unit": "GDOF·iter/s", "higher_is_better": True,
+                  "makespan_s": t_batch, "sequential_mixed_s": seq_mixed,
+                  "sequential_fp64_1e-10_s": seq_fp64,
+                  "speedup_vs_sequential_mixed": seq_mixed / t_batch,
+                  "speedup_vs_sequential_fp64": seq_fp64 / t_batch,
+                  "solo_latency_p50_s": _pct(lat, 50), "solo_latency_p99_s": _pct(lat, 99),
+                  "all_converged": all(r["converged"] for r in res),
+                  "max_rel_res_true": max(r["rel_res_true"] for r in res),
+                  "problems": len(meshes), "n_local_total": n_tot, "geom": args.geom,
+                  "dtype": "f32+f64", "data": "synthetic",
+                  "config": {"workload": "64 problems 8^3..20^3, N in {5,7,9}, mixed to 1e-8"}})
+
+
+def run_config5(args):
+    """Serving: seeded Poisson arrivals of solve requests (4^3..24^3 deformed
+    hexahedra, N in {5, 7, 9}, mixed precision to 1e-8); continuous batching
+    with admission by device-memory footprint; latency p50/p99 and solves/s."""
+    import numpy as np
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from paper_2108_12188_amd.serve import GpuEngine, Request, Scheduler, summarize
+    from seminputs import MESH_SEED_BASE, arrival_times, batch_problems, box_mesh
+    geom = sem.PRECOMPUTED if args.geom == "pre" else sem.ON_THE_FLY
+    specs = batch_problems(args.requests, seed=MESH_SEED_BASE + 5, e_lo=4 ** 3, e_hi=24 ** 3)
+    rate = args.rate if args.rate > 0 else 20.0
+    arr = arrival_times(len(specs), rate, seed=MESH_SEED_BASE + 50)
+    reqs = [Request(tag=q, arrival=float(arr[q]), n_elem=sp["nx"] * sp["ny"] * sp["nz"],
+                    order=sp["N"], payload=sp) for q, sp in enumerate(specs)]
+
+    def make_problem(r):
+        sp = r.payload
+        bx = box_mesh(sp["nx"], sp["ny"], sp["nz"], sp["N"], perturb=0.1, seed=sp["seed"])
+        return bx.vert, bx.glob_id, bx.dirichlet, sp["N"], _forcing
+
+    free, total = torch.cuda.mem_get_info()
+    eng = GpuEngine(make_problem, tol=1e-8, geom=geom, round_iters=16, prep_workers=4)
+    sch = Scheduler(eng, budget_bytes=int(0.8 * free), max_slots=64)
+    out = sch.run(reqs)
+    eng.close()
+    st = summarize(out)
+    return _emit({"metric": "serving: solve latency p50 (arrival to result)",
+                  "value": st["p50_s"], "unit": "s", "higher_is_better": False,
+                  "p50_s": st["p50_s"], "p99_s": st["p99_s"], "solves_per_s": st["solves_per_s"],
+                  "summary": st, "arrival_rate_per_s": rate, "peak_admitted_bytes": sch.peak_used,
+                  "budget_bytes": sch.budget, "geom": args.geom, "dtype": "f32+f64",
+                  "data": "synthetic",
+                  "config": {"workload": f"{len(reqs)} requests, 4^3..24^3, N in {{5,7,9}}, "
+                                         f"mixed to 1e-8, Poisson arrivals {rate}/s"}})
+
+
+SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5}
 
 
 if __name__ == "__main__":

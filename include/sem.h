@@ -234,6 +234,19 @@ sem_status sem_server_step(sem_server_t server, int64_t *done_tags, sem_cg_resul
 sem_status sem_mesh_footprint(int64_t n_elem, int order_N, uint32_t flags, sem_precision prec,
                               size_t *bytes);
 
+/*
+ * Tile shape of the local-operator kernels: elements per workgroup for an
+ * order, precision (SEM_FP32 / SEM_FP64) and geometric-factor form; one
+ * thread per (i, j) column, so a workgroup has roundup64(epb (N+1)^2)
+ * threads.  0 restores the built-in default; values are clamped to 512
+ * threads and 64 KiB of LDS.  Process-wide, used by later launches (the
+ * shape fixes the grouping of the FP64 partial sums, so solves that must
+ * agree bitwise need the same shapes).  For the autotuner.
+ */
+sem_status sem_ax_shape_set(int order_N, sem_precision prec, sem_geom geom, int elems_per_block);
+sem_status sem_ax_shape_get(int order_N, sem_precision prec, sem_geom geom, int *elems_per_block,
+                            int *threads, size_t *lds_bytes);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *sem_last_error(void);
 

@@ -12,7 +12,8 @@ import os
 
 import numpy as np
 
-__all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
+__all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_set",
+           "ax_shape_get", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
            "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
@@ -57,8 +58,8 @@ _lib = None
 EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "sem_gs",
            "sem_dot", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
            "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
-           "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_last_error",
-           "sem_version"]
+           "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_ax_shape_set",
+           "sem_ax_shape_get", "sem_last_error", "sem_version"]
 
 
 def library_path() -> str:
@@ -95,13 +96,17 @@ def lib():
     L.sem_server_add.argtypes = [vp, vp, vp, vp, i64]
     L.sem_server_step.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.sem_mesh_footprint.argtypes = [i64, i32, u32, i32, C.POINTER(C.c_size_t)]
+    L.sem_ax_shape_set.argtypes = [i32, i32, i32, i32]
+    L.sem_ax_shape_get.argtypes = [i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_size_t)]
     L.sem_last_error.restype = C.c_char_p
     L.sem_last_error.argtypes = []
     L.sem_version.restype = C.c_char_p
     L.sem_version.argtypes = []
     for name in ("sem_mesh_create", "sem_mesh_info", "sem_ax", "sem_gs", "sem_dot",
                  "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve",
-                 "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint"):
+                 "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint",
+                 "sem_ax_shape_set", "sem_ax_shape_get"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -326,6 +331,17 @@ class Batch:
             return xs, out
         _check(code)
         return xs, out
+
+
+def ax_shape_set(N: int, prec: int, geom: int, elems_per_block: int):
+    """Tile shape (elements per workgroup) of the local operator; 0 = default."""
+    _check(lib().sem_ax_shape_set(N, prec, geom, elems_per_block))
+
+
+def ax_shape_get(N: int, prec: int, geom: int) -> dict:
+    e, t, l = C.c_int(), C.c_int(), C.c_size_t()
+    _check(lib().sem_ax_shape_get(N, prec, geom, C.byref(e), C.byref(t), C.byref(l)))
+    return {"elems_per_block": e.value, "threads": t.value, "lds_bytes": int(l.value)}
 
 
 def mesh_footprint(n_elem: int, N: int, g_fp32: bool = True, g_fp64: bool = False,

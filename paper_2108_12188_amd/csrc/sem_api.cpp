@@ -355,6 +355,31 @@ sem_status sem_mesh_footprint(int64_t n_elem, int order_N, uint32_t flags, sem_p
     });
 }
 
+sem_status sem_ax_shape_set(int order_N, sem_precision prec, sem_geom geom, int elems_per_block) {
+    return guarded([&]() -> sem_status {
+        if (order_N < 1 || order_N > kMaxOrder) fail(SEM_EUNSUPPORTED, "order not built");
+        check_prec(prec);
+        if (geom != SEM_G_PRECOMPUTED && geom != SEM_G_ON_THE_FLY)
+            fail(SEM_EINVAL, "unknown geometry form");
+        if (elems_per_block < 0) fail(SEM_EINVAL, "elems_per_block must be >= 0");
+        ax_shape_set(order_N, prec == SEM_FP64, geom == SEM_G_ON_THE_FLY, elems_per_block);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_ax_shape_get(int order_N, sem_precision prec, sem_geom geom, int *elems_per_block,
+                            int *threads, size_t *lds_bytes) {
+    return guarded([&]() -> sem_status {
+        if (order_N < 1 || order_N > kMaxOrder) fail(SEM_EUNSUPPORTED, "order not built");
+        check_prec(prec);
+        const AxShape sh = ax_shape(order_N, prec == SEM_FP64, geom == SEM_G_ON_THE_FLY, 0);
+        if (elems_per_block) *elems_per_block = sh.epb;
+        if (threads) *threads = sh.threads;
+        if (lds_bytes) *lds_bytes = sh.lds;
+        return SEM_OK;
+    });
+}
+
 const char *sem_last_error(void) { return g_last_error.c_str(); }
 
 const char *sem_version(void) { return "sem-mi355x 0.1 (gfx950)"; }

@@ -1,6 +1,7 @@
 // sem_ax_dispatch.cpp -- order dispatch and launch shapes of the local operator.
 #include "sem_internal.h"
 
+#include <atomic>
 #include <cstdlib>
 
 namespace sem {
@@ -74,21 +75,28 @@ static const Fn64 kFn64[kMaxOrder + 1] = {nullptr,        ax_order_1_f64, ax_ord
 
 // Default elements per block: fill a multiple of 64 lanes with (i, j)
 // columns as tightly as possible, at most 512 threads and 64 KiB of LDS.
+// The autotuner (sem_ax_shape_set) overrides them per order, precision
+// and geometric-factor form.
 static const int kEpb32[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 5, 2, 3};
 static const int kEpb64[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 3, 2, 1};
 
-// Per-process overrides, e.g. from the autotuner: SEM_AX_EPB_<N>=<epb>.
-static int epb_from_env(int N) {
-    char name[32];
-    std::snprintf(name, sizeof name, "SEM_AX_EPB_%d", N);
-    const char *v = std::getenv(name);
-    return v ? std::atoi(v) : 0;
+// Process-wide tile shapes set by the autotuner (0: built-in default),
+// indexed [on-the-fly][fp64][N], and a generation counter that tells cached
+// graphs and batch tables that a shape changed.
+static std::atomic<int> g_epb[2][2][kMaxOrder + 1];
+static std::atomic<int> g_shape_gen{0};
+
+int ax_shape_generation() { return g_shape_gen.load(); }
+
+void ax_shape_set(int N, bool fp64, bool otf, int epb) {
+    g_epb[otf ? 1 : 0][fp64 ? 1 : 0][N].store(epb > 0 ? epb : 0);
+    g_shape_gen.fetch_add(1);
 }
 
-AxShape ax_shape(int N, bool fp64, int epb_override) {
+AxShape ax_shape(int N, bool fp64, bool otf, int epb_override) {
     const int P = N + 1, P2 = P * P, P3 = P2 * P;
     const size_t tsz = fp64 ? 8 : 4;
-    int epb = epb_override > 0 ? epb_override : epb_from_env(N);
+    int epb = epb_override > 0 ? epb_override : g_epb[otf ? 1 : 0][fp64 ? 1 : 0][N].load();
     if (epb <= 0) epb = fp64 ? kEpb64[N] : kEpb32[N];
     // clamp to the kernel limits
     while (epb > 1 && (((epb * P2 + 63) / 64) * 64 > 512 || 2 * tsz * epb * P3 > 65536)) --epb;
@@ -101,7 +109,7 @@ AxShape ax_shape(int N, bool fp64, int epb_override) {
 
 template <>
 void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hipStream_t s) {
-    const AxShape sh = ax_shape(m.N, false, a.epb);
+    const AxShape sh = ax_shape(m.N, false, otf, a.epb);
     a.epb = sh.epb;
     a.E = m.E;
     a.D = m.b32.D;
@@ -117,7 +125,7 @@ void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hip
 
 template <>
 void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, hipStream_t s) {
-    const AxShape sh = ax_shape(m.N, true, a.epb);
+    const AxShape sh = ax_shape(m.N, true, otf, a.epb);
     a.epb = sh.epb;
     a.E = m.E;
     a.D = m.b64.D;
@@ -132,7 +140,7 @@ void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, h
 }
 
 void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
-    const AxShape sh = ax_shape(m.N, false, 0);
+    const AxShape sh = ax_shape(m.N, false, otf, 0);
     a.epb = sh.epb;
     a.E = m.E;
     a.D = m.b32.D;
@@ -152,8 +160,8 @@ void launch_ax_batch(int N, bool otf, const AxArgs<float> *descs, const int2 *bl
     check_hip(hipGetLastError(), "batched ax kernel launch");
 }
 
-int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override) {
-    const AxShape sh = ax_shape(m.N, fp64, epb_override);
+int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override) {
+    const AxShape sh = ax_shape(m.N, fp64, otf, epb_override);
     return ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused);
 }
 

@@ -112,7 +112,7 @@ struct BatchImpl {
         int2 *blk = nullptr;
         int64_t nblk = 0;
     };
-    std::vector<OrderGroup> groups;
+    std::vector<OrderGroup> groups[2];              // [precomputed, on the fly]
     AxArgs<float> *d_ax[2] = {nullptr, nullptr};   // [precomputed, on the fly]
     GsClasses *d_cls = nullptr;
     GsBatchDesc *d_gs = nullptr;
@@ -121,23 +121,25 @@ struct BatchImpl {
     UpdBatchDesc *d_upd = nullptr;
     int2 *d_upd_blk = nullptr;
     int64_t n_upd_blk = 0;
-    FinBatchDesc *d_fin = nullptr;
+    FinBatchDesc *d_fin[2] = {nullptr, nullptr};   // [precomputed, on the fly]
     int2 *d_states = nullptr;
     int2 *h_states = nullptr;                        // pinned
-    size_t cap_ax[2] = {0, 0}, cap_cls = 0, cap_gs = 0, cap_gs_blk = 0, cap_upd = 0,
-           cap_upd_blk = 0, cap_fin = 0, cap_states = 0, cap_h_states = 0;
+    size_t cap_ax[2] = {0, 0}, cap_fin[2] = {0, 0}, cap_cls = 0, cap_gs = 0, cap_gs_blk = 0,
+           cap_upd = 0, cap_upd_blk = 0, cap_states = 0, cap_h_states = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
     size_t bytes = 0;
+    int shape_gen = -1;       // tile-shape generation the tables were built for
 
     ~BatchImpl() {
         (void)hipDeviceSynchronize();
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
-        for (auto &g : groups)
-            if (g.blk) (void)hipFree(g.blk);
-        void *ptrs[] = {d_ax[0], d_ax[1], d_cls, d_gs, d_gs_blk, d_upd, d_upd_blk, d_fin,
-                        d_states};
+        for (int f = 0; f < 2; ++f)
+            for (auto &g : groups[f])
+                if (g.blk) (void)hipFree(g.blk);
+        void *ptrs[] = {d_ax[0], d_ax[1], d_cls, d_gs, d_gs_blk, d_upd, d_upd_blk, d_fin[0],
+                        d_fin[1], d_states};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
         if (h_states) (void)hipHostFree(h_states);
@@ -152,19 +154,20 @@ struct BatchImpl {
     // one batched CG iteration of every problem
     void enqueue_iteration(bool otf, hipStream_t s) {
         if (count() == 0) return;
-        for (const auto &g : groups) {
-            launch_ax_batch(g.N, otf, d_ax[otf ? 1 : 0], g.blk, g.nblk, g.epb,
-                            order_D[g.N].data(), order_xi[g.N].data(), order_w[g.N].data(), s);
+        const int f = otf ? 1 : 0;
+        for (const auto &g : groups[f]) {
+            launch_ax_batch(g.N, otf, d_ax[f], g.blk, g.nblk, g.epb, order_D[g.N].data(),
+                            order_xi[g.N].data(), order_w[g.N].data(), s);
         }
         if (n_gs_blk > 0)
             hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)n_gs_blk), dim3(gsb::kGsThreads), 0,
                                s, d_gs, d_gs_blk);
         hipLaunchKernelGGL(finalize_alpha_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0,
-                           s, d_fin);
+                           s, d_fin[f]);
         hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)n_upd_blk), dim3(vecb::kVecThreads),
                            0, s, d_upd, d_upd_blk);
         hipLaunchKernelGGL(finalize_rho_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0, s,
-                           d_fin);
+                           d_fin[f]);
         check_hip(hipGetLastError(), "batched iteration launch");
     }
 
@@ -173,7 +176,7 @@ struct BatchImpl {
             for (int c = 0; c < chunk; ++c) enqueue_iteration(otf, stream);
             return;
         }
-        const GraphKey key{otf, chunk};
+        const GraphKey key{otf, chunk, ax_shape_generation()};
         auto it = graphs.find(key);
         if (it == graphs.end()) {
             hipGraph_t g = nullptr;
@@ -199,7 +202,7 @@ struct BatchImpl {
     // reads (stop, iter) of every problem
     void read_states() {
         hipLaunchKernelGGL(gather_states_kernel, dim3((count() + 255) / 256), dim3(256), 0, stream,
-                           d_fin, count(), d_states);
+                           d_fin[0], count(), d_states);
         SEM_HIP(hipMemcpyAsync(h_states, d_states, sizeof(int2) * count(), hipMemcpyDeviceToHost,
                                stream));
         SEM_HIP(hipStreamSynchronize(stream));
@@ -249,6 +252,7 @@ BatchImpl *batch_create(int count, const sem_mesh_t *handles) {
 // captured graphs refer to the old tables and are dropped).
 void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     SEM_HIP(hipStreamSynchronize(stream));
+    shape_gen = ax_shape_generation();
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
     meshes = ms;
@@ -257,10 +261,10 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     std::vector<GsClasses> cls;
     std::vector<GsBatchDesc> gsd;
     std::vector<UpdBatchDesc> upd;
-    std::vector<FinBatchDesc> fin;
+    std::vector<FinBatchDesc> fin[2];
     std::vector<int2> gs_blk, upd_blk;
-    std::map<int, std::vector<int2>> order_blk;
-    std::map<int, int> order_epb;
+    std::map<int, std::vector<int2>> order_blk[2];
+    std::map<int, int> order_epb[2];
     ensure_cap(d_cls, cap_cls, count, bytes);
     for (int q = 0; q < count; ++q) {
         Mesh &m = *ms[q];
@@ -276,9 +280,12 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             a.partial = ws.part_ax;
             ax[otf].push_back(a);
         }
-        const AxArgs<float> &a0 = ax[0].back();
-        order_epb[m.N] = a0.epb;
-        for (int64_t vb = 0; vb < a0.vgrid; ++vb) order_blk[m.N].push_back(make_int2(q, (int)vb));
+        for (int f = 0; f < 2; ++f) {
+            const AxArgs<float> &af = ax[f].back();
+            order_epb[f][m.N] = af.epb;
+            for (int64_t vb = 0; vb < af.vgrid; ++vb)
+                order_blk[f][m.N].push_back(make_int2(q, (int)vb));
+        }
         if (!order_D.count(m.N)) {
             order_D[m.N] = m.h_D;
             order_xi[m.N] = m.h_xi;
@@ -293,7 +300,8 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
                        static_cast<const float *>(ws.p), static_cast<const float *>(ws.w), m.mcode,
                        ws.st, ws.part_vec, nv});
         for (int vb = 0; vb < nv; ++vb) upd_blk.push_back(make_int2(q, vb));
-        fin.push_back({ws.st, ws.part_ax, a0.vgrid, ws.part_vec, nv});
+        for (int f = 0; f < 2; ++f)
+            fin[f].push_back({ws.st, ws.part_ax, ax[f].back().vgrid, ws.part_vec, nv});
     }
     for (int otf = 0; otf < 2; ++otf) {
         ensure_cap(d_ax[otf], cap_ax[otf], count, bytes);
@@ -304,8 +312,10 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     upload_sync(d_gs, gsd);
     ensure_cap(d_upd, cap_upd, count, bytes);
     upload_sync(d_upd, upd);
-    ensure_cap(d_fin, cap_fin, count, bytes);
-    upload_sync(d_fin, fin);
+    for (int f = 0; f < 2; ++f) {
+        ensure_cap(d_fin[f], cap_fin[f], count, bytes);
+        upload_sync(d_fin[f], fin[f]);
+    }
     ensure_cap(d_states, cap_states, count, bytes);
     if (cap_h_states < (size_t)count) {
         if (h_states) (void)hipHostFree(h_states);
@@ -319,17 +329,19 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     n_upd_blk = (int64_t)upd_blk.size();
     ensure_cap(d_upd_blk, cap_upd_blk, upd_blk.size(), bytes);
     upload_sync(d_upd_blk, upd_blk);
-    for (auto &g : groups)
-        if (g.blk) (void)hipFree(g.blk);
-    groups.clear();
-    for (auto &kv : order_blk) {
-        OrderGroup g;
-        g.N = kv.first;
-        g.epb = order_epb[kv.first];
-        g.nblk = (int64_t)kv.second.size();
-        g.blk = dalloc<int2>(kv.second.size(), bytes);
-        upload_sync(g.blk, kv.second);
-        groups.push_back(g);
+    for (int f = 0; f < 2; ++f) {
+        for (auto &g : groups[f])
+            if (g.blk) (void)hipFree(g.blk);
+        groups[f].clear();
+        for (auto &kv : order_blk[f]) {
+            OrderGroup g;
+            g.N = kv.first;
+            g.epb = order_epb[f][kv.first];
+            g.nblk = (int64_t)kv.second.size();
+            g.blk = dalloc<int2>(kv.second.size(), bytes);
+            upload_sync(g.blk, kv.second);
+            groups[f].push_back(g);
+        }
     }
 }
 
@@ -388,6 +400,7 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
     if (o.kernel_ms || o.hist_rho || o.hist_alpha)
         fail(SEM_EUNSUPPORTED, "histories and kernel timing are single-mesh options");
     hipStream_t s = B.stream;
+    if (B.shape_gen != ax_shape_generation()) B.rebuild(B.meshes);
     SEM_HIP(hipEventRecord(B.ev, user_s));
     SEM_HIP(hipStreamWaitEvent(s, B.ev, 0));
     int64_t nmax = 0;
@@ -679,7 +692,8 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
     for (ServerReq &r : sv.reqs)
         if (r.phase == 1) inner.push_back(r.m);
     if (!inner.empty()) {
-        if (inner != sv.batch.meshes) sv.batch.rebuild(inner);
+        if (inner != sv.batch.meshes || sv.batch.shape_gen != ax_shape_generation())
+            sv.batch.rebuild(inner);
         for (int c = 0; c < sv.round_iters; ++c) sv.batch.enqueue_iteration(otf, s);
         sv.batch.read_states();
         int q = 0;

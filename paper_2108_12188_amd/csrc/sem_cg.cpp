@@ -116,7 +116,7 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s) {
     a.st = ws.st;
     a.partial = ws.part_ax;
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
-    const int64_t nax = ax_blocks(m, sizeof(T) == 8, 0);
+    const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
     launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
 }
@@ -137,7 +137,7 @@ void enqueue_iteration_timed(const Mesh &m, Workspace &ws, bool otf, hipStream_t
     SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     SEM_HIP(hipEventRecord(ev[1], s));
-    const int64_t nax = ax_blocks(m, sizeof(T) == 8, 0);
+    const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
     launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     SEM_HIP(hipEventRecord(ev[2], s));
     launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
@@ -178,7 +178,7 @@ void run_chunk(const Mesh &m, Workspace &ws, bool otf, int chunk, bool use_graph
         for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, s);
         return;
     }
-    const GraphKey key{otf, chunk};
+    const GraphKey key{otf, chunk, ax_shape_generation()};
     auto it = ws.graphs.find(key);
     if (it == ws.graphs.end()) {
         hipGraph_t g = nullptr;

@@ -9,11 +9,16 @@
 
 namespace sem {
 
+// A captured iteration graph is valid for one geometric-factor form, one
+// chunk length and one generation of the tile-shape table.
 struct GraphKey {
     bool otf;
     int chunk;
+    int shape_gen;
     bool operator<(const GraphKey &o) const {
-        return otf != o.otf ? otf < o.otf : chunk < o.chunk;
+        if (otf != o.otf) return otf < o.otf;
+        if (chunk != o.chunk) return chunk < o.chunk;
+        return shape_gen < o.shape_gen;
     }
 };
 

@@ -139,19 +139,21 @@ struct AxArgs {
 };
 
 // Launch configuration chosen for an order (threads, elements per block,
-// dynamic LDS bytes).  `variant` selects among the tuned shapes.
+// dynamic LDS bytes).
 struct AxShape {
     int epb;
     int threads;
     size_t lds;
 };
-AxShape ax_shape(int N, bool fp64, int epb_override);
+AxShape ax_shape(int N, bool fp64, bool otf, int epb_override);
+void ax_shape_set(int N, bool fp64, bool otf, int epb);
+int ax_shape_generation();
 
 // Fills the basis / geometry pointers and the shape from the mesh; the
 // caller sets u, p, w, mcode, st, partial (and epb to force a shape).
 template <typename T>
 void launch_ax(const Mesh &m, bool otf, AxMode mode, AxArgs<T> a, hipStream_t s);
-int64_t ax_blocks(const Mesh &m, bool fp64, int epb_override);
+int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override);
 // Fills `a` (basis, geometry, epb, vgrid) for a batched FP32 launch of mesh m.
 void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a);
 // One FP32 CG-fused operator launch over many problems of order N:
