@@ -490,6 +490,8 @@ def run_config5(args):
                   "value": st["p50_s"], "unit": "s", "higher_is_better": False,
                   "p50_s": st["p50_s"], "p99_s": st["p99_s"], "solves_per_s": st["solves_per_s"],
                   "summary": st, "arrival_rate_per_s": rate, "peak_admitted_bytes": sch.peak_used,
+                  "not_converged": [(r.tag, r.status, r.result) for r in out
+                                    if r.status != "done"],
                   "budget_bytes": sch.budget, "geom": args.geom, "dtype": "f32+f64",
                   "data": "synthetic",
                   "config": {"workload": f"{len(reqs)} requests, 4^3..24^3, N in {{5,7,9}}, "

@@ -565,6 +565,7 @@ void batch_delete(BatchImpl *b) { delete b; }
 namespace sem {
 
 struct ServerReq {
+    uint64_t uid = 0;       // unique per request (mesh addresses can be reused)
     Mesh *m = nullptr;
     const double *b = nullptr;
     double *x = nullptr;
@@ -580,6 +581,8 @@ struct ServerImpl {
     int round_iters = 16;
     BatchImpl batch;
     std::vector<ServerReq> reqs;
+    uint64_t next_uid = 1;
+    std::vector<uint64_t> batch_uids;   // requests the batch tables were built for
     double inner_tol = 1e-5;
     int max_outer = 20, inner_cap = 100000;
 };
@@ -619,6 +622,7 @@ void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag
     launch_mask<double>(*m, x64, s);
     launch_dot<double>(*m, b, b, w64.dval + 1, w64.part_vec, s);
     ServerReq r;
+    r.uid = sv.next_uid++;
     r.m = m;
     r.b = b;
     r.x = x;
@@ -689,11 +693,17 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
     sv.reqs.swap(keep);
     // 2. a round of batched inner iterations
     std::vector<Mesh *> inner;
+    std::vector<uint64_t> inner_uids;
     for (ServerReq &r : sv.reqs)
-        if (r.phase == 1) inner.push_back(r.m);
+        if (r.phase == 1) {
+            inner.push_back(r.m);
+            inner_uids.push_back(r.uid);
+        }
     if (!inner.empty()) {
-        if (inner != sv.batch.meshes || sv.batch.shape_gen != ax_shape_generation())
+        if (inner_uids != sv.batch_uids || sv.batch.shape_gen != ax_shape_generation()) {
             sv.batch.rebuild(inner);
+            sv.batch_uids = inner_uids;
+        }
         for (int c = 0; c < sv.round_iters; ++c) sv.batch.enqueue_iteration(otf, s);
         sv.batch.read_states();
         int q = 0;

@@ -33,7 +33,7 @@ def candidates(N: int, fp64: bool):
     return out
 
 
-def tune_one(N: int, prec: str, geom: str, target_points: int = 2_000_000, iters: int = 20):
+def tune_one(N: int, prec: str, geom: str, target_points: int = 8_000_000, iters: int = 20):
     """Returns (best epb, {epb: mean fused-operator ms})."""
     import numpy as np
     import torch

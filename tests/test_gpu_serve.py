@@ -58,3 +58,40 @@ def test_serving_mix_equals_solo(geom):
         assert torch.equal(x, eng.results[r.tag]), r.tag
         assert r.result["rel_res_true"] <= 1e-8
         gm.close()
+
+
+def test_server_reuse_after_release():
+    """A request added after another one's mesh was destroyed (its address
+    may be reused) still runs on its own work vectors: every request
+    converges to the bitwise solo result."""
+    import torch
+    import paper_2108_12188_amd as sem
+    srv = sem.Server(tol=1e-8, geom=sem.ON_THE_FLY, round_iters=4)
+    live = {}
+
+    def add(tag):
+        vert, gid, dirichlet, N, forcing = _make_problem(type("R", (), {"tag": tag})())
+        gm = sem.Mesh(vert, gid, dirichlet, N, g_fp32=False)
+        b = gm.rhs(forcing(gm.coords()).contiguous(), prec=sem.MIXED)
+        x = torch.zeros_like(b)
+        srv.add(gm, b, x, tag)
+        live[tag] = (gm, b, x)
+
+    results = {}
+    add(0)
+    add(1)
+    nxt = 2
+    while live:
+        done, _ = srv.step()
+        for tag, res in done:
+            gm, b, x = live.pop(tag)
+            xs, rs = gm.cg_solve(b, prec=sem.MIXED, geom=sem.ON_THE_FLY, tol=1e-8)
+            assert res["converged"] == 1, (tag, res)
+            assert torch.equal(x, xs), tag
+            results[tag] = res
+            gm.close()
+            if nxt < len(SPECS):
+                add(nxt)
+                nxt += 1
+    srv.close()
+    assert len(results) == len(SPECS)
