@@ -140,6 +140,9 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
     ap.add_argument("--no-tune", action="store_true", help="ignore the tuned tile shapes")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (reference kernel of known "
+                         "size for HBM counter calibration)")
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--nel", type=int, default=32, help="elements per direction")
     ap.add_argument("--order", type=int, default=7)
@@ -182,6 +185,13 @@ def main(argv=None):
         x.zero_()
         return gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=iters)
 
+    if args.copy_calib:
+        ca = torch.empty(64 << 20, dtype=torch.float32, device="cuda").uniform_()
+        cb = torch.empty_like(ca)
+        for _ in range(3):
+            cb.copy_(ca)
+        torch.cuda.synchronize()
+        del ca, cb
     log("bench: warmup")
     for _ in range(args.warmup):
         step()
