@@ -97,6 +97,9 @@ typedef struct {
     int64_t n_groups;      /* global points with multiplicity > 1 */
     int64_t n_dirichlet;   /* local points on the Dirichlet boundary */
     size_t device_bytes;   /* device memory held by the handle (mesh arrays and work vectors) */
+    int32_t gs_in_update;  /* 1: every shared point lies on an element face, and sem_cg_solve
+                              gathers the shared sums inside its vector update instead of a
+                              separate gather-scatter pass (same results, bitwise) */
 } sem_mesh_info_t;
 
 sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);

@@ -51,7 +51,8 @@ class CgResult(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [("n_elem", C.c_int64), ("order_N", C.c_int32), ("n_local", C.c_int64),
                 ("n_glob", C.c_int64), ("n_shared", C.c_int64), ("n_groups", C.c_int64),
-                ("n_dirichlet", C.c_int64), ("device_bytes", C.c_size_t)]
+                ("n_dirichlet", C.c_int64), ("device_bytes", C.c_size_t),
+                ("gs_in_update", C.c_int32)]
 
 
 _lib = None

@@ -25,7 +25,7 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["sem_ax_dispatch.cpp", "sem_basis.cpp", "sem_mesh.cpp", "sem_cg.cpp",
+SOURCES = ["sem_ax_dispatch.cpp", "sem_basis.cpp", "sem_mesh.cpp", "sem_tables.cpp", "sem_cg.cpp",
            "sem_api.cpp", "sem_gs.hip", "sem_vec.hip", "sem_geom.hip", "sem_batch.hip"]
 
 

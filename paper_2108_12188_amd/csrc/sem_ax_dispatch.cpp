@@ -77,7 +77,7 @@ static const Fn64 kFn64[kMaxOrder + 1] = {nullptr,        ax_order_1_f64, ax_ord
 // columns as tightly as possible, at most 512 threads and 64 KiB of LDS.
 // The autotuner (sem_ax_shape_set) overrides them per order, precision
 // and geometric-factor form.
-static const int kEpb32[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 5, 2, 3};
+static const int kEpb32[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 2, 2, 3};
 static const int kEpb64[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 3, 2, 1};
 
 // Process-wide tile shapes set by the autotuner (0: built-in default),

@@ -9,12 +9,14 @@
 // and two modes:
 //   * Plain: w = A_L u;
 //   * CgFused: the p-update of Algorithm 1 is the prologue (p <- r + beta p,
-//     the loop fusion of Sec. 5.1), the Dirichlet mask is the epilogue, and
-//     the block's FP64 partial of sum_l p_l w_l is reduced.  Because p is
-//     continuous (p = Q p_g) and the weights of every group add up to one,
-//     <p, QQ^T w, c> = p_g^T Q^T w = sum_l p_l w_l over the local, not yet
-//     gathered w: the whole alpha reduction of Algorithm 1 happens here, before
-//     the gather-scatter, instead of after it as in Sec. 5.1.
+//     the loop fusion of Sec. 5.1) and the block's FP64 partial of
+//     sum_l p_l w_l is reduced.  Because p is continuous (p = Q p_g), zero on
+//     the Dirichlet points, and the weights of every group add up to one,
+//     <p, mask(QQ^T w), c> = p_g^T Q^T w = sum_l p_l w_l over the local, not
+//     yet gathered or masked w: the whole alpha reduction of Algorithm 1
+//     happens here, before the gather-scatter, instead of after it as in
+//     Sec. 5.1.  The mask itself is applied where w is next read (the
+//     vector update), which already holds the point codes.
 //
 // Work decomposition (gfx950, 64-lane waves): a block holds `epb` elements;
 // one thread owns one (i, j) column of one element and walks the k
@@ -283,10 +285,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                     wv += DjT[l] * sa[k * P2 + l * P + i];
                     wv += bk.D[l * P + k] * vtr[l];
                 }
-                if constexpr (FUSED) {
-                    if (a.mcode[base + k * P2] & kDirichletBit) wv = T(0);
-                    acc += (double)uc[k] * (double)wv;
-                }
+                if constexpr (FUSED) acc += (double)uc[k] * (double)wv;
                 a.w[base + k * P2] = wv;
             }
         }

@@ -275,7 +275,6 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             a.u = static_cast<float *>(ws.r);
             a.p = static_cast<float *>(ws.p);
             a.w = static_cast<float *>(ws.w);
-            a.mcode = m.mcode;
             a.st = ws.st;
             a.partial = ws.part_ax;
             ax[otf].push_back(a);

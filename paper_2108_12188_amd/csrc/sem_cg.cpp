@@ -2,12 +2,18 @@
 // refinement built on it.
 //
 // One CG iteration is three kernels:
-//   1. p <- r + beta p fused with w <- mask(A_L p) and the block partials of
-//      <p, w, c> (Algorithm 1: p-update, operator and mask steps);
+//   1. p <- r + beta p fused with w <- A_L p and the block partials of
+//      <p, w, c> (Algorithm 1: p-update and operator steps);
 //   2. w <- QQ^T w on the shared points, then a one-block kernel forms
 //      alpha = rho / <p, w, c>;
-//   3. x += alpha p, r -= alpha w and the partials of rho = <r, r, c>, then a
-//      one-block kernel forms beta and runs the convergence test.
+//   3. x += alpha p, r -= alpha mask(w) and the partials of rho = <r, r, c>,
+//      then a one-block kernel forms beta and runs the convergence test.
+// When every shared point lies on an element's surface (any conforming
+// mesh), step 2 only writes the sums of the groups of more than two copies
+// (edge and vertex nodes) to a compact array, and step 3 forms (QQ^T w)_l
+// itself: a face node adds its partner's w, an edge or vertex node takes its
+// group's sum.  The summed w is never written back, and the results are
+// bitwise those of the three-pass form.
 // The CG scalars never leave the device.  Iterations are enqueued in chunks
 // (replayed HIP graphs by default); after each chunk the host reads the
 // state once.  Kernels of iterations past convergence exit at their first
@@ -26,7 +32,7 @@ namespace {
 void ws_free(Workspace *ws) {
     if (!ws) return;
     for (auto &kv : ws->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->part_ax, ws->part_vec,
+    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->gsum, ws->part_ax, ws->part_vec,
                    ws->st, ws->hist, ws->dval};
     for (void *q : dev)
         if (q) (void)hipFree(q);
@@ -63,6 +69,7 @@ Workspace *ws_create(const Mesh &m, bool fp64) {
         ws->p = ws_alloc<char>(*ws, nv);
         ws->w = ws_alloc<char>(*ws, nv);
         ws->b = ws_alloc<char>(*ws, nv);
+        if (m.gs_in_update) ws->gsum = ws_alloc<char>(*ws, (size_t)m.n_groups_multi * tsz);
         // the smallest shape (1 element per block) bounds the Ax partial count
         ws->cap_ax = m.E;
         ws->cap_vec = vec_blocks(m.n);
@@ -112,13 +119,18 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s) {
     a.u = r;
     a.p = p;
     a.w = w;
-    a.mcode = m.mcode;
     a.st = ws.st;
     a.partial = ws.part_ax;
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
-    launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
-    launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
+    if (m.gs_in_update) {
+        T *gsum = static_cast<T *>(ws.gsum);
+        launch_group_sums_cg<T>(m, w, gsum, ws.st, ws.part_ax, (int)nax, s);
+        launch_update_gather<T>(m, x, r, p, w, gsum, ws.st, ws.part_vec, s);
+    } else {
+        launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
+        launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
+    }
 }
 
 // One iteration with an event before and after each of its three kernels.
@@ -131,16 +143,18 @@ void enqueue_iteration_timed(const Mesh &m, Workspace &ws, bool otf, hipStream_t
     a.u = r;
     a.p = p;
     a.w = w;
-    a.mcode = m.mcode;
     a.st = ws.st;
     a.partial = ws.part_ax;
     SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     SEM_HIP(hipEventRecord(ev[1], s));
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
-    launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
+    T *gsum = static_cast<T *>(ws.gsum);
+    if (m.gs_in_update) launch_group_sums_cg<T>(m, w, gsum, ws.st, ws.part_ax, (int)nax, s);
+    else launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     SEM_HIP(hipEventRecord(ev[2], s));
-    launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
+    if (m.gs_in_update) launch_update_gather<T>(m, x, r, p, w, gsum, ws.st, ws.part_vec, s);
+    else launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
     SEM_HIP(hipEventRecord(ev[3], s));
 }
 

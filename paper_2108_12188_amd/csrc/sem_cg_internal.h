@@ -27,6 +27,7 @@ struct Workspace {
     int64_t n = 0;
     int device = 0;
     void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *b = nullptr;
+    void *gsum = nullptr;           // sums of the groups with m > 2 (gather in the update)
     double *part_ax = nullptr, *part_vec = nullptr;
     int64_t cap_ax = 0;
     int cap_vec = 0;

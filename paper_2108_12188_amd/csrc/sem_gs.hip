@@ -23,14 +23,27 @@ __device__ __forceinline__ int64_t logical_block(int64_t b, int64_t nb_phys) {
     return (b % kXcds) * per + b / kXcds;
 }
 
-// st (may be null): a stopped CG state makes the whole grid exit at once.
+// Logical blocks lb0 .. lb0 + nb_logical - 1.  st (may be null): a stopped
+// CG state makes the whole grid exit at once.
 template <typename T>
 __global__ void __launch_bounds__(kGsThreads)
-gs_kernel(const GsClasses cls, int64_t nb_logical, const int32_t *__restrict__ idx,
+gs_kernel(const GsClasses cls, int64_t lb0, int64_t nb_logical, const int32_t *__restrict__ idx,
           T *__restrict__ w, const CgState *st) {
     if (st && st->stop) return;
     const int64_t b = logical_block(blockIdx.x, gridDim.x);
-    if (b < nb_logical) gs_logical_block<T>(cls, b, idx, w);
+    if (b < nb_logical) gs_logical_block<T>(cls, lb0 + b, idx, w);
+}
+
+// Group sums of the classes with M > 2: logical blocks lb0 .. lb0 +
+// nb_logical - 1 of the gather-scatter numbering.
+template <typename T>
+__global__ void __launch_bounds__(kGsThreads)
+group_sums_kernel(const GsClasses cls, int64_t lb0, int64_t nb_logical,
+                  const int32_t *__restrict__ idx, const T *__restrict__ w, T *__restrict__ out,
+                  const CgState *st) {
+    if (st->stop) return;
+    const int64_t b = logical_block(blockIdx.x, gridDim.x);
+    if (b < nb_logical) gs_sums_logical_block<T>(cls, lb0 + b, idx, w, out);
 }
 
 template <typename T>
@@ -41,31 +54,20 @@ __global__ void mask_kernel(const int32_t *__restrict__ dir, int64_t n_dir, T *_
 
 }  // namespace
 
-int64_t gs_logical_blocks(const Mesh &m) {
-    const int c = m.gs.ncls - 1;
-    return c >= 0 ? m.gs.blk0[c] + (m.gs.ng[c] + gs_per_block(m.gs.M[c]) - 1) / gs_per_block(m.gs.M[c])
-                  : 0;
-}
+int64_t gs_logical_blocks(const Mesh &m) { return gs_total_blocks(m.gs); }
 
-// physical grid: the logical block count rounded up to a multiple of the XCD count
-int gs_cg_blocks(const Mesh &m) {
-    const int64_t b = gs_logical_blocks(m);
-    return (int)(b > 0 ? ((b + kXcds - 1) / kXcds) * kXcds : 1);
-}
+namespace {
+// physical grid: a logical block count rounded up to a multiple of the XCD count
+int gs_phys_blocks(int64_t b) { return (int)(b > 0 ? ((b + kXcds - 1) / kXcds) * kXcds : 1); }
+}  // namespace
 
-void gs_classes_finish(GsClasses &c) {
-    int64_t blk = 0;
-    for (int q = 0; q < c.ncls; ++q) {
-        c.blk0[q] = blk;
-        blk += (c.ng[q] + gs_per_block(c.M[q]) - 1) / gs_per_block(c.M[q]);
-    }
-}
+int gs_cg_blocks(const Mesh &m) { return gs_phys_blocks(gs_logical_blocks(m)); }
 
 template <typename T>
 void launch_gs(const Mesh &m, T *w, hipStream_t s) {
     if (m.n_groups == 0) return;
     const int nb = gs_cg_blocks(m);
-    hipLaunchKernelGGL((gs_kernel<T>), dim3(nb), dim3(kGsThreads), 0, s, m.gs,
+    hipLaunchKernelGGL((gs_kernel<T>), dim3(nb), dim3(kGsThreads), 0, s, m.gs, (int64_t)0,
                        gs_logical_blocks(m), m.gs_idx, w, (const CgState *)nullptr);
     check_hip(hipGetLastError(), "gs kernel launch");
 }
@@ -81,10 +83,23 @@ void launch_mask(const Mesh &m, T *w, hipStream_t s) {
 template <typename T>
 void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, int n_ax_partial,
                   hipStream_t s) {
-    if (m.n_groups > 0) {
-        hipLaunchKernelGGL((gs_kernel<T>), dim3(gs_cg_blocks(m)), dim3(kGsThreads), 0, s, m.gs,
-                           gs_logical_blocks(m), m.gs_idx, w, (const CgState *)st);
+    const int64_t nlb = gs_logical_blocks(m);
+    if (nlb > 0) {
+        hipLaunchKernelGGL((gs_kernel<T>), dim3(gs_phys_blocks(nlb)), dim3(kGsThreads), 0, s,
+                           m.gs, (int64_t)0, nlb, m.gs_idx, w, (const CgState *)st);
         check_hip(hipGetLastError(), "gs/cg kernel launch");
+    }
+    launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
+}
+
+template <typename T>
+void launch_group_sums_cg(const Mesh &m, const T *w, T *gsum, CgState *st,
+                          const double *ax_partial, int n_ax_partial, hipStream_t s) {
+    const int64_t nlb = gs_logical_blocks(m) - m.gs_blk_multi;
+    if (nlb > 0) {
+        hipLaunchKernelGGL((group_sums_kernel<T>), dim3(gs_phys_blocks(nlb)), dim3(kGsThreads), 0,
+                           s, m.gs, m.gs_blk_multi, nlb, m.gs_idx, w, gsum, (const CgState *)st);
+        check_hip(hipGetLastError(), "group sums kernel launch");
     }
     launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
 }
@@ -97,5 +112,9 @@ template void launch_gs_cg<float>(const Mesh &, float *, CgState *, const double
                                   hipStream_t);
 template void launch_gs_cg<double>(const Mesh &, double *, CgState *, const double *, int,
                                    hipStream_t);
+template void launch_group_sums_cg<float>(const Mesh &, const float *, float *, CgState *,
+                                          const double *, int, hipStream_t);
+template void launch_group_sums_cg<double>(const Mesh &, const double *, double *, CgState *,
+                                           const double *, int, hipStream_t);
 
 }  // namespace sem

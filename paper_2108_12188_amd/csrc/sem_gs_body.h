@@ -74,6 +74,82 @@ __device__ __forceinline__ void gs_groups_any(const int32_t *__restrict__ ib, in
     }
 }
 
+// Sums only: out[g] = sum of the copies of group g (ascending local index,
+// the order of gs_groups_fixed); w is read, not written.  Loads of all of a
+// lane's groups are issued before any sum, as in gs_groups_fixed.
+template <typename T, int M>
+__device__ __forceinline__ void gs_sums_fixed(const int32_t *__restrict__ ib, int64_t g0,
+                                              int64_t ng, const T *__restrict__ w,
+                                              T *__restrict__ out) {
+    constexpr int kGsPerThread = gs_per_thread(M);
+    int32_t q[kGsPerThread][M];
+    bool ok[kGsPerThread];
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it) {
+        const int64_t g = g0 + (int64_t)it * kGsThreads;
+        ok[it] = g < ng;
+        if (ok[it]) {
+            const IdxVec<M> iv = *reinterpret_cast<const IdxVec<M> *>(ib + g * M);
+#pragma unroll
+            for (int t = 0; t < M; ++t) q[it][t] = iv.v[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < M; ++t) q[it][t] = 0;
+        }
+    }
+    T v[kGsPerThread][M];
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it)
+#pragma unroll
+        for (int t = 0; t < M; ++t) v[it][t] = ok[it] ? w[q[it][t]] : T(0);
+#pragma unroll
+    for (int it = 0; it < kGsPerThread; ++it) {
+        if (!ok[it]) continue;
+        T s = v[it][0];
+#pragma unroll
+        for (int t = 1; t < M; ++t) s += v[it][t];
+        out[g0 + (int64_t)it * kGsThreads] = s;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gs_sums_any(const int32_t *__restrict__ ib, int M, int64_t g0,
+                                            int64_t ng, const T *__restrict__ w,
+                                            T *__restrict__ out) {
+    for (int it = 0; it < gs_per_thread(M); ++it) {
+        const int64_t g = g0 + (int64_t)it * kGsThreads;
+        if (g >= ng) break;
+        const int32_t *gi = ib + g * M;
+        T s = w[gi[0]];
+        for (int t = 1; t < M; ++t) s += w[gi[t]];
+        out[g] = s;
+    }
+}
+
+// One logical block lb of a mesh's group sums over the classes with M > 2
+// (lb counts from the first block of those classes).  The sums of class c
+// go to out + (groups of the classes with M > 2 before c).
+template <typename T>
+__device__ __forceinline__ void gs_sums_logical_block(const GsClasses &cls, int64_t lb,
+                                                      const int32_t *__restrict__ idx,
+                                                      const T *__restrict__ w,
+                                                      T *__restrict__ out) {
+    int c = 0;
+    while (c + 1 < cls.ncls && lb >= cls.blk0[c + 1]) ++c;
+    int64_t goff = 0;
+    for (int q = 0; q < c; ++q)
+        if (cls.M[q] > 2) goff += cls.ng[q];
+    const int M = cls.M[c];
+    const int64_t g0 = (lb - cls.blk0[c]) * gs_per_block(M) + threadIdx.x;
+    const int32_t *ib = idx + cls.io[c];
+    const int64_t ng = cls.ng[c];
+    switch (M) {
+        case 4: gs_sums_fixed<T, 4>(ib, g0, ng, w, out + goff); break;
+        case 8: gs_sums_fixed<T, 8>(ib, g0, ng, w, out + goff); break;
+        default: gs_sums_any<T>(ib, M, g0, ng, w, out + goff); break;
+    }
+}
+
 // One logical block lb of a mesh's gather-scatter (uniform across the block).
 template <typename T>
 __device__ __forceinline__ void gs_logical_block(const GsClasses &cls, int64_t lb,

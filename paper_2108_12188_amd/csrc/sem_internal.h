@@ -72,6 +72,7 @@ struct GsClasses {
     int64_t blk0[kMaxGsClasses];   // first block of the class in a gs launch
 };
 void gs_classes_finish(GsClasses &c);
+int64_t gs_total_blocks(const GsClasses &c);   // logical blocks of a whole gather-scatter
 
 struct Mesh {
     int device = 0;
@@ -94,6 +95,20 @@ struct Mesh {
     uint8_t *mcode = nullptr;     // [n]: multiplicity | Dirichlet bit
     int32_t *gs_idx = nullptr;    // [n_shared], class-major, groups of M ascending indices
     int32_t *dir_idx = nullptr;   // [n_dir]
+    // Shared sums inside the CG update (used when every shared point lies on
+    // the surface of its element's P^3 block): surf_slot[loc] ranks local
+    // node loc among the S surface nodes of an element (-1 inside);
+    // slink[e][slot] is the other copy of a pair (m = 2) or the rank of a
+    // larger group among the n_groups_multi groups with m > 2, whose sums a
+    // gather-scatter variant over blocks gs_blk_multi.. writes to a compact
+    // array.  Local index l = e P3 + loc, with e = (l * p3_magic) >> p3_shift.
+    bool gs_in_update = false;
+    int S = 0;
+    int64_t n_groups_multi = 0, gs_blk_multi = 0;
+    int16_t *surf_slot = nullptr;  // [P3]
+    int32_t *slink = nullptr;      // [E][S]
+    uint32_t p3_magic = 0;
+    int p3_shift = 0;
     Basis<float> b32;
     Basis<double> b64;
     void *basis_blob = nullptr;
@@ -107,6 +122,26 @@ struct Mesh {
 };
 
 Mesh *as_mesh(sem_mesh_t m);
+
+// Host tables of a mesh's scatter map (sem_tables.cpp; no device calls).
+struct HostTables {
+    int64_t n_glob = 0, n_groups = 0, n_shared = 0, n_dir = 0;
+    GsClasses gs{};
+    std::vector<uint8_t> mcode;     // [n]
+    std::vector<int32_t> gs_idx;    // class-major ascending member lists
+    std::vector<int32_t> dir_idx;   // Dirichlet local points
+    bool gs_in_update = false;      // every shared point on its element's surface
+    int S = 0;                      // surface nodes per element
+    int64_t n_groups_multi = 0;     // groups with more than two copies
+    int64_t gs_blk_multi = 0;       // their first gather-scatter block
+    std::vector<int16_t> slot;      // [P3] surface slot or -1
+    std::vector<int32_t> slink;     // [E][S] (only when gs_in_update)
+    uint32_t p3_magic = 0;
+    int p3_shift = 0;
+};
+// Validates glob_id / dirichlet (fail() on error) and fills t.
+void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, HostTables &t);
+int surface_nodes(int N);
 
 // ---------------------------------------------------------------------------
 // Host basis construction (sem_basis.cpp)
@@ -132,7 +167,6 @@ struct AxArgs {
     const T *Dt;                // [P][P]
     const T *xi;                // [P]
     const T *wq;                // [P]
-    const uint8_t *mcode;       // CgFused: mask / interior weights
     CgState *st;                // CgFused: beta, stop flag
     double *partial;            // CgFused: one FP64 partial of sum p w per block
     int64_t vgrid;              // batched launches: this problem's own grid size
@@ -172,6 +206,12 @@ void launch_mask(const Mesh &m, T *w, hipStream_t s);
 template <typename T>
 void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, int n_ax_partial,
                   hipStream_t s);
+// The same for the gather in the update: gsum[k] = sum of the copies of the
+// k-th group with m > 2 (ascending local index; w is not modified), then
+// alpha.
+template <typename T>
+void launch_group_sums_cg(const Mesh &m, const T *w, T *gsum, CgState *st,
+                          const double *ax_partial, int n_ax_partial, hipStream_t s);
 int gs_cg_blocks(const Mesh &m);
 int64_t gs_logical_blocks(const Mesh &m);
 
@@ -183,6 +223,12 @@ int vec_blocks(int64_t n);
 template <typename T>
 void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
                    double *partial, hipStream_t s);
+// The same with w read as QQ^T w, w holding the operator's masked local
+// output and gsum the group sums of launch_group_sums_cg: pairs are summed
+// inside the update (needs m.gs_in_update).
+template <typename T>
+void launch_update_gather(const Mesh &m, T *x, T *r, const T *p, const T *w, const T *gsum,
+                          CgState *st, double *partial, hipStream_t s);
 // r = b - w (w may be null: r = b); p = 0; rho_0 = <r, r, c>; initial state
 template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,

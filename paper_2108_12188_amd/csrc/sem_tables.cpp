@@ -1,0 +1,229 @@
+// sem_tables.cpp -- host construction of the gather-scatter tables.
+//
+// The scatter map Q of Sec. 3.1 arrives as one global id per local point.
+// Local points sharing an id are the copies summed by the gather-scatter
+// (Sec. 4.3: points with equal position).  They are grouped here, once per
+// mesh: groups of m > 1 copies are bucketed by m, each group's local
+// indices ascending, and groups inside a bucket in ascending order of their
+// first local index.  No device call is made in this file.
+#include <algorithm>
+#include <numeric>
+
+#include "sem_gs_body.h"
+#include "sem_internal.h"
+
+namespace sem {
+
+// Nodes on the surface of one element's P^3 block: P^3 - (P-2)^3 (all 8 for N = 1).
+int surface_nodes(int N) {
+    const int P = N + 1, Pi = P - 2;
+    return P * P * P - (Pi > 0 ? Pi * Pi * Pi : 0);
+}
+
+// Rank of every local node among the surface nodes of its element, in
+// ascending local index (-1 for interior nodes).
+static std::vector<int16_t> surface_slots(int N) {
+    const int P = N + 1;
+    std::vector<int16_t> slot((size_t)P * P * P, -1);
+    int16_t s = 0;
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j)
+            for (int i = 0; i < P; ++i)
+                if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N)
+                    slot[i + P * (j + P * k)] = s++;
+    return slot;
+}
+
+// Division of l < 2^31 by d (1 <= d < 2^16) as (l * magic) >> shift with
+// shift = 31 + ceil(log2 d) and magic = ceil(2^shift / d) < 2^32: the
+// rounding excess magic * d - 2^shift is below d <= 2^(shift - 31), so the
+// error term l (magic d - 2^shift) / (d 2^shift) stays below 1/d and
+// never crosses an integer.
+static void division_magic(uint32_t d, uint32_t &magic, int &shift) {
+    int lg = 0;
+    while ((1u << lg) < d) ++lg;
+    shift = 31 + lg;
+    const unsigned __int128 one = 1;
+    magic = (uint32_t)(((one << shift) + d - 1) / d);
+}
+
+void gs_classes_finish(GsClasses &c) {
+    int64_t blk = 0;
+    for (int q = 0; q < c.ncls; ++q) {
+        c.blk0[q] = blk;
+        blk += (c.ng[q] + gsb::gs_per_block(c.M[q]) - 1) / gsb::gs_per_block(c.M[q]);
+    }
+}
+
+int64_t gs_total_blocks(const GsClasses &c) {
+    const int q = c.ncls - 1;
+    return q >= 0 ? c.blk0[q] + (c.ng[q] + gsb::gs_per_block(c.M[q]) - 1) / gsb::gs_per_block(c.M[q])
+                  : 0;
+}
+
+void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, HostTables &t) {
+    const int P = N + 1, P3 = P * P * P;
+    const int64_t n = E * P3;
+    // ---- global ids: validate, count copies -------------------------------
+    int64_t maxid = -1;
+    for (int64_t l = 0; l < n; ++l) {
+        if (gid[l] < 0) fail(SEM_EINVAL, "glob_id has a negative entry at " + std::to_string(l));
+        maxid = std::max(maxid, gid[l]);
+    }
+    // compact ids to 0..n_glob-1 in order of first appearance
+    std::vector<int32_t> cid(n);
+    {
+        const bool dense = maxid < 4 * n + 16;
+        if (dense) {
+            std::vector<int32_t> map(maxid + 1, -1);
+            int32_t next = 0;
+            for (int64_t l = 0; l < n; ++l) {
+                int32_t &c = map[gid[l]];
+                if (c < 0) c = next++;
+                cid[l] = c;
+            }
+            t.n_glob = next;
+        } else {
+            std::vector<int64_t> order(n);
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int64_t a, int64_t b) { return gid[a] < gid[b]; });
+            // first-appearance numbering: smallest l of each id
+            std::vector<std::pair<int64_t, int64_t>> first;   // (first l, rank in sorted ids)
+            int32_t rank = -1;
+            std::vector<int32_t> rank_of(n);
+            for (int64_t t = 0; t < n; ++t) {
+                if (t == 0 || gid[order[t]] != gid[order[t - 1]]) {
+                    ++rank;
+                    first.push_back({order[t], rank});
+                }
+                rank_of[order[t]] = rank;
+            }
+            std::vector<int32_t> renum(first.size());
+            std::sort(first.begin(), first.end());
+            for (size_t q = 0; q < first.size(); ++q) renum[first[q].second] = (int32_t)q;
+            for (int64_t l = 0; l < n; ++l) cid[l] = renum[rank_of[l]];
+            t.n_glob = (int64_t)first.size();
+        }
+    }
+    const int64_t G = t.n_glob;
+    std::vector<int32_t> cnt(G, 0);
+    for (int64_t l = 0; l < n; ++l) ++cnt[cid[l]];
+    std::vector<int8_t> dflag(G, -1);
+    for (int64_t l = 0; l < n; ++l) {
+        const int8_t d = dir ? (dir[l] ? 1 : 0) : 0;
+        int8_t &f = dflag[cid[l]];
+        if (f < 0) f = d;
+        else if (f != d)
+            fail(SEM_EINVAL, "dirichlet flags differ between copies of a global point (local " +
+                                 std::to_string(l) + ")");
+    }
+    std::vector<uint8_t> &mcode = t.mcode;
+    mcode.assign(n, 0);
+    int64_t n_dir = 0;
+    for (int64_t l = 0; l < n; ++l) {
+        const int32_t c = cnt[cid[l]];
+        if (c > kMaxMultiplicity)
+            fail(SEM_EINVAL, "more than 127 local copies of one global point");
+        const bool d = dflag[cid[l]] == 1;
+        mcode[l] = (uint8_t)((d ? kDirichletBit : 0) | c);
+        n_dir += d;
+    }
+
+    // ---- groups by size class ----------------------------------------------
+    // CSR of local points by compact id (ascending l inside each id)
+    std::vector<int64_t> start(G + 1, 0);
+    for (int64_t g = 0; g < G; ++g) start[g + 1] = start[g] + cnt[g];
+    std::vector<int32_t> byid(n);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t l = 0; l < n; ++l) byid[fill[cid[l]]++] = (int32_t)l;
+    }
+    // compact ids are numbered by first appearance, so ascending id order is
+    // ascending first-local-index order
+    int sizes_seen[256] = {0};
+    for (int64_t g = 0; g < G; ++g)
+        if (cnt[g] > 1) sizes_seen[cnt[g]] = 1;
+    GsClasses cls{};
+    int64_t n_shared = 0, n_groups = 0;
+    std::vector<int32_t> &gs_idx = t.gs_idx;
+    gs_idx.clear();
+    // per local point: the other copy of a pair (m = 2), or the rank of its
+    // group among the groups of more than two copies (class order)
+    std::vector<int32_t> plink(n, 0);
+    int64_t n_multi = 0;
+    for (int msz = 2; msz <= kMaxMultiplicity; ++msz) {
+        if (!sizes_seen[msz]) continue;
+        if (cls.ncls == kMaxGsClasses)
+            fail(SEM_EUNSUPPORTED, "more than 32 distinct multiplicities");
+        const int c = cls.ncls++;
+        cls.M[c] = msz;
+        // every class starts on a 32-byte boundary (vector index loads)
+        while (gs_idx.size() % 8) gs_idx.push_back(0);
+        cls.io[c] = (int64_t)gs_idx.size();
+        int64_t ng = 0;
+        for (int64_t g = 0; g < G; ++g) {
+            if (cnt[g] != msz) continue;
+            for (int64_t o = start[g]; o < start[g + 1]; ++o) gs_idx.push_back(byid[o]);
+            if (msz == 2) {
+                plink[byid[start[g]]] = byid[start[g] + 1];
+                plink[byid[start[g] + 1]] = byid[start[g]];
+            } else {
+                for (int64_t o = start[g]; o < start[g + 1]; ++o) plink[byid[o]] = (int32_t)n_multi;
+                ++n_multi;
+            }
+            ++ng;
+        }
+        cls.ng[c] = ng;
+        n_groups += ng;
+        n_shared += ng * msz;
+    }
+    while (gs_idx.size() % 8) gs_idx.push_back(0);
+    gs_classes_finish(cls);
+    t.gs = cls;
+    // classes are in ascending m: the groups of more than two copies are the
+    // gather-scatter blocks from the first class with M > 2 on
+    t.n_groups_multi = n_multi;
+    t.gs_blk_multi = gs_total_blocks(cls);
+    for (int c = 0; c < cls.ncls; ++c)
+        if (cls.M[c] > 2) {
+            t.gs_blk_multi = cls.blk0[c];
+            break;
+        }
+    t.n_groups = n_groups;
+    t.n_shared = n_shared;
+    t.n_dir = n_dir;
+    std::vector<int32_t> &dir_idx = t.dir_idx;
+    dir_idx.clear();
+    dir_idx.reserve(n_dir);
+    for (int64_t l = 0; l < n; ++l)
+        if (mcode[l] & kDirichletBit) dir_idx.push_back((int32_t)l);
+
+    // Tables of the gather inside the CG update: possible when every shared
+    // point lies on its element's surface (true of every conforming mesh:
+    // shared nodes are face, edge and vertex nodes).  The entry of a pair
+    // point is its partner's local index; that of a point in a larger group
+    // is the group's rank among the groups with m > 2, in class order (the
+    // order of the group-sum kernel's output).
+    t.slot = surface_slots(N);
+    const std::vector<int16_t> &slot = t.slot;
+    const int S = surface_nodes(N);
+    bool ok = true;
+    for (int64_t l = 0; l < n && ok; ++l)
+        if ((mcode[l] & kMultMask) > 1 && slot[l % P3] < 0) ok = false;
+    t.slink.clear();
+    if (ok) {
+        t.slink.assign((size_t)E * S, 0);
+        for (int64_t l = 0; l < n; ++l) {
+            const int sl = slot[l % P3];
+            if (sl >= 0) t.slink[(size_t)(l / P3) * S + sl] = plink[l];
+        }
+    }
+    std::vector<int32_t>().swap(plink);
+    t.gs_in_update = ok;
+    t.S = S;
+    division_magic((uint32_t)P3, t.p3_magic, t.p3_shift);
+
+}
+
+}  // namespace sem

@@ -20,6 +20,15 @@ update_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restri
     update_body<T>(n, x, r, p, w, mcode, st, partial, blockIdx.x, gridDim.x);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+update_gather_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
+                     const T *__restrict__ w, const T *__restrict__ gsum,
+                     const uint8_t *__restrict__ mcode, const GatherMap gm, CgState *st,
+                     double *partial) {
+    update_gather_body<T>(n, x, r, p, w, gsum, mcode, gm, st, partial, blockIdx.x, gridDim.x);
+}
+
 __global__ void __launch_bounds__(kFinalizeThreads)
 finalize_rho_kernel(CgState *st, const double *partial, int cnt) {
     finalize_rho_body(st, partial, cnt);
@@ -167,6 +176,20 @@ void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *s
 }
 
 template <typename T>
+void launch_update_gather(const Mesh &m, T *x, T *r, const T *p, const T *w, const T *gsum,
+                          CgState *st, double *partial, hipStream_t s) {
+    if (!m.gs_in_update)
+        fail(SEM_EUNSUPPORTED, "mesh shares points inside elements: no gather in the update");
+    const GatherMap gm{m.surf_slot, m.slink, m.p3_magic, m.p3_shift, m.P3, m.S};
+    const int nb = vec_blocks(m.n);
+    hipLaunchKernelGGL((update_gather_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, x, r,
+                       p, w, gsum, m.mcode, gm, st, partial);
+    hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
+                       (const double *)partial, nb);
+    check_hip(hipGetLastError(), "update kernel launch");
+}
+
+template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
                     double *partial, hipStream_t s) {
     const int nb = vec_blocks(m.n);
@@ -228,6 +251,12 @@ template void launch_update<float>(const Mesh &, float *, float *, const float *
                                    CgState *, double *, hipStream_t);
 template void launch_update<double>(const Mesh &, double *, double *, const double *,
                                     const double *, CgState *, double *, hipStream_t);
+template void launch_update_gather<float>(const Mesh &, float *, float *, const float *,
+                                          const float *, const float *, CgState *, double *,
+                                          hipStream_t);
+template void launch_update_gather<double>(const Mesh &, double *, double *, const double *,
+                                           const double *, const double *, CgState *, double *,
+                                           hipStream_t);
 template void launch_cg_init<float>(const Mesh &, const float *, const float *, float *, float *,
                                     CgState *, double *, hipStream_t);
 template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,

@@ -26,8 +26,9 @@ __device__ __forceinline__ void weights_lds(double *cw) {
     __syncthreads();
 }
 
-// x += alpha p; r -= alpha w; rho_i = <r, r, c>  (Algorithm 1, fused updates
-// and reduction), then beta_i = rho_i / rho_{i-1} and the convergence test.
+// x += alpha p; r -= alpha mask(w); rho_i = <r, r, c>  (Algorithm 1: mask,
+// fused updates and reduction; the operator leaves w unmasked), then
+// beta_i = rho_i / rho_{i-1} and the convergence test.
 // Virtual block vb of a grid of vgrid blocks; the partial goes to
 // partial[vb].
 template <typename T>
@@ -52,8 +53,9 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
         const Code4 mv = reinterpret_cast<const Code4 *>(mcode)[q];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+            const T wm = (mv.v[t] & kDirichletBit) ? T(0) : wv.v[t];
             xv.v[t] += a * pv.v[t];
-            rv.v[t] -= a * wv.v[t];
+            rv.v[t] -= a * wm;
             const double rd = (double)rv.v[t];
             acc += rd * rd * cw[mv.v[t]];
         }
@@ -61,10 +63,120 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
         reinterpret_cast<Pack4<T> *>(r)[q] = rv;
     }
     for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
+        const uint8_t c = mcode[q];
         x[q] += a * p[q];
-        const T rn = r[q] - a * w[q];
+        const T rn = r[q] - a * ((c & kDirichletBit) ? T(0) : w[q]);
         r[q] = rn;
-        acc += (double)rn * (double)rn * cw[mcode[q]];
+        acc += (double)rn * (double)rn * cw[c];
+    }
+    const double s = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) partial[vb] = s;
+}
+
+// Where the sums over the copies are formed inside the update (the tables
+// of the mesh, see Mesh::slink).
+struct GatherMap {
+    const int16_t *surf_slot;    // [P3]
+    const int32_t *slink;        // [E][S]
+    uint32_t p3_magic;
+    int p3_shift;
+    int P3;
+    int S;
+};
+
+// Entry of the gather table for local point l: the partner of a pair point,
+// the group rank of a point in a larger group (its element's first entry
+// for nodes inside the element, so the load is always in bounds).  slot:
+// the surface-slot table (in LDS on the device).
+__host__ __device__ __forceinline__ int32_t node_link(uint32_t l, const GatherMap &g,
+                                                      const int16_t *slot) {
+    const uint32_t e = (uint32_t)(((uint64_t)l * g.p3_magic) >> g.p3_shift);
+    const int sl = slot[l - e * (uint32_t)g.P3];
+    return g.slink[(size_t)e * g.S + (sl > 0 ? sl : 0)];
+}
+
+// Code of a pair point off the Dirichlet boundary: m = 2, flag clear.
+constexpr uint8_t kPairCode = 2;
+
+__host__ __device__ __forceinline__ bool is_group_code(uint8_t code) {
+    return (code & kMultMask) > 2 && !(code & kDirichletBit);
+}
+
+// The one value point l loads besides its own: its partner's w (pairs), its
+// group's sum (larger groups), else its own w again.
+template <typename T>
+__host__ __device__ __forceinline__ const T *gather_source(const T *w, const T *gsum,
+                                                           uint8_t code, int32_t lk, int64_t l) {
+    return code == kPairCode ? w + (uint32_t)lk
+                             : (is_group_code(code) ? gsum + (uint32_t)lk : w + l);
+}
+
+// mask(QQ^T w)_l: a pair adds its partner's value (a + b == b + a in IEEE
+// arithmetic, so both copies get the sum the gather-scatter forms); a point
+// of a larger group takes the group's sum (formed in the gather-scatter's
+// order); points with m = 1 keep their own value, Dirichlet points get 0.
+// src: the value at gather_source.
+template <typename T>
+__host__ __device__ __forceinline__ T copies_sum(T own, uint8_t code, T src) {
+    if (code & kDirichletBit) return T(0);
+    return code == kPairCode ? own + src : (is_group_code(code) ? src : own);
+}
+
+// update_body with w replaced by QQ^T w (w itself is not modified).  Same
+// grid, same per-thread order and the same sums as gather-scatter +
+// update_body, so the results are bitwise those of the two-pass form.  All
+// loads are unconditional: a pack costs two dependent rounds of loads.
+template <typename T>
+__device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ x,
+                                                   T *__restrict__ r, const T *__restrict__ p,
+                                                   const T *__restrict__ w,
+                                                   const T *__restrict__ gsum,
+                                                   const uint8_t *__restrict__ mcode,
+                                                   const GatherMap &gm, CgState *st,
+                                                   double *partial, int64_t vb, int64_t vgrid) {
+    if (st->stop) return;
+    __shared__ double cw[kVecThreads];
+    __shared__ double red[16];
+    __shared__ int16_t slot[kMaxP * kMaxP * kMaxP];
+    for (int q = threadIdx.x; q < gm.P3; q += blockDim.x) slot[q] = gm.surf_slot[q];
+    weights_lds(cw);
+    const T a = (T)st->alpha;
+    double acc = 0.0;
+    const int64_t n4 = n >> 2;
+    const int64_t stride = vgrid * blockDim.x;
+    const int64_t tid = vb * blockDim.x + threadIdx.x;
+    for (int64_t q = tid; q < n4; q += stride) {
+        const uint32_t l0 = (uint32_t)(4 * q);
+        int32_t lk[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) lk[t] = node_link(l0 + t, gm, slot);
+        Pack4<T> xv = reinterpret_cast<const Pack4<T> *>(x)[q];
+        Pack4<T> rv = reinterpret_cast<const Pack4<T> *>(r)[q];
+        const Pack4<T> pv = reinterpret_cast<const Pack4<T> *>(p)[q];
+        const Pack4<T> wv = reinterpret_cast<const Pack4<T> *>(w)[q];
+        const Code4 mv = reinterpret_cast<const Code4 *>(mcode)[q];
+        T src[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) src[t] = *gather_source<T>(w, gsum, mv.v[t], lk[t], l0 + t);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const T wg = copies_sum<T>(wv.v[t], mv.v[t], src[t]);
+            xv.v[t] += a * pv.v[t];
+            rv.v[t] -= a * wg;
+            const double rd = (double)rv.v[t];
+            acc += rd * rd * cw[mv.v[t]];
+        }
+        reinterpret_cast<Pack4<T> *>(x)[q] = xv;
+        reinterpret_cast<Pack4<T> *>(r)[q] = rv;
+    }
+    for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
+        const uint8_t c = mcode[q];
+        const int32_t lk = node_link((uint32_t)q, gm, slot);
+        const T wg = copies_sum<T>(w[q], c, *gather_source<T>(w, gsum, c, lk, q));
+        x[q] += a * p[q];
+        const T rn = r[q] - a * wg;
+        r[q] = rn;
+        acc += (double)rn * (double)rn * cw[c];
     }
     const double s = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partial[vb] = s;

@@ -1,0 +1,160 @@
+// Host check of the gather-scatter tables and of the gather that the CG
+// update does with them (the same __host__ __device__ functions the kernel
+// calls, run here on the CPU over every local point): the sums of the groups
+// of more than two copies, then the update's gather, must give every point
+// the ascending-order sum of all its copies, bitwise.
+//
+// usage: gather_tables_check E N glob_id.bin dirichlet.bin seed
+//   glob_id.bin: int64 [E][(N+1)^3], dirichlet.bin: uint8 [E][(N+1)^3]
+// Prints "gs_in_update=<0|1> checked=<points> odd_m=<points with m other
+// than 1, 2, 4, 8>" and exits 0, or names the first failing point and exits 1.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <random>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../paper_2108_12188_amd/csrc/sem_vec_body.h"
+
+namespace sem {
+void set_error(const std::string &) {}
+[[noreturn]] void fail(sem_status code, const std::string &msg) {
+    throw std::runtime_error("status " + std::to_string((int)code) + ": " + msg);
+}
+void check_hip(hipError_t, const char *) {}
+}  // namespace sem
+
+template <typename T>
+static std::vector<T> read_all(const char *path, size_t count) {
+    std::vector<T> v(count);
+    FILE *f = std::fopen(path, "rb");
+    if (!f || std::fread(v.data(), sizeof(T), count, f) != count) {
+        std::fprintf(stderr, "cannot read %s\n", path);
+        std::exit(2);
+    }
+    std::fclose(f);
+    return v;
+}
+
+#define CHECK(cond, ...)                                   \
+    do {                                                   \
+        if (!(cond)) {                                     \
+            std::printf("FAIL l=%lld: ", (long long)l);    \
+            std::printf(__VA_ARGS__);                      \
+            std::printf("\n");                             \
+            return 1;                                      \
+        }                                                  \
+    } while (0)
+
+int main(int argc, char **argv) {
+    if (argc != 6) {
+        std::fprintf(stderr, "usage: %s E N glob_id.bin dirichlet.bin seed\n", argv[0]);
+        return 2;
+    }
+    const int64_t E = std::atoll(argv[1]);
+    const int N = std::atoi(argv[2]);
+    const int P = N + 1, P3 = P * P * P;
+    const int64_t n = E * P3;
+    const std::vector<int64_t> gid = read_all<int64_t>(argv[3], (size_t)n);
+    const std::vector<uint8_t> dir = read_all<uint8_t>(argv[4], (size_t)n);
+    sem::HostTables t;
+    sem::build_tables(E, N, gid.data(), dir.data(), t);
+    int64_t l = -1;
+    CHECK(t.S == sem::surface_nodes(N), "S");
+    CHECK((int)t.slot.size() == P3, "slot table size");
+
+    // reference: copies of every global id in ascending local index
+    std::map<int64_t, std::vector<int64_t>> copies;
+    for (l = 0; l < n; ++l) copies[gid[l]].push_back(l);
+
+    std::mt19937_64 rng(std::strtoull(argv[5], nullptr, 10));
+    std::uniform_real_distribution<float> U(-1.f, 1.f);
+    std::vector<float> w32(n);
+    std::vector<double> w64(n);
+    // the operator leaves w unmasked: Dirichlet points hold values too
+    for (l = 0; l < n; ++l) {
+        w32[l] = U(rng);
+        w64[l] = (double)U(rng) + 1e-9 * (double)U(rng);
+    }
+
+    int64_t checked = 0, odd_m = 0;
+    if (t.gs_in_update) {
+        // the group-sum pass covers exactly the groups of more than two
+        // copies: gather-scatter blocks gs_blk_multi onwards
+        int64_t n_multi = 0;
+        for (int c = 0; c < t.gs.ncls; ++c) {
+            CHECK((t.gs.blk0[c] >= t.gs_blk_multi) == (t.gs.M[c] > 2),
+                  "class %d (M = %d) on the wrong side of block %lld", c, t.gs.M[c],
+                  (long long)t.gs_blk_multi);
+            if (t.gs.M[c] > 2) n_multi += t.gs.ng[c];
+        }
+        CHECK(n_multi == t.n_groups_multi, "%lld groups with m > 2, tables say %lld",
+              (long long)n_multi, (long long)t.n_groups_multi);
+        // that pass on the host: ascending-order sums, class by class
+        std::vector<float> gs32;
+        std::vector<double> gs64;
+        for (int c = 0; c < t.gs.ncls; ++c) {
+            const int M = t.gs.M[c];
+            if (M <= 2) continue;
+            for (int64_t g = 0; g < t.gs.ng[c]; ++g) {
+                const int32_t *ix = t.gs_idx.data() + t.gs.io[c] + g * M;
+                float s32 = w32[ix[0]];
+                double s64 = w64[ix[0]];
+                for (int q = 1; q < M; ++q) {
+                    s32 += w32[ix[q]];
+                    s64 += w64[ix[q]];
+                }
+                gs32.push_back(s32);
+                gs64.push_back(s64);
+            }
+        }
+        const sem::vecb::GatherMap gm{t.slot.data(), t.slink.data(), t.p3_magic, t.p3_shift, P3,
+                                      t.S};
+        for (l = 0; l < n; ++l) {
+            const uint32_t e = (uint32_t)(((uint64_t)l * t.p3_magic) >> t.p3_shift);
+            CHECK(e == (uint64_t)(l / P3), "element %u by multiply-shift, %lld by division", e,
+                  (long long)(l / P3));
+            const int sl = t.slot[l - (int64_t)e * P3];
+            CHECK(sl >= -1 && sl < t.S, "slot %d", sl);
+            CHECK((size_t)e * t.S + (sl > 0 ? sl : 0) < t.slink.size(), "gather table index");
+            const int32_t lk = sem::vecb::node_link((uint32_t)l, gm, t.slot.data());
+            const uint8_t code = t.mcode[l];
+            const int m = code & sem::kMultMask;
+            const std::vector<int64_t> &cp = copies[gid[l]];
+            CHECK((int)cp.size() == m, "multiplicity %d, copies %zu", m, cp.size());
+            if (m != 1 && m != 2 && m != 4 && m != 8) ++odd_m;
+            if (m >= 2) CHECK(sl >= 0, "shared point not on the element surface");
+            if (m == 2) {
+                const int64_t other = cp[0] == l ? cp[1] : cp[0];
+                CHECK(lk == other, "partner %d, expected %lld", lk, (long long)other);
+            }
+            if (m > 2) CHECK(lk >= 0 && lk < n_multi, "group rank %d", lk);
+            // the gathered value against the ascending-order sum of the copies
+            float s32 = w32[cp[0]];
+            double s64 = w64[cp[0]];
+            for (size_t q = 1; q < cp.size(); ++q) {
+                s32 += w32[cp[q]];
+                s64 += w64[cp[q]];
+            }
+            if (code & sem::kDirichletBit) {
+                s32 = 0.f;
+                s64 = 0.0;
+            }
+            const float *src32 = sem::vecb::gather_source<float>(w32.data(), gs32.data(), code,
+                                                                 lk, l);
+            const double *src64 = sem::vecb::gather_source<double>(w64.data(), gs64.data(), code,
+                                                                   lk, l);
+            const float g32 = sem::vecb::copies_sum<float>(w32[l], code, *src32);
+            const double g64 = sem::vecb::copies_sum<double>(w64[l], code, *src64);
+            CHECK(std::memcmp(&g32, &s32, 4) == 0, "fp32 gather %a, expected %a", g32, s32);
+            CHECK(std::memcmp(&g64, &s64, 8) == 0, "fp64 gather %a, expected %a", g64, s64);
+            ++checked;
+        }
+    }
+    std::printf("gs_in_update=%d checked=%lld odd_m=%lld\n", t.gs_in_update ? 1 : 0,
+                (long long)checked, (long long)odd_m);
+    return 0;
+}

@@ -157,3 +157,40 @@ def test_mixed_precision_reaches_1e10(geom):
     xs, _, _ = pr.cg(bh, tol=1e-12, max_iter=20000)
     assert rel_norm(xh, xs) < 1e-8
     gm.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cg_gather_in_update_modes(prec):
+    """A conforming mesh gathers the shared sums inside the CG update (also
+    with a group of 3 copies); a scatter map that ties two element-interior
+    nodes (valid, not conforming) takes the separate gather-scatter pass.
+    All follow the oracle."""
+    import dataclasses
+
+    import torch
+    import paper_2108_12188_amd as sem
+    fp64 = prec == "fp64"
+    mesh = box_mesh(3, 2, 2, 4, perturb=0.1, seed=2111)
+    P = mesh.N + 1
+    centre = 2 + P * (2 + P * 2)
+    gid = mesh.glob_id.copy()
+    gid[1, centre] = gid[0, centre]
+    tied = dataclasses.replace(mesh, glob_id=gid)
+    # one copy of a face node moved into another face node's group: m = 3
+    gid3 = mesh.glob_id.copy()
+    gid3[5, P * (2 + P * 2)] = gid3[0, mesh.N + P * (2 + P * 2)]
+    odd = dataclasses.replace(mesh, glob_id=gid3)
+    for m, expect in ((mesh, 1), (odd, 1), (tied, 0)):
+        say(f"cg {prec} gather-in-update={expect}")
+        pr = oracle.Problem(m)
+        gm = sem.Mesh.from_box(m, g_fp64=fp64, g_fp32=not fp64)
+        assert gm.info()["gs_in_update"] == expect
+        b = random_global_rhs(m, seed=12188)
+        xo, _, hist = pr.cg(b, fixed=12)
+        x, res = gm.cg_solve(to_dev(b, torch.float64 if fp64 else torch.float32),
+                             prec=sem.FP64 if fp64 else sem.FP32, fixed_iters=12, history=13)
+        assert res["iters"] == 12
+        np.testing.assert_allclose(res["hist_rho"][:13], hist["rho"][:13],
+                                   rtol=1e-11 if fp64 else 1e-4)
+        assert rel_norm(to_host(x), xo) < (1e-11 if fp64 else 1e-4)
+        gm.close()
