@@ -98,12 +98,17 @@ AxShape ax_shape(int N, bool fp64, bool otf, int epb_override) {
     const size_t tsz = fp64 ? 8 : 4;
     int epb = epb_override > 0 ? epb_override : g_epb[otf ? 1 : 0][fp64 ? 1 : 0][N].load();
     if (epb <= 0) epb = fp64 ? kEpb64[N] : kEpb32[N];
-    // clamp to the kernel limits
-    while (epb > 1 && (((epb * P2 + 63) / 64) * 64 > 512 || 2 * tsz * epb * P3 > 65536)) --epb;
+    // clamp to the kernel limits (FP32 CG-fused tiles of odd N also stage
+    // the next tile's r, p and vertices in LDS)
+    const bool staged = !fp64 && P3 % 4 == 0;
+    auto lds = [&](int q) {
+        return 2 * tsz * (size_t)q * P3 + (staged ? 8 * (size_t)q * P3 + 96 * (size_t)q : 0);
+    };
+    while (epb > 1 && (((epb * P2 + 63) / 64) * 64 > 512 || lds(epb) > 65536)) --epb;
     AxShape s;
     s.epb = epb;
     s.threads = ((epb * P2 + 63) / 64) * 64;
-    s.lds = 2 * tsz * (size_t)epb * P3;
+    s.lds = lds(epb);
     return s;
 }
 

@@ -144,6 +144,57 @@ __device__ __forceinline__ double block_sum(double v) {
 template <typename T>
 constexpr int ax_min_waves() { return (sizeof(T) == 4 && kP <= 8) ? 4 : 1; }
 
+// FP32 CG-fused tiles stage the next tile's r, p and vertices in LDS with
+// gfx950's direct global-to-LDS loads (16 bytes per lane, no registers
+// held while in flight), issued while the current tile computes.  Needs
+// 16-byte aligned element blocks: P^3 a multiple of 4 (odd N).
+template <typename T, bool FUSED>
+__host__ __device__ constexpr bool ax_dma() {
+    return FUSED && sizeof(T) == 4 && (kP * kP * kP) % 4 == 0;
+}
+
+// Dynamic LDS of a block: the two operator tiles, plus the staging buffers.
+template <typename T, bool OTF, bool FUSED>
+__host__ __device__ constexpr size_t ax_lds_bytes(int epb) {
+    constexpr size_t P3 = (size_t)kP * kP * kP;
+    return 2 * sizeof(T) * epb * P3 +
+           (ax_dma<T, FUSED>() ? 2 * sizeof(float) * epb * P3 + (OTF ? 24 * 4 * (size_t)epb : 0)
+                               : 0);
+}
+
+// s_waitcnt immediates (gfx9 encoding): vmcnt(0) alone, lgkmcnt(0) alone
+constexpr int kWaitVmcnt0 = 0x0F70;
+constexpr int kWaitLgkmcnt0 = 0xC07F;
+
+// Barrier for LDS traffic only: the wave's own LDS accesses complete
+// before it, but global loads and stores -- and the staging loads, which
+// write LDS -- keep flying across it (a fenced __syncthreads would wait for
+// all of them).  The memory clobber keeps the compiler from moving any
+// memory access across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkmcnt0);
+    __asm__ volatile("s_barrier" ::: "memory");
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// The block copies nf floats (a multiple of 4; src and dst 16-byte aligned)
+// from global memory to LDS: every wave moves 64 x 16 bytes per
+// instruction, lane q of a wave landing at the wave's (uniform) LDS base +
+// 16 q.  Completion is tracked by vmcnt.
+__device__ __forceinline__ void dma_to_lds(const float *src, float *dst, int nf) {
+    const int pieces = nf >> 2;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nwave = (int)((blockDim.x + 63) >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    for (int q0 = wave * 64; q0 < pieces; q0 += nwave * 64) {
+        if (q0 + lane < pieces)
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(src + 4 * (q0 + lane)),
+                                             (lds_void_t *)(dst + 4 * q0), 16, 0, 0);
+    }
+}
+
 // Tiles vb, vb + vgrid, vb + 2 vgrid, ... of one problem; in the fused mode
 // the block's partial goes to a.partial[vb].  Every thread of the block
 // calls it.
@@ -151,9 +202,14 @@ template <typename T, bool OTF, bool FUSED>
 __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk, int64_t ntiles,
                                         int64_t vb, int64_t vgrid) {
     constexpr int P = kP, P2 = P * P, P3 = P2 * P;
+    constexpr bool kDma = ax_dma<T, FUSED>();
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *const sA = reinterpret_cast<T *>(lds_raw);
     T *const sB = sA + a.epb * P3;
+    // staging (kDma): r and p of a tile, then its vertices
+    float *const sR = reinterpret_cast<float *>(sB + a.epb * P3);
+    float *const sP = sR + a.epb * P3;
+    float *const sV = sP + a.epb * P3;
 
     if constexpr (FUSED) {
         if (a.st->stop) return;          // uniform: the whole grid exits
@@ -178,6 +234,28 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
     }
     T beta = T(0);
     if constexpr (FUSED) beta = (T)a.st->beta;
+    // per-lane GLL abscissae and weight product of the column
+    T xi_i = T(0), eta_j = T(0), wij = T(0);
+    if constexpr (OTF) {
+        xi_i = a.xi[i];
+        eta_j = a.xi[j];
+        wij = a.wq[i] * a.wq[j];
+    }
+
+    // stage tile tl (its valid elements only)
+    auto stage = [&](int64_t tl) {
+        if constexpr (kDma) {
+            const int64_t e0 = tl * a.epb;
+            const int nval = (int)(a.E - e0 < a.epb ? a.E - e0 : a.epb);
+            dma_to_lds(reinterpret_cast<const float *>(a.u) + e0 * P3, sR, nval * P3);
+            dma_to_lds(reinterpret_cast<const float *>(a.p) + e0 * P3, sP, nval * P3);
+            if constexpr (OTF)
+                dma_to_lds(reinterpret_cast<const float *>(a.vert) + e0 * 24, sV, nval * 24);
+        }
+    };
+    if constexpr (kDma) {
+        if (vb < ntiles) stage(vb);
+    }
 
     double acc = 0.0;
     // a tile is `epb` consecutive elements; the grid strides over tiles
@@ -185,10 +263,22 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         const int64_t e = tile * a.epb + el;
         const bool valid = (el < a.epb) && (e < a.E);
         const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
+        if constexpr (kDma) {
+            // this tile's staged data has landed (every wave's share)
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            lds_barrier();
+        }
 
         T uc[P];
         if (valid) {
-            if constexpr (FUSED) {
+            if constexpr (kDma) {
+                const float *const rr = sR + el * P3 + col;
+                const float *const pp = sP + el * P3 + col;
+#pragma unroll
+                for (int k = 0; k < P; ++k) uc[k] = rr[k * P2] + beta * pp[k * P2];
+#pragma unroll
+                for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+            } else if constexpr (FUSED) {
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     const T r = a.u[base + k * P2];
@@ -208,7 +298,11 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         ColumnGeom<T> cg;
         if constexpr (OTF) {
             if (valid) {
-                cg = column_geom<T>(a.vert + e * 24, a.xi[i], a.xi[j], a.wq[i] * a.wq[j]);
+                if constexpr (kDma)
+                    cg = column_geom<T>(reinterpret_cast<const T *>(sV) + el * 24, xi_i, eta_j,
+                                        wij);
+                else
+                    cg = column_geom<T>(a.vert + e * 24, xi_i, eta_j, wij);
             }
         }
         constexpr bool kPre = !OTF && prefetch_g<T>();
@@ -222,7 +316,11 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                     for (int k = 0; k < P; ++k) gq[c][k] = Ge[c * P3 + k * P2];
             }
         }
-        __syncthreads();
+        lds_barrier();
+        // every thread is done with the staged tile: stage the next one
+        if constexpr (kDma) {
+            if (tile + vgrid < ntiles) stage(tile + vgrid);
+        }
 
         T vsr[P], vtr[P];
         if (valid) {
@@ -268,12 +366,12 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                 vtr[k] = vt;
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (valid) {
 #pragma unroll
             for (int k = 0; k < P; ++k) sa[k * P2 + col] = vsr[k];
         }
-        __syncthreads();
+        lds_barrier();
 
         if (valid) {
 #pragma unroll
@@ -289,7 +387,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                 a.w[base + k * P2] = wv;
             }
         }
-        __syncthreads();   // the next tile overwrites the LDS tile
+        lds_barrier();   // the next tile overwrites the LDS tile
     }
     if constexpr (FUSED) {
         const double s = block_sum(acc);
@@ -329,9 +427,8 @@ BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
 
 template <typename T, bool OTF, bool FUSED>
 void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s) {
-    constexpr int P3 = kP * kP * kP;
     const int threads = ((a.epb * kP * kP + 63) / 64) * 64;
-    const size_t lds = 2 * sizeof(T) * (size_t)a.epb * P3;
+    const size_t lds = ax_lds_bytes<T, OTF, FUSED>(a.epb);
     const int64_t ntiles = (a.E + a.epb - 1) / a.epb;
     hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED>), dim3((unsigned)grid), dim3(threads), lds, s, a,
                        bk, ntiles);
@@ -360,16 +457,16 @@ template <typename T>
 static void ax_batch_entry(bool otf, const AxArgs<T> *descs, const int2 *blk, int64_t nblk,
                            int epb, const double *D, const double *xi, const double *w,
                            hipStream_t s) {
-    constexpr int P3 = kP * kP * kP;
     const BasisK<T> bk = make_basis<T>(D, xi, w);
     const int threads = ((epb * kP * kP + 63) / 64) * 64;
-    const size_t lds = 2 * sizeof(T) * (size_t)epb * P3;
+    const size_t lds_otf = ax_lds_bytes<T, true, true>(epb);
+    const size_t lds_pre = ax_lds_bytes<T, false, true>(epb);
     if (otf)
-        hipLaunchKernelGGL((ax_batch_kernel<T, true>), dim3((unsigned)nblk), dim3(threads), lds, s,
-                           descs, blk, bk);
+        hipLaunchKernelGGL((ax_batch_kernel<T, true>), dim3((unsigned)nblk), dim3(threads),
+                           lds_otf, s, descs, blk, bk);
     else
-        hipLaunchKernelGGL((ax_batch_kernel<T, false>), dim3((unsigned)nblk), dim3(threads), lds, s,
-                           descs, blk, bk);
+        hipLaunchKernelGGL((ax_batch_kernel<T, false>), dim3((unsigned)nblk), dim3(threads),
+                           lds_pre, s, descs, blk, bk);
 }
 
 void SEM_CAT3(ax_batch_order_, SEM_ORDER, _f32)(bool otf, const AxArgs<float> *descs,

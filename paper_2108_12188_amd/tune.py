@@ -25,9 +25,14 @@ _GEOM = {"pre": 0, "otf": 1}
 def candidates(N: int, fp64: bool):
     P2, P3 = (N + 1) ** 2, (N + 1) ** 3
     tsz = 8 if fp64 else 4
+    staged = not fp64 and P3 % 4 == 0     # FP32 fused tiles also stage r, p, vertices
+
+    def lds(q):
+        return 2 * tsz * q * P3 + (8 * q * P3 + 96 * q if staged else 0)
+
     out = []
     epb = 1
-    while ((epb * P2 + 63) // 64) * 64 <= 512 and 2 * tsz * epb * P3 <= 65536:
+    while ((epb * P2 + 63) // 64) * 64 <= 512 and lds(epb) <= 65536:
         out.append(epb)
         epb += 1
     return out
