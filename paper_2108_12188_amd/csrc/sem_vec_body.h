@@ -145,29 +145,47 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ x,
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
-    for (int64_t q = tid; q < n4; q += stride) {
-        const uint32_t l0 = (uint32_t)(4 * q);
-        int32_t lk[4];
+    // two packs (q, q + stride) per step, every load of both issued before
+    // any result is used; the sum of r^2/m still runs pack by pack in the
+    // thread's order q, q + stride, q + 2 stride, ...
+    for (int64_t q = tid; q < n4; q += 2 * stride) {
+        const bool two = q + stride < n4;
+        const int64_t qq[2] = {q, two ? q + stride : q};
+        int32_t lk[2][4];
+        Pack4<T> xv[2], rv[2], pv[2], wv[2];
+        Code4 mv[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) lk[t] = node_link(l0 + t, gm, slot);
-        Pack4<T> xv = reinterpret_cast<const Pack4<T> *>(x)[q];
-        Pack4<T> rv = reinterpret_cast<const Pack4<T> *>(r)[q];
-        const Pack4<T> pv = reinterpret_cast<const Pack4<T> *>(p)[q];
-        const Pack4<T> wv = reinterpret_cast<const Pack4<T> *>(w)[q];
-        const Code4 mv = reinterpret_cast<const Code4 *>(mcode)[q];
-        T src[4];
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t l0 = (uint32_t)(4 * qq[h]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) src[t] = *gather_source<T>(w, gsum, mv.v[t], lk[t], l0 + t);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const T wg = copies_sum<T>(wv.v[t], mv.v[t], src[t]);
-            xv.v[t] += a * pv.v[t];
-            rv.v[t] -= a * wg;
-            const double rd = (double)rv.v[t];
-            acc += rd * rd * cw[mv.v[t]];
+            for (int t = 0; t < 4; ++t) lk[h][t] = node_link(l0 + t, gm, slot);
+            xv[h] = reinterpret_cast<const Pack4<T> *>(x)[qq[h]];
+            rv[h] = reinterpret_cast<const Pack4<T> *>(r)[qq[h]];
+            pv[h] = reinterpret_cast<const Pack4<T> *>(p)[qq[h]];
+            wv[h] = reinterpret_cast<const Pack4<T> *>(w)[qq[h]];
+            mv[h] = reinterpret_cast<const Code4 *>(mcode)[qq[h]];
         }
-        reinterpret_cast<Pack4<T> *>(x)[q] = xv;
-        reinterpret_cast<Pack4<T> *>(r)[q] = rv;
+        T src[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                src[h][t] = *gather_source<T>(w, gsum, mv[h].v[t], lk[h][t],
+                                              (int64_t)(4 * qq[h] + t));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !two) break;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T wg = copies_sum<T>(wv[h].v[t], mv[h].v[t], src[h][t]);
+                xv[h].v[t] += a * pv[h].v[t];
+                rv[h].v[t] -= a * wg;
+                const double rd = (double)rv[h].v[t];
+                acc += rd * rd * cw[mv[h].v[t]];
+            }
+            reinterpret_cast<Pack4<T> *>(x)[qq[h]] = xv[h];
+            reinterpret_cast<Pack4<T> *>(r)[qq[h]] = rv[h];
+        }
     }
     for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
         const uint8_t c = mcode[q];
