@@ -9,8 +9,10 @@
 // and two modes:
 //   * Plain: w = A_L u;
 //   * CgFused: the p-update of Algorithm 1 is the prologue (p <- r + beta p,
-//     the loop fusion of Sec. 5.1) and the block's FP64 partial of
-//     sum_l p_l w_l is reduced.  Because p is continuous (p = Q p_g), zero on
+//     the loop fusion of Sec. 5.1), the block's FP64 partial of
+//     sum_l p_l w_l is reduced, and (optionally) the values of the edge and
+//     corner nodes are also written to a compact per-element array for the
+//     group sums of the gather-scatter.  Because p is continuous (p = Q p_g), zero on
 //     the Dirichlet points, and the weights of every group add up to one,
 //     <p, mask(QQ^T w), c> = p_g^T Q^T w = sum_l p_l w_l over the local, not
 //     yet gathered or masked w: the whole alpha reduction of Algorithm 1
@@ -234,6 +236,11 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
     }
     T beta = T(0);
     if constexpr (FUSED) beta = (T)a.st->beta;
+    // edge-array slots of the column (edge_slot): base ecb (-1 off the
+    // border) holds k = 0, ecb + 1 holds k = N, and corner columns keep
+    // k = 1 .. N-1 at ecb + 1 + k
+    const int ecb = edge_column_base(kOrder, i, j);
+    const bool ecorner = (i == 0 || i == P - 1) && (j == 0 || j == P - 1);
     // per-lane GLL abscissae and weight product of the column
     T xi_i = T(0), eta_j = T(0), wij = T(0);
     if constexpr (OTF) {
@@ -263,6 +270,9 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         const int64_t e = tile * a.epb + el;
         const bool valid = (el < a.epb) && (e < a.E);
         const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
+        T *const wep = (FUSED && a.wedge && valid && ecb >= 0)
+                           ? a.wedge + e * edge_slots(kOrder) + ecb
+                           : nullptr;
         if constexpr (kDma) {
             // this tile's staged data has landed (every wave's share)
             __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
@@ -383,7 +393,12 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                     wv += DjT[l] * sa[k * P2 + l * P + i];
                     wv += bk.D[l * P + k] * vtr[l];
                 }
-                if constexpr (FUSED) acc += (double)uc[k] * (double)wv;
+                if constexpr (FUSED) {
+                    acc += (double)uc[k] * (double)wv;
+                    // compact copy of the edge and corner nodes
+                    if (wep && (k == 0 || k == P - 1 || ecorner))
+                        wep[k == 0 ? 0 : (k == P - 1 ? 1 : 1 + k)] = wv;
+                }
                 a.w[base + k * P2] = wv;
             }
         }

@@ -32,7 +32,7 @@ namespace {
 void ws_free(Workspace *ws) {
     if (!ws) return;
     for (auto &kv : ws->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->gsum, ws->part_ax, ws->part_vec,
+    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->gsum, ws->wedge, ws->part_ax, ws->part_vec,
                    ws->st, ws->hist, ws->dval};
     for (void *q : dev)
         if (q) (void)hipFree(q);
@@ -70,6 +70,7 @@ Workspace *ws_create(const Mesh &m, bool fp64) {
         ws->w = ws_alloc<char>(*ws, nv);
         ws->b = ws_alloc<char>(*ws, nv);
         if (m.gs_in_update) ws->gsum = ws_alloc<char>(*ws, (size_t)m.n_groups_multi * tsz);
+        if (m.gsum_wedge) ws->wedge = ws_alloc<char>(*ws, (size_t)m.E * edge_slots(m.N) * tsz);
         // the smallest shape (1 element per block) bounds the Ax partial count
         ws->cap_ax = m.E;
         ws->cap_vec = vec_blocks(m.n);
@@ -109,53 +110,32 @@ void ensure_hist(Workspace &ws, int len) {
 }
 
 // ---------------------------------------------------------------------------
-// one CG iteration (three kernels) on stream s
+// one CG iteration (three steps) on stream s; ev (may be null): events
+// recorded before and after each step
 // ---------------------------------------------------------------------------
 template <typename T>
-void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s) {
+void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
+                       hipEvent_t *ev = nullptr) {
     T *x = static_cast<T *>(ws.x), *r = static_cast<T *>(ws.r);
     T *p = static_cast<T *>(ws.p), *w = static_cast<T *>(ws.w);
+    T *gsum = static_cast<T *>(ws.gsum), *wedge = static_cast<T *>(ws.wedge);
     AxArgs<T> a{};
     a.u = r;
     a.p = p;
     a.w = w;
     a.st = ws.st;
     a.partial = ws.part_ax;
+    a.wedge = m.gsum_wedge ? wedge : nullptr;
+    if (ev) SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
+    if (ev) SEM_HIP(hipEventRecord(ev[1], s));
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
-    if (m.gs_in_update) {
-        T *gsum = static_cast<T *>(ws.gsum);
-        launch_group_sums_cg<T>(m, w, gsum, ws.st, ws.part_ax, (int)nax, s);
-        launch_update_gather<T>(m, x, r, p, w, gsum, ws.st, ws.part_vec, s);
-    } else {
-        launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
-        launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
-    }
-}
-
-// One iteration with an event before and after each of its three kernels.
-template <typename T>
-void enqueue_iteration_timed(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
-                             hipEvent_t *ev) {
-    T *x = static_cast<T *>(ws.x), *r = static_cast<T *>(ws.r);
-    T *p = static_cast<T *>(ws.p), *w = static_cast<T *>(ws.w);
-    AxArgs<T> a{};
-    a.u = r;
-    a.p = p;
-    a.w = w;
-    a.st = ws.st;
-    a.partial = ws.part_ax;
-    SEM_HIP(hipEventRecord(ev[0], s));
-    launch_ax<T>(m, otf, AxMode::CgFused, a, s);
-    SEM_HIP(hipEventRecord(ev[1], s));
-    const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
-    T *gsum = static_cast<T *>(ws.gsum);
-    if (m.gs_in_update) launch_group_sums_cg<T>(m, w, gsum, ws.st, ws.part_ax, (int)nax, s);
+    if (m.gs_in_update) launch_group_sums_cg<T>(m, w, wedge, gsum, ws.st, ws.part_ax, (int)nax, s);
     else launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
-    SEM_HIP(hipEventRecord(ev[2], s));
+    if (ev) SEM_HIP(hipEventRecord(ev[2], s));
     if (m.gs_in_update) launch_update_gather<T>(m, x, r, p, w, gsum, ws.st, ws.part_vec, s);
     else launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
-    SEM_HIP(hipEventRecord(ev[3], s));
+    if (ev) SEM_HIP(hipEventRecord(ev[3], s));
 }
 
 struct KernelTimes {
@@ -172,7 +152,7 @@ void run_chunk_timed(const Mesh &m, Workspace &ws, bool otf, int chunk, int iter
         SEM_HIP(hipEventCreate(&e));
         ws.tev.push_back(e);
     }
-    for (int c = 0; c < chunk; ++c) enqueue_iteration_timed<T>(m, ws, otf, s, &ws.tev[4 * c]);
+    for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, s, &ws.tev[4 * c]);
     SEM_HIP(hipMemcpyAsync(ws.h_st, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
     const int done = std::min(chunk, ws.h_st->iter - iter_before);

@@ -28,6 +28,7 @@ struct Workspace {
     int device = 0;
     void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *b = nullptr;
     void *gsum = nullptr;           // sums of the groups with m > 2 (gather in the update)
+    void *wedge = nullptr;          // operator's copy of the edge and corner nodes
     double *part_ax = nullptr, *part_vec = nullptr;
     int64_t cap_ax = 0;
     int cap_vec = 0;

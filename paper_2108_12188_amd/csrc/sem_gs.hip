@@ -9,6 +9,7 @@
 // first local index, which keeps neighbouring lanes on neighbouring faces.
 #include "sem_gs_body.h"
 #include "sem_internal.h"
+#include "sem_vec_body.h"
 
 namespace sem {
 namespace {
@@ -24,26 +25,41 @@ __device__ __forceinline__ int64_t logical_block(int64_t b, int64_t nb_phys) {
 }
 
 // Logical blocks lb0 .. lb0 + nb_logical - 1.  st (may be null): a stopped
-// CG state makes the whole grid exit at once.
+// CG state makes the whole grid exit at once.  With part_ax, the grid has
+// one more block, which forms alpha from the operator's partials (Algorithm
+// 1; it needs none of this kernel's results).
 template <typename T>
 __global__ void __launch_bounds__(kGsThreads)
 gs_kernel(const GsClasses cls, int64_t lb0, int64_t nb_logical, const int32_t *__restrict__ idx,
-          T *__restrict__ w, const CgState *st) {
+          T *__restrict__ w, CgState *st, const double *part_ax, int64_t n_ax) {
     if (st && st->stop) return;
-    const int64_t b = logical_block(blockIdx.x, gridDim.x);
+    int64_t nb = gridDim.x;
+    if (part_ax) {
+        if (blockIdx.x == gridDim.x - 1) {
+            vecb::finalize_alpha_body(st, part_ax, n_ax);
+            return;
+        }
+        --nb;
+    }
+    const int64_t b = logical_block(blockIdx.x, nb);
     if (b < nb_logical) gs_logical_block<T>(cls, lb0 + b, idx, w);
 }
 
 // Group sums of the classes with M > 2: logical blocks lb0 .. lb0 +
-// nb_logical - 1 of the gather-scatter numbering.
+// nb_logical - 1 of the gather-scatter numbering; the last block forms
+// alpha from the operator's partials.
 template <typename T>
 __global__ void __launch_bounds__(kGsThreads)
 group_sums_kernel(const GsClasses cls, int64_t lb0, int64_t nb_logical,
-                  const int32_t *__restrict__ idx, const T *__restrict__ w, T *__restrict__ out,
-                  const CgState *st) {
+                  const int32_t *__restrict__ idx, int64_t io0, const T *__restrict__ src,
+                  T *__restrict__ out, CgState *st, const double *part_ax, int64_t n_ax) {
     if (st->stop) return;
-    const int64_t b = logical_block(blockIdx.x, gridDim.x);
-    if (b < nb_logical) gs_sums_logical_block<T>(cls, lb0 + b, idx, w, out);
+    if (blockIdx.x == gridDim.x - 1) {
+        vecb::finalize_alpha_body(st, part_ax, n_ax);
+        return;
+    }
+    const int64_t b = logical_block(blockIdx.x, gridDim.x - 1);
+    if (b < nb_logical) gs_sums_logical_block<T>(cls, lb0 + b, idx, io0, src, out);
 }
 
 template <typename T>
@@ -68,7 +84,8 @@ void launch_gs(const Mesh &m, T *w, hipStream_t s) {
     if (m.n_groups == 0) return;
     const int nb = gs_cg_blocks(m);
     hipLaunchKernelGGL((gs_kernel<T>), dim3(nb), dim3(kGsThreads), 0, s, m.gs, (int64_t)0,
-                       gs_logical_blocks(m), m.gs_idx, w, (const CgState *)nullptr);
+                       gs_logical_blocks(m), m.gs_idx, w, (CgState *)nullptr,
+                       (const double *)nullptr, (int64_t)0);
     check_hip(hipGetLastError(), "gs kernel launch");
 }
 
@@ -85,23 +102,29 @@ void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, in
                   hipStream_t s) {
     const int64_t nlb = gs_logical_blocks(m);
     if (nlb > 0) {
-        hipLaunchKernelGGL((gs_kernel<T>), dim3(gs_phys_blocks(nlb)), dim3(kGsThreads), 0, s,
-                           m.gs, (int64_t)0, nlb, m.gs_idx, w, (const CgState *)st);
+        hipLaunchKernelGGL((gs_kernel<T>), dim3(gs_phys_blocks(nlb) + 1), dim3(kGsThreads), 0, s,
+                           m.gs, (int64_t)0, nlb, m.gs_idx, w, st, ax_partial,
+                           (int64_t)n_ax_partial);
         check_hip(hipGetLastError(), "gs/cg kernel launch");
+    } else {
+        launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
     }
-    launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
 }
 
 template <typename T>
-void launch_group_sums_cg(const Mesh &m, const T *w, T *gsum, CgState *st,
+void launch_group_sums_cg(const Mesh &m, const T *w, const T *wedge, T *gsum, CgState *st,
                           const double *ax_partial, int n_ax_partial, hipStream_t s) {
     const int64_t nlb = gs_logical_blocks(m) - m.gs_blk_multi;
     if (nlb > 0) {
-        hipLaunchKernelGGL((group_sums_kernel<T>), dim3(gs_phys_blocks(nlb)), dim3(kGsThreads), 0,
-                           s, m.gs, m.gs_blk_multi, nlb, m.gs_idx, w, gsum, (const CgState *)st);
+        const bool compact = m.gsum_wedge;
+        hipLaunchKernelGGL((group_sums_kernel<T>), dim3(gs_phys_blocks(nlb) + 1),
+                           dim3(kGsThreads), 0, s, m.gs, m.gs_blk_multi, nlb,
+                           compact ? m.wedge_idx : m.gs_idx, compact ? m.wedge_io0 : (int64_t)0,
+                           compact ? wedge : w, gsum, st, ax_partial, (int64_t)n_ax_partial);
         check_hip(hipGetLastError(), "group sums kernel launch");
+    } else {
+        launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
     }
-    launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
 }
 
 template void launch_gs<float>(const Mesh &, float *, hipStream_t);
@@ -112,9 +135,10 @@ template void launch_gs_cg<float>(const Mesh &, float *, CgState *, const double
                                   hipStream_t);
 template void launch_gs_cg<double>(const Mesh &, double *, CgState *, const double *, int,
                                    hipStream_t);
-template void launch_group_sums_cg<float>(const Mesh &, const float *, float *, CgState *,
-                                          const double *, int, hipStream_t);
-template void launch_group_sums_cg<double>(const Mesh &, const double *, double *, CgState *,
-                                           const double *, int, hipStream_t);
+template void launch_group_sums_cg<float>(const Mesh &, const float *, const float *, float *,
+                                          CgState *, const double *, int, hipStream_t);
+template void launch_group_sums_cg<double>(const Mesh &, const double *, const double *,
+                                           double *, CgState *, const double *, int,
+                                           hipStream_t);
 
 }  // namespace sem

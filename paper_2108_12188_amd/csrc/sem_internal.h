@@ -19,6 +19,33 @@ constexpr uint8_t kDirichletBit = 0x80;
 constexpr uint8_t kMultMask = 0x7F;
 constexpr int kMaxP = kMaxOrder + 1;
 
+// Edge and corner nodes of an element's P^3 block (on two or three of its
+// faces): 12 N - 4 of them, numbered column by column (i, j on the border
+// of the face square): every border column starts at its base with its
+// k = 0 node, then k = N; the 4 corner columns (bases 0, P, 2P, 3P) follow
+// with k = 1 .. N-1, the other border columns (bases 4P + 2s) have no more.
+// -1 for other nodes.
+__host__ __device__ inline int edge_slots(int N) { return 12 * N - 4; }
+__host__ __device__ inline int edge_column_base(int N, int i, int j) {
+    const int P = N + 1;
+    const bool bi = i == 0 || i == N, bj = j == 0 || j == N;
+    if (bi && bj) return ((i == N) + 2 * (j == N)) * P;
+    if (!(bi || bj)) return -1;
+    int s;
+    if (j == 0) s = i - 1;
+    else if (j == N) s = (P - 2) + i - 1;
+    else if (i == 0) s = 2 * (P - 2) + j - 1;
+    else s = 3 * (P - 2) + j - 1;
+    return 4 * P + 2 * s;
+}
+__host__ __device__ inline int edge_slot(int N, int i, int j, int k) {
+    const int cb = edge_column_base(N, i, j);
+    if (cb < 0) return -1;
+    if (k == 0 || k == N) return cb + (k == N);
+    const bool corner = (i == 0 || i == N) && (j == 0 || j == N);
+    return corner ? cb + 1 + k : -1;
+}
+
 // ---------------------------------------------------------------------------
 // Errors
 // ---------------------------------------------------------------------------
@@ -107,6 +134,14 @@ struct Mesh {
     int64_t n_groups_multi = 0, gs_blk_multi = 0;
     int16_t *surf_slot = nullptr;  // [P3]
     int32_t *slink = nullptr;      // [E][S]
+    // When every copy of a group with m > 2 is an edge or corner node of its
+    // element (edge_slot), the CG operator also writes those nodes' values
+    // to a compact [E][edge_slots(N)] array and the group sums read it:
+    // wedge_idx lists, for the groups with m > 2 in gs_idx's layout from
+    // offset wedge_io0, the copies' positions e * edge_slots(N) + slot.
+    bool gsum_wedge = false;
+    int64_t wedge_io0 = 0;
+    int32_t *wedge_idx = nullptr;
     uint32_t p3_magic = 0;
     int p3_shift = 0;
     Basis<float> b32;
@@ -134,6 +169,9 @@ struct HostTables {
     int S = 0;                      // surface nodes per element
     int64_t n_groups_multi = 0;     // groups with more than two copies
     int64_t gs_blk_multi = 0;       // their first gather-scatter block
+    bool gsum_wedge = false;        // every copy of those groups an edge or corner node
+    int64_t wedge_io0 = 0;          // gs_idx offset of the first such group
+    std::vector<int32_t> wedge_idx; // copies' positions in the compact edge array
     std::vector<int16_t> slot;      // [P3] surface slot or -1
     std::vector<int32_t> slink;     // [E][S] (only when gs_in_update)
     uint32_t p3_magic = 0;
@@ -170,6 +208,8 @@ struct AxArgs {
     CgState *st;                // CgFused: beta, stop flag
     double *partial;            // CgFused: one FP64 partial of sum p w per block
     int64_t vgrid;              // batched launches: this problem's own grid size
+    T *wedge;                   // CgFused, may be null: w of the edge and corner
+                                // nodes, [E][edge_slots(N)]
 };
 
 // Launch configuration chosen for an order (threads, elements per block,
@@ -207,10 +247,11 @@ template <typename T>
 void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, int n_ax_partial,
                   hipStream_t s);
 // The same for the gather in the update: gsum[k] = sum of the copies of the
-// k-th group with m > 2 (ascending local index; w is not modified), then
-// alpha.
+// k-th group with m > 2 (ascending local index; read from wedge, the
+// operator's compact copy of the edge and corner nodes, when m.gsum_wedge,
+// else from w; neither is modified), and alpha.
 template <typename T>
-void launch_group_sums_cg(const Mesh &m, const T *w, T *gsum, CgState *st,
+void launch_group_sums_cg(const Mesh &m, const T *w, const T *wedge, T *gsum, CgState *st,
                           const double *ax_partial, int n_ax_partial, hipStream_t s);
 int gs_cg_blocks(const Mesh &m);
 int64_t gs_logical_blocks(const Mesh &m);

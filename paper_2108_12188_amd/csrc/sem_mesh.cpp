@@ -33,7 +33,7 @@ void upload(T *dst, const T *src, size_t count, hipStream_t s) {
 void free_mesh_arrays(Mesh *m) {
     void *ptrs[] = {m->vert64,     m->vert32,  m->G32,     m->G64,       m->B64,
                     m->mcode,      m->gs_idx,  m->dir_idx, m->surf_slot, m->slink,
-                    m->basis_blob, m->scratch, m->state};
+                    m->wedge_idx,  m->basis_blob, m->scratch, m->state};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -64,13 +64,15 @@ size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec) {
     b += n * 1;                                    // point codes
     b += n * 4 * 2;                                // group index list and Dirichlet list (bounds)
     b += (size_t)E * surface_nodes(N) * 4 + P3 * 2;   // tables of the gather in the update
+    b += n / 3 * 4;                                    // edge-array positions (bound)
     if (flags & SEM_MESH_G_FP32) b += n * 24;
     if (flags & SEM_MESH_G_FP64) b += n * 48;
     b += ((size_t)vec_blocks((int64_t)n) + 16) * 8 + sizeof(CgState) + 4096;
     // 5 vectors, the group sums (at most n / 3 groups of more than two
     // copies), reduction partials
-    const size_t ws32 = n * 4 * 5 + n / 3 * 4 + (size_t)E * 8 + (size_t)vec_blocks((int64_t)n) * 8 + 1024;
-    const size_t ws64 = n * 8 * 5 + n / 3 * 8 + (size_t)E * 8 + (size_t)vec_blocks((int64_t)n) * 8 + 1024;
+    const size_t we = (size_t)E * edge_slots(N);      // compact edge array
+    const size_t ws32 = n * 4 * 5 + n / 3 * 4 + we * 4 + (size_t)E * 8 + (size_t)vec_blocks((int64_t)n) * 8 + 1024;
+    const size_t ws64 = n * 8 * 5 + n / 3 * 8 + we * 8 + (size_t)E * 8 + (size_t)vec_blocks((int64_t)n) * 8 + 1024;
     if (prec == SEM_FP32) b += ws32;
     else if (prec == SEM_FP64) b += ws64;
     else b += ws32 + ws64;
@@ -109,6 +111,8 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     m->S = t.S;
     m->n_groups_multi = t.n_groups_multi;
     m->gs_blk_multi = t.gs_blk_multi;
+    m->gsum_wedge = t.gsum_wedge;
+    m->wedge_io0 = t.wedge_io0;
     m->p3_magic = t.p3_magic;
     m->p3_shift = t.p3_shift;
 
@@ -130,6 +134,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
             m->surf_slot = dev_alloc<int16_t>(*m, t.slot.size());
             m->slink = dev_alloc<int32_t>(*m, t.slink.size());
         }
+        if (t.gsum_wedge) m->wedge_idx = dev_alloc<int32_t>(*m, t.wedge_idx.size());
         // basis blob: FP64 D, Dt, xi, w then FP32 D, Dt, xi, w
         const size_t PP = (size_t)P * P;
         const size_t nd = 2 * PP + 2 * P;
@@ -166,6 +171,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
             upload(m->surf_slot, t.slot.data(), t.slot.size(), s);
             upload(m->slink, t.slink.data(), t.slink.size(), s);
         }
+        if (t.gsum_wedge) upload(m->wedge_idx, t.wedge_idx.data(), t.wedge_idx.size(), s);
         upload(b64, h64.data(), nd, s);
         upload(b32, h32.data(), nd, s);
         SEM_HIP(hipMemsetAsync(m->state, 0, sizeof(CgState), s));

@@ -222,6 +222,37 @@ void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, Host
     std::vector<int32_t>().swap(plink);
     t.gs_in_update = ok;
     t.S = S;
+
+    // compact edge-array positions of the copies of the groups with m > 2
+    t.gsum_wedge = false;
+    t.wedge_idx.clear();
+    t.wedge_io0 = 0;
+    int c0 = -1;
+    for (int c = 0; c < cls.ncls; ++c)
+        if (cls.M[c] > 2) {
+            c0 = c;
+            break;
+        }
+    if (ok && c0 >= 0) {
+        t.wedge_io0 = cls.io[c0];
+        const int MS = edge_slots(N);
+        bool all_edge = true;
+        t.wedge_idx.assign(gs_idx.size() - (size_t)t.wedge_io0, 0);
+        for (int c = c0; c < cls.ncls && all_edge; ++c)
+            for (int64_t q = 0; q < cls.ng[c] * cls.M[c]; ++q) {
+                const int64_t o = cls.io[c] + q;
+                const int64_t l = gs_idx[o], e = l / P3, loc = l % P3;
+                const int i = (int)(loc % P), j = (int)((loc / P) % P), k = (int)(loc / (P * P));
+                const int es = edge_slot(N, i, j, k);
+                if (es < 0) {
+                    all_edge = false;
+                    break;
+                }
+                t.wedge_idx[o - t.wedge_io0] = (int32_t)(e * MS + es);
+            }
+        t.gsum_wedge = all_edge;
+        if (!all_edge) t.wedge_idx.clear();
+    }
     division_magic((uint32_t)P3, t.p3_magic, t.p3_shift);
 
 }

@@ -7,7 +7,8 @@
 // usage: gather_tables_check E N glob_id.bin dirichlet.bin seed
 //   glob_id.bin: int64 [E][(N+1)^3], dirichlet.bin: uint8 [E][(N+1)^3]
 // Prints "gs_in_update=<0|1> checked=<points> odd_m=<points with m other
-// than 1, 2, 4, 8>" and exits 0, or names the first failing point and exits 1.
+// than 1, 2, 4, 8> gsum_wedge=<0|1>" and exits 0, or names the first
+// failing point and exits 1.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -111,6 +112,42 @@ int main(int argc, char **argv) {
                 gs64.push_back(s64);
             }
         }
+        // the same sums from the operator's compact copy of the edge and
+        // corner nodes, when the tables allow it
+        if (t.gsum_wedge) {
+            const int MS = sem::edge_slots(N);
+            std::vector<float> we32((size_t)E * MS, 0.f);
+            std::vector<double> we64((size_t)E * MS, 0.0);
+            for (l = 0; l < n; ++l) {
+                const int64_t e = l / P3, loc = l % P3;
+                const int es = sem::edge_slot(N, (int)(loc % P), (int)((loc / P) % P),
+                                              (int)(loc / (P * P)));
+                CHECK(es < MS, "edge slot %d of %d", es, MS);
+                if (es >= 0) {
+                    we32[e * MS + es] = w32[l];
+                    we64[e * MS + es] = w64[l];
+                }
+            }
+            size_t k = 0;
+            for (int c = 0; c < t.gs.ncls; ++c) {
+                const int M = t.gs.M[c];
+                if (M <= 2) continue;
+                for (int64_t g = 0; g < t.gs.ng[c]; ++g, ++k) {
+                    const int64_t o = t.gs.io[c] + g * M - t.wedge_io0;
+                    l = t.gs_idx[t.gs.io[c] + g * M];
+                    CHECK(o >= 0 && (size_t)(o + M) <= t.wedge_idx.size(), "edge list offset");
+                    float s32 = we32[t.wedge_idx[o]];
+                    double s64 = we64[t.wedge_idx[o]];
+                    for (int q = 1; q < M; ++q) {
+                        CHECK(t.wedge_idx[o + q] >= 0 && t.wedge_idx[o + q] < E * MS, "position");
+                        s32 += we32[t.wedge_idx[o + q]];
+                        s64 += we64[t.wedge_idx[o + q]];
+                    }
+                    CHECK(std::memcmp(&s32, &gs32[k], 4) == 0 && std::memcmp(&s64, &gs64[k], 8) == 0,
+                          "group sum from the edge array differs");
+                }
+            }
+        }
         const sem::vecb::GatherMap gm{t.slot.data(), t.slink.data(), t.p3_magic, t.p3_shift, P3,
                                       t.S};
         for (l = 0; l < n; ++l) {
@@ -154,7 +191,8 @@ int main(int argc, char **argv) {
             ++checked;
         }
     }
-    std::printf("gs_in_update=%d checked=%lld odd_m=%lld\n", t.gs_in_update ? 1 : 0,
-                (long long)checked, (long long)odd_m);
+    std::printf("gs_in_update=%d checked=%lld odd_m=%lld gsum_wedge=%d\n",
+                t.gs_in_update ? 1 : 0, (long long)checked, (long long)odd_m,
+                t.gsum_wedge ? 1 : 0);
     return 0;
 }

@@ -47,6 +47,8 @@ def test_conforming_meshes_gather_in_update(checker, tmp_path, shape, N):
     out = _run(checker, tmp_path, mesh)
     assert out["gs_in_update"] == "1"
     assert int(out["checked"]) == mesh.E * (N + 1) ** 3
+    if min(shape) > 1:   # interior edges exist: groups with m > 2 on element edges
+        assert out["gsum_wedge"] == "1"
 
 
 def test_odd_multiplicities_take_the_generic_loop(checker, tmp_path):
@@ -63,6 +65,7 @@ def test_odd_multiplicities_take_the_generic_loop(checker, tmp_path):
     out = _run(checker, tmp_path, mesh, gid)
     assert out["gs_in_update"] == "1"
     assert int(out["odd_m"]) == 3
+    assert out["gsum_wedge"] == "0"   # a group of face-interior nodes
 
 
 def test_interior_tie_disables_gather_in_update(checker, tmp_path):
