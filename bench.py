@@ -6,8 +6,9 @@ on a 32x32x32 mesh of hexahedra of order N = 7 (16,777,216 local points),
 interior vertices perturbed by U(-10%, +10%) of the spacing (seeded), a
 random continuous right-hand side U[-1, 1] per global point, homogeneous
 Dirichlet boundary.  Every step runs every kernel of the CG iteration:
-p-update + local operator + <p,w,c> partials; sums of the edge and vertex
-groups + alpha; gather of the face pairs + mask + x/r update + rho + beta.
+p-update + previous x step + local operator + <p,w,c> partials; sums of the
+edge and vertex groups + alpha; gather of the face pairs + mask + r update +
+rho + beta; and the closing x step.
 
 Prints ONE JSON line (rank 0) with the throughput in GDOF*iter/s
 (local points times iterations per second), the roofline of the dominant
@@ -224,7 +225,7 @@ def main(argv=None):
         achieved = fpp * n / (ax_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS}
-    roof["kernel"] = "ax_kernel<float, %s, CgFused> (p-update + A_L + <p,w,c> partials)" % (
+    roof["kernel"] = "ax_kernel<float, %s, CgFused> (p-update + previous x step + A_L + <p,w,c> partials)" % (
         "precomputed G" if args.geom == "pre" else "on-the-fly G")
     roof["avg_ms"] = ax_ms
     roof["traffic"] = read_traffic(f"cg_fused_{args.geom}_N{N}", n)

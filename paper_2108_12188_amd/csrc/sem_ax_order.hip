@@ -147,9 +147,11 @@ template <typename T>
 constexpr int ax_min_waves() { return (sizeof(T) == 4 && kP <= 8) ? 4 : 1; }
 
 // FP32 CG-fused tiles stage the next tile's r, p and vertices in LDS with
-// gfx950's direct global-to-LDS loads (16 bytes per lane, no registers
-// held while in flight), issued while the current tile computes.  Needs
-// 16-byte aligned element blocks: P^3 a multiple of 4 (odd N).
+// gfx950's direct global-to-LDS loads (16 bytes per lane, no registers held
+// while in flight), issued while the current tile computes; x (when the
+// previous step is applied here) lands in the operator tile itself, issued
+// once the tile is free.  Needs 16-byte aligned element blocks: P^3 a
+// multiple of 4 (odd N).
 template <typename T, bool FUSED>
 __host__ __device__ constexpr bool ax_dma() {
     return FUSED && sizeof(T) == 4 && (kP * kP * kP) % 4 == 0;
@@ -208,10 +210,11 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *const sA = reinterpret_cast<T *>(lds_raw);
     T *const sB = sA + a.epb * P3;
-    // staging (kDma): r and p of a tile, then its vertices
+    // staging (kDma): r and p of a tile, then its vertices; x goes to sA
     float *const sR = reinterpret_cast<float *>(sB + a.epb * P3);
     float *const sP = sR + a.epb * P3;
     float *const sV = sP + a.epb * P3;
+    float *const sX = reinterpret_cast<float *>(sA);
 
     if constexpr (FUSED) {
         if (a.st->stop) return;          // uniform: the whole grid exits
@@ -235,12 +238,21 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         DjT[l] = a.Dt[j * P + l];
     }
     T beta = T(0);
-    if constexpr (FUSED) beta = (T)a.st->beta;
+    // single-mesh CG: x += alpha_{i-1} p_{i-1} of the previous iteration,
+    // applied here where p_{i-1} is read anyway
+    bool xlag = false;
+    T aprev = T(0);
+    if constexpr (FUSED) {
+        beta = (T)a.st->beta;
+        xlag = a.x != nullptr && a.st->x_lag != 0;
+        aprev = (T)a.st->alpha;
+    }
     // edge-array slots of the column (edge_slot): base ecb (-1 off the
     // border) holds k = 0, ecb + 1 holds k = N, and corner columns keep
     // k = 1 .. N-1 at ecb + 1 + k
     const int ecb = edge_column_base(kOrder, i, j);
     const bool ecorner = (i == 0 || i == P - 1) && (j == 0 || j == P - 1);
+
     // per-lane GLL abscissae and weight product of the column
     T xi_i = T(0), eta_j = T(0), wij = T(0);
     if constexpr (OTF) {
@@ -249,7 +261,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         wij = a.wq[i] * a.wq[j];
     }
 
-    // stage tile tl (its valid elements only)
+    // stage tile tl (its valid elements only): r, p, vertices; x separately
     auto stage = [&](int64_t tl) {
         if constexpr (kDma) {
             const int64_t e0 = tl * a.epb;
@@ -260,8 +272,18 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                 dma_to_lds(reinterpret_cast<const float *>(a.vert) + e0 * 24, sV, nval * 24);
         }
     };
+    auto stage_x = [&](int64_t tl) {
+        if constexpr (kDma) {
+            const int64_t e0 = tl * a.epb;
+            const int nval = (int)(a.E - e0 < a.epb ? a.E - e0 : a.epb);
+            if (xlag) dma_to_lds(reinterpret_cast<const float *>(a.x) + e0 * P3, sX, nval * P3);
+        }
+    };
     if constexpr (kDma) {
-        if (vb < ntiles) stage(vb);
+        if (vb < ntiles) {
+            stage(vb);
+            stage_x(vb);
+        }
     }
 
     double acc = 0.0;
@@ -288,12 +310,20 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                 for (int k = 0; k < P; ++k) uc[k] = rr[k * P2] + beta * pp[k * P2];
 #pragma unroll
                 for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                if (xlag) {
+                    // x was staged in this thread's own slots of the tile,
+                    // which the p-update below overwrites
+                    const float *const xx = sX + el * P3 + col;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) a.x[base + k * P2] = xx[k * P2] + aprev * pp[k * P2];
+                }
             } else if constexpr (FUSED) {
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     const T r = a.u[base + k * P2];
                     const T pold = a.p[base + k * P2];
                     uc[k] = r + beta * pold;
+                    if (xlag) a.x[base + k * P2] += aprev * pold;
                 }
 #pragma unroll
                 for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
@@ -403,6 +433,9 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
             }
         }
         lds_barrier();   // the next tile overwrites the LDS tile
+        if constexpr (kDma) {
+            if (tile + vgrid < ntiles) stage_x(tile + vgrid);
+        }
     }
     if constexpr (FUSED) {
         const double s = block_sum(acc);

@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(vecb::kVecThreads)
 update_batch_kernel(const UpdBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
     const int2 pv = blk[blockIdx.x];
     const UpdBatchDesc u = d[pv.x];
-    vecb::update_body<float>(u.n, u.x, u.r, u.p, u.w, u.mcode, u.st, u.partial, pv.y, u.vgrid);
+    vecb::update_body<float, true>(u.n, u.x, u.r, u.p, u.w, u.mcode, u.st, u.partial, pv.y,
+                                   u.vgrid);
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)

@@ -3,11 +3,13 @@
 //
 // One CG iteration is three kernels:
 //   1. p <- r + beta p fused with w <- A_L p and the block partials of
-//      <p, w, c> (Algorithm 1: p-update and operator steps);
-//   2. w <- QQ^T w on the shared points, then a one-block kernel forms
+//      <p, w, c> (Algorithm 1: p-update and operator steps); the same pass
+//      applies the previous iteration's x += alpha p while p_old is at hand;
+//   2. w <- QQ^T w on the shared points, and one block forms
 //      alpha = rho / <p, w, c>;
-//   3. x += alpha p, r -= alpha mask(w) and the partials of rho = <r, r, c>,
-//      then a one-block kernel forms beta and runs the convergence test.
+//   3. r -= alpha mask(w) and the partials of rho = <r, r, c>, then a
+//      one-block kernel forms beta and runs the convergence test.
+// After the last iteration a flush applies the pending x += alpha p.
 // When every shared point lies on an element's surface (any conforming
 // mesh), step 2 only writes the sums of the groups of more than two copies
 // (edge and vertex nodes) to a compact array, and step 3 forms (QQ^T w)_l
@@ -126,6 +128,7 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
     a.st = ws.st;
     a.partial = ws.part_ax;
     a.wedge = m.gsum_wedge ? wedge : nullptr;
+    a.x = x;
     if (ev) SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     if (ev) SEM_HIP(hipEventRecord(ev[1], s));
@@ -133,8 +136,8 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
     if (m.gs_in_update) launch_group_sums_cg<T>(m, w, wedge, gsum, ws.st, ws.part_ax, (int)nax, s);
     else launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     if (ev) SEM_HIP(hipEventRecord(ev[2], s));
-    if (m.gs_in_update) launch_update_gather<T>(m, x, r, p, w, gsum, ws.st, ws.part_vec, s);
-    else launch_update<T>(m, x, r, p, w, ws.st, ws.part_vec, s);
+    if (m.gs_in_update) launch_update_gather<T>(m, r, w, gsum, ws.st, ws.part_vec, s);
+    else launch_update<T>(m, r, w, ws.st, ws.part_vec, s);
     if (ev) SEM_HIP(hipEventRecord(ev[3], s));
 }
 
@@ -272,6 +275,8 @@ InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, boo
         if (kt) run_chunk_timed<T>(m, ws, otf, chunk, last_iter, *kt);
         else run_chunk<T>(m, ws, otf, chunk, use_graph);
     }
+    // the last completed iteration's x step
+    launch_x_flush<T>(m, x, p, ws.st, s);
     InnerOut o;
     o.iters = ws.h_st->iter;
     o.stop = ws.h_st->stop;

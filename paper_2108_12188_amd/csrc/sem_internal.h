@@ -71,6 +71,9 @@ struct CgState {
     int max_iter;      // iteration cap
     int stop;          // 0 running, 1 converged, 2 cap reached, 3 breakdown
     int fixed;         // 1: no convergence test
+    int x_lag;         // 1: x still lacks alpha_i p_i of the last completed
+                       // update (single-mesh solves apply it in the next
+                       // operator launch, or in the closing flush)
     int hist_len;      // capacity of the history arrays
     double *hist_rho;  // device history (may be null)
     double *hist_alpha;
@@ -210,6 +213,8 @@ struct AxArgs {
     int64_t vgrid;              // batched launches: this problem's own grid size
     T *wedge;                   // CgFused, may be null: w of the edge and corner
                                 // nodes, [E][edge_slots(N)]
+    T *x;                       // CgFused, may be null: solution; when st->x_lag,
+                                // x += alpha p_old (previous iteration's step)
 };
 
 // Launch configuration chosen for an order (threads, elements per block,
@@ -260,16 +265,20 @@ int64_t gs_logical_blocks(const Mesh &m);
 // partial per block (`partial`, at least vec_blocks(n) entries) and a
 // one-block finalize kernel sums them in index order.
 int vec_blocks(int64_t n);
-// x += alpha p; r -= alpha w; rho = <r, r, c>; then beta, convergence, history
+// r -= alpha mask(w); rho = <r, r, c>; then beta, convergence, history (x is
+// advanced by the next operator launch or launch_x_flush)
 template <typename T>
-void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
-                   double *partial, hipStream_t s);
+void launch_update(const Mesh &m, T *r, const T *w, CgState *st, double *partial,
+                   hipStream_t s);
+// x += alpha p when st->x_lag (the step of the last completed update)
+template <typename T>
+void launch_x_flush(const Mesh &m, T *x, const T *p, const CgState *st, hipStream_t s);
 // The same with w read as QQ^T w, w holding the operator's masked local
 // output and gsum the group sums of launch_group_sums_cg: pairs are summed
 // inside the update (needs m.gs_in_update).
 template <typename T>
-void launch_update_gather(const Mesh &m, T *x, T *r, const T *p, const T *w, const T *gsum,
-                          CgState *st, double *partial, hipStream_t s);
+void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgState *st,
+                          double *partial, hipStream_t s);
 // r = b - w (w may be null: r = b); p = 0; rho_0 = <r, r, c>; initial state
 template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,

@@ -14,19 +14,28 @@ using namespace vecb;
 
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
-update_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-              const T *__restrict__ w, const uint8_t *__restrict__ mcode, CgState *st,
-              double *partial) {
-    update_body<T>(n, x, r, p, w, mcode, st, partial, blockIdx.x, gridDim.x);
+update_kernel(int64_t n, T *__restrict__ r, const T *__restrict__ w,
+              const uint8_t *__restrict__ mcode, CgState *st, double *partial) {
+    update_body<T, false>(n, nullptr, r, nullptr, w, mcode, st, partial, blockIdx.x, gridDim.x);
+}
+
+// x += alpha p when the state says the last update's step is pending
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+x_flush_kernel(int64_t n, T *__restrict__ x, const T *__restrict__ p, const CgState *st) {
+    if (!st->x_lag) return;
+    const T a = (T)st->alpha;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        x[q] += a * p[q];
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
-update_gather_kernel(int64_t n, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-                     const T *__restrict__ w, const T *__restrict__ gsum,
-                     const uint8_t *__restrict__ mcode, const GatherMap gm, CgState *st,
-                     double *partial) {
-    update_gather_body<T>(n, x, r, p, w, gsum, mcode, gm, st, partial, blockIdx.x, gridDim.x);
+update_gather_kernel(int64_t n, T *__restrict__ r, const T *__restrict__ w,
+                     const T *__restrict__ gsum, const uint8_t *__restrict__ mcode,
+                     const GatherMap gm, CgState *st, double *partial) {
+    update_gather_body<T>(n, r, w, gsum, mcode, gm, st, partial, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)
@@ -71,6 +80,7 @@ finalize_init_kernel(CgState *st, const double *partial, int cnt) {
         st->thresh = st->thresh * rho0;
         st->beta = 0.0;
         st->alpha = 0.0;
+        st->x_lag = 0;
         st->iter = 0;
         if (st->hist_rho && st->hist_len > 0) st->hist_rho[0] = rho0;
         int stop = 0;
@@ -165,10 +175,10 @@ int vec_blocks(int64_t n) {
 }
 
 template <typename T>
-void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *st,
-                   double *partial, hipStream_t s) {
+void launch_update(const Mesh &m, T *r, const T *w, CgState *st, double *partial,
+                   hipStream_t s) {
     const int nb = vec_blocks(m.n);
-    hipLaunchKernelGGL((update_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, x, r, p, w,
+    hipLaunchKernelGGL((update_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, r, w,
                        m.mcode, st, partial);
     hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
                        (const double *)partial, nb);
@@ -176,14 +186,21 @@ void launch_update(const Mesh &m, T *x, T *r, const T *p, const T *w, CgState *s
 }
 
 template <typename T>
-void launch_update_gather(const Mesh &m, T *x, T *r, const T *p, const T *w, const T *gsum,
-                          CgState *st, double *partial, hipStream_t s) {
+void launch_x_flush(const Mesh &m, T *x, const T *p, const CgState *st, hipStream_t s) {
+    hipLaunchKernelGGL((x_flush_kernel<T>), dim3(elem_blocks(m.n)), dim3(kVecThreads), 0, s, m.n,
+                       x, p, st);
+    check_hip(hipGetLastError(), "x flush kernel launch");
+}
+
+template <typename T>
+void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgState *st,
+                          double *partial, hipStream_t s) {
     if (!m.gs_in_update)
         fail(SEM_EUNSUPPORTED, "mesh shares points inside elements: no gather in the update");
     const GatherMap gm{m.surf_slot, m.slink, m.p3_magic, m.p3_shift, m.P3, m.S};
     const int nb = vec_blocks(m.n);
-    hipLaunchKernelGGL((update_gather_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, x, r,
-                       p, w, gsum, m.mcode, gm, st, partial);
+    hipLaunchKernelGGL((update_gather_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, r, w,
+                       gsum, m.mcode, gm, st, partial);
     hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
                        (const double *)partial, nb);
     check_hip(hipGetLastError(), "update kernel launch");
@@ -247,16 +264,18 @@ void launch_mul64(int64_t n, const double *a, const double *b, double *out, hipS
     check_hip(hipGetLastError(), "mul kernel launch");
 }
 
-template void launch_update<float>(const Mesh &, float *, float *, const float *, const float *,
-                                   CgState *, double *, hipStream_t);
-template void launch_update<double>(const Mesh &, double *, double *, const double *,
-                                    const double *, CgState *, double *, hipStream_t);
-template void launch_update_gather<float>(const Mesh &, float *, float *, const float *,
-                                          const float *, const float *, CgState *, double *,
-                                          hipStream_t);
-template void launch_update_gather<double>(const Mesh &, double *, double *, const double *,
-                                           const double *, const double *, CgState *, double *,
-                                           hipStream_t);
+template void launch_update<float>(const Mesh &, float *, const float *, CgState *, double *,
+                                   hipStream_t);
+template void launch_update<double>(const Mesh &, double *, const double *, CgState *, double *,
+                                    hipStream_t);
+template void launch_x_flush<float>(const Mesh &, float *, const float *, const CgState *,
+                                    hipStream_t);
+template void launch_x_flush<double>(const Mesh &, double *, const double *, const CgState *,
+                                     hipStream_t);
+template void launch_update_gather<float>(const Mesh &, float *, const float *, const float *,
+                                          CgState *, double *, hipStream_t);
+template void launch_update_gather<double>(const Mesh &, double *, const double *,
+                                           const double *, CgState *, double *, hipStream_t);
 template void launch_cg_init<float>(const Mesh &, const float *, const float *, float *, float *,
                                     CgState *, double *, hipStream_t);
 template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,

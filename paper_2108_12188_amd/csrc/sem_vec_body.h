@@ -26,12 +26,12 @@ __device__ __forceinline__ void weights_lds(double *cw) {
     __syncthreads();
 }
 
-// x += alpha p; r -= alpha mask(w); rho_i = <r, r, c>  (Algorithm 1: mask,
-// fused updates and reduction; the operator leaves w unmasked), then
-// beta_i = rho_i / rho_{i-1} and the convergence test.
+// [x += alpha p;] r -= alpha mask(w); rho_i = <r, r, c>  (Algorithm 1:
+// mask, fused updates and reduction; the operator leaves w unmasked).
+// WithX = false leaves x to the next operator launch (single-mesh solves).
 // Virtual block vb of a grid of vgrid blocks; the partial goes to
 // partial[vb].
-template <typename T>
+template <typename T, bool WithX>
 __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__restrict__ r,
                                             const T *__restrict__ p, const T *__restrict__ w,
                                             const uint8_t *__restrict__ mcode, CgState *st,
@@ -46,25 +46,28 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
     for (int64_t q = tid; q < n4; q += stride) {
-        Pack4<T> xv = reinterpret_cast<const Pack4<T> *>(x)[q];
         Pack4<T> rv = reinterpret_cast<const Pack4<T> *>(r)[q];
-        const Pack4<T> pv = reinterpret_cast<const Pack4<T> *>(p)[q];
         const Pack4<T> wv = reinterpret_cast<const Pack4<T> *>(w)[q];
         const Code4 mv = reinterpret_cast<const Code4 *>(mcode)[q];
+        if constexpr (WithX) {
+            Pack4<T> xv = reinterpret_cast<const Pack4<T> *>(x)[q];
+            const Pack4<T> pv = reinterpret_cast<const Pack4<T> *>(p)[q];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) xv.v[t] += a * pv.v[t];
+            reinterpret_cast<Pack4<T> *>(x)[q] = xv;
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const T wm = (mv.v[t] & kDirichletBit) ? T(0) : wv.v[t];
-            xv.v[t] += a * pv.v[t];
             rv.v[t] -= a * wm;
             const double rd = (double)rv.v[t];
             acc += rd * rd * cw[mv.v[t]];
         }
-        reinterpret_cast<Pack4<T> *>(x)[q] = xv;
         reinterpret_cast<Pack4<T> *>(r)[q] = rv;
     }
     for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
         const uint8_t c = mcode[q];
-        x[q] += a * p[q];
+        if constexpr (WithX) x[q] += a * p[q];
         const T rn = r[q] - a * ((c & kDirichletBit) ? T(0) : w[q]);
         r[q] = rn;
         acc += (double)rn * (double)rn * cw[c];
@@ -122,13 +125,15 @@ __host__ __device__ __forceinline__ T copies_sum(T own, uint8_t code, T src) {
     return code == kPairCode ? own + src : (is_group_code(code) ? src : own);
 }
 
-// update_body with w replaced by QQ^T w (w itself is not modified).  Same
-// grid, same per-thread order and the same sums as gather-scatter +
-// update_body, so the results are bitwise those of the two-pass form.  All
-// loads are unconditional: a pack costs two dependent rounds of loads.
+// update_body<T, false> with w replaced by QQ^T w (w itself is not
+// modified).  Same grid, same per-thread order and the same sums as
+// gather-scatter + update_body, so the results are bitwise those of the
+// two-pass form.  All loads are unconditional: two packs (q, q + stride)
+// per step, each costing two dependent rounds of loads, all loads of both
+// issued before any result is used; the sum of r^2/m still runs pack by
+// pack in the thread's order q, q + stride, q + 2 stride, ...
 template <typename T>
-__device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ x,
-                                                   T *__restrict__ r, const T *__restrict__ p,
+__device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
                                                    const T *__restrict__ w,
                                                    const T *__restrict__ gsum,
                                                    const uint8_t *__restrict__ mcode,
@@ -145,23 +150,18 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ x,
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
-    // two packs (q, q + stride) per step, every load of both issued before
-    // any result is used; the sum of r^2/m still runs pack by pack in the
-    // thread's order q, q + stride, q + 2 stride, ...
     for (int64_t q = tid; q < n4; q += 2 * stride) {
         const bool two = q + stride < n4;
         const int64_t qq[2] = {q, two ? q + stride : q};
         int32_t lk[2][4];
-        Pack4<T> xv[2], rv[2], pv[2], wv[2];
+        Pack4<T> rv[2], wv[2];
         Code4 mv[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t l0 = (uint32_t)(4 * qq[h]);
 #pragma unroll
             for (int t = 0; t < 4; ++t) lk[h][t] = node_link(l0 + t, gm, slot);
-            xv[h] = reinterpret_cast<const Pack4<T> *>(x)[qq[h]];
             rv[h] = reinterpret_cast<const Pack4<T> *>(r)[qq[h]];
-            pv[h] = reinterpret_cast<const Pack4<T> *>(p)[qq[h]];
             wv[h] = reinterpret_cast<const Pack4<T> *>(w)[qq[h]];
             mv[h] = reinterpret_cast<const Code4 *>(mcode)[qq[h]];
         }
@@ -178,12 +178,10 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ x,
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const T wg = copies_sum<T>(wv[h].v[t], mv[h].v[t], src[h][t]);
-                xv[h].v[t] += a * pv[h].v[t];
                 rv[h].v[t] -= a * wg;
                 const double rd = (double)rv[h].v[t];
                 acc += rd * rd * cw[mv[h].v[t]];
             }
-            reinterpret_cast<Pack4<T> *>(x)[qq[h]] = xv[h];
             reinterpret_cast<Pack4<T> *>(r)[qq[h]] = rv[h];
         }
     }
@@ -191,7 +189,6 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ x,
         const uint8_t c = mcode[q];
         const int32_t lk = node_link((uint32_t)q, gm, slot);
         const T wg = copies_sum<T>(w[q], c, *gather_source<T>(w, gsum, c, lk, q));
-        x[q] += a * p[q];
         const T rn = r[q] - a * wg;
         r[q] = rn;
         acc += (double)rn * (double)rn * cw[c];
@@ -211,6 +208,7 @@ __device__ __forceinline__ void finalize_rho_body(CgState *st, const double *par
         const double beta = rho / st->rho;
         st->beta = beta;
         st->rho = rho;
+        st->x_lag = 1;
         const int it = st->iter + 1;
         st->iter = it;
         if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rho;
@@ -232,6 +230,7 @@ __device__ __forceinline__ void finalize_alpha_body(CgState *st, const double *p
         const double alpha = st->rho / pw;
         st->pw = pw;
         st->alpha = alpha;
+        st->x_lag = 0;     // the operator launch before this one applied it
         if (!(pw > 0.0) || !isfinite(alpha)) st->stop = 3;
         const int i = st->iter + 1;
         if (st->hist_alpha && i < st->hist_len) st->hist_alpha[i] = alpha;
