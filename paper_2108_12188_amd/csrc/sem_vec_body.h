@@ -110,8 +110,10 @@ __host__ __device__ __forceinline__ bool is_group_code(uint8_t code) {
 template <typename T>
 __host__ __device__ __forceinline__ const T *gather_source(const T *w, const T *gsum,
                                                            uint8_t code, int32_t lk, int64_t l) {
-    return code == kPairCode ? w + (uint32_t)lk
-                             : (is_group_code(code) ? gsum + (uint32_t)lk : w + l);
+    const bool group = is_group_code(code);
+    const T *base = group ? gsum : w;
+    const int64_t off = (code == kPairCode || group) ? (int64_t)(uint32_t)lk : l;
+    return base + off;
 }
 
 // mask(QQ^T w)_l: a pair adds its partner's value (a + b == b + a in IEEE
@@ -121,8 +123,11 @@ __host__ __device__ __forceinline__ const T *gather_source(const T *w, const T *
 // src: the value at gather_source.
 template <typename T>
 __host__ __device__ __forceinline__ T copies_sum(T own, uint8_t code, T src) {
-    if (code & kDirichletBit) return T(0);
-    return code == kPairCode ? own + src : (is_group_code(code) ? src : own);
+    // selects, not branches: src is consumed on every path
+    const T pair_sum = own + src;
+    T v = code == kPairCode ? pair_sum : own;
+    v = is_group_code(code) ? src : v;
+    return (code & kDirichletBit) ? T(0) : v;
 }
 
 // update_body<T, false> with w replaced by QQ^T w (w itself is not
@@ -172,15 +177,19 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
             for (int t = 0; t < 4; ++t)
                 src[h][t] = *gather_source<T>(w, gsum, mv[h].v[t], lk[h][t],
                                               (int64_t)(4 * qq[h] + t));
+        // without a second pack (!two) the first is computed twice: the
+        // second copy stores the same values and adds exactly 0 to the sum
+        // (every result is consumed on every path, so no load of this step
+        // is still pending when the next step reuses its registers)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            if (h == 1 && !two) break;
+            const bool live = h == 0 || two;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const T wg = copies_sum<T>(wv[h].v[t], mv[h].v[t], src[h][t]);
                 rv[h].v[t] -= a * wg;
                 const double rd = (double)rv[h].v[t];
-                acc += rd * rd * cw[mv[h].v[t]];
+                acc += live ? rd * rd * cw[mv[h].v[t]] : 0.0;
             }
             reinterpret_cast<Pack4<T> *>(r)[qq[h]] = rv[h];
         }
