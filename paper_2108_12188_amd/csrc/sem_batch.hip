@@ -1,9 +1,12 @@
 // sem_batch.hip -- many independent meshes advanced together.
 //
 // One batched CG iteration is a fixed sequence of launches that each cover
-// every problem: the fused local operator once per polynomial order, then
-// the gather-scatter, the alpha finalize (one block per problem), the x/r
-// update and the rho finalize (one block per problem).  Block b of a
+// every problem, the same schedule as a single-mesh solve: the fused local
+// operator once per polynomial order (p-update, the previous iteration's x
+// step, <p,w,c> partials), the edge/vertex group sums (or, for a mesh that
+// shares element-interior nodes, the whole gather-scatter), the alpha
+// finalize (one block per problem), the r update with the gather and the rho
+// finalize (one block per problem).  Block b of a
 // launch runs "virtual block" blk[b].y of problem blk[b].x -- exactly the
 // block that the problem's own single-mesh launch would run, with the same
 // tiles, the same grid stride and the same partial slot -- so every
@@ -32,11 +35,32 @@ struct GsBatchDesc {
 
 struct UpdBatchDesc {
     int64_t n;
-    float *x;
     float *r;
-    const float *p;
     const float *w;
     const uint8_t *mcode;
+    CgState *st;
+    double *partial;
+    int64_t vgrid;
+};
+
+// group sums of one problem (see launch_group_sums_cg)
+struct GsumBatchDesc {
+    const GsClasses *cls;
+    const int32_t *idx;
+    int64_t io0;
+    const float *src;
+    float *out;
+    const CgState *st;
+};
+
+// update with gather of one problem (see launch_update_gather)
+struct UpdGBatchDesc {
+    int64_t n;
+    float *r;
+    const float *w;
+    const float *gsum;
+    const uint8_t *mcode;
+    vecb::GatherMap gm;
     CgState *st;
     double *partial;
     int64_t vgrid;
@@ -64,12 +88,28 @@ finalize_alpha_batch_kernel(const FinBatchDesc *__restrict__ d) {
     vecb::finalize_alpha_body(f.st, f.part_ax, f.n_ax);
 }
 
+__global__ void __launch_bounds__(gsb::kGsThreads)
+group_sums_batch_kernel(const GsumBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
+    const int2 pv = blk[blockIdx.x];
+    const GsumBatchDesc g = d[pv.x];
+    if (g.st->stop) return;
+    gsb::gs_sums_logical_block<float>(*g.cls, pv.y, g.idx, g.io0, g.src, g.out);
+}
+
 __global__ void __launch_bounds__(vecb::kVecThreads)
 update_batch_kernel(const UpdBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
     const int2 pv = blk[blockIdx.x];
     const UpdBatchDesc u = d[pv.x];
-    vecb::update_body<float, true>(u.n, u.x, u.r, u.p, u.w, u.mcode, u.st, u.partial, pv.y,
-                                   u.vgrid);
+    vecb::update_body<float, false>(u.n, nullptr, u.r, nullptr, u.w, u.mcode, u.st, u.partial,
+                                    pv.y, u.vgrid);
+}
+
+__global__ void __launch_bounds__(vecb::kVecThreads)
+update_gather_batch_kernel(const UpdGBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
+    const int2 pv = blk[blockIdx.x];
+    const UpdGBatchDesc u = d[pv.x];
+    vecb::update_gather_body<float>(u.n, u.r, u.w, u.gsum, u.mcode, u.gm, u.st, u.partial, pv.y,
+                                    u.vgrid);
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)
@@ -122,11 +162,18 @@ struct BatchImpl {
     UpdBatchDesc *d_upd = nullptr;
     int2 *d_upd_blk = nullptr;
     int64_t n_upd_blk = 0;
+    GsumBatchDesc *d_gsum = nullptr;
+    int2 *d_gsum_blk = nullptr;
+    int64_t n_gsum_blk = 0;
+    UpdGBatchDesc *d_updg = nullptr;
+    int2 *d_updg_blk = nullptr;
+    int64_t n_updg_blk = 0;
     FinBatchDesc *d_fin[2] = {nullptr, nullptr};   // [precomputed, on the fly]
     int2 *d_states = nullptr;
     int2 *h_states = nullptr;                        // pinned
     size_t cap_ax[2] = {0, 0}, cap_fin[2] = {0, 0}, cap_cls = 0, cap_gs = 0, cap_gs_blk = 0,
-           cap_upd = 0, cap_upd_blk = 0, cap_states = 0, cap_h_states = 0;
+           cap_upd = 0, cap_upd_blk = 0, cap_gsum = 0, cap_gsum_blk = 0, cap_updg = 0,
+           cap_updg_blk = 0, cap_states = 0, cap_h_states = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -139,8 +186,9 @@ struct BatchImpl {
         for (int f = 0; f < 2; ++f)
             for (auto &g : groups[f])
                 if (g.blk) (void)hipFree(g.blk);
-        void *ptrs[] = {d_ax[0], d_ax[1], d_cls, d_gs, d_gs_blk, d_upd, d_upd_blk, d_fin[0],
-                        d_fin[1], d_states};
+        void *ptrs[] = {d_ax[0],   d_ax[1], d_cls,      d_gs,   d_gs_blk,   d_upd,
+                        d_upd_blk, d_gsum,  d_gsum_blk, d_updg, d_updg_blk, d_fin[0],
+                        d_fin[1],  d_states};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
         if (h_states) (void)hipHostFree(h_states);
@@ -163,10 +211,17 @@ struct BatchImpl {
         if (n_gs_blk > 0)
             hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)n_gs_blk), dim3(gsb::kGsThreads), 0,
                                s, d_gs, d_gs_blk);
+        if (n_gsum_blk > 0)
+            hipLaunchKernelGGL(group_sums_batch_kernel, dim3((unsigned)n_gsum_blk),
+                               dim3(gsb::kGsThreads), 0, s, d_gsum, d_gsum_blk);
         hipLaunchKernelGGL(finalize_alpha_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0,
                            s, d_fin[f]);
-        hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)n_upd_blk), dim3(vecb::kVecThreads),
-                           0, s, d_upd, d_upd_blk);
+        if (n_upd_blk > 0)
+            hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)n_upd_blk),
+                               dim3(vecb::kVecThreads), 0, s, d_upd, d_upd_blk);
+        if (n_updg_blk > 0)
+            hipLaunchKernelGGL(update_gather_batch_kernel, dim3((unsigned)n_updg_blk),
+                               dim3(vecb::kVecThreads), 0, s, d_updg, d_updg_blk);
         hipLaunchKernelGGL(finalize_rho_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0, s,
                            d_fin[f]);
         check_hip(hipGetLastError(), "batched iteration launch");
@@ -262,8 +317,10 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     std::vector<GsClasses> cls;
     std::vector<GsBatchDesc> gsd;
     std::vector<UpdBatchDesc> upd;
+    std::vector<GsumBatchDesc> gsumd;
+    std::vector<UpdGBatchDesc> updg;
     std::vector<FinBatchDesc> fin[2];
-    std::vector<int2> gs_blk, upd_blk;
+    std::vector<int2> gs_blk, upd_blk, gsum_blk, updg_blk;
     std::map<int, std::vector<int2>> order_blk[2];
     std::map<int, int> order_epb[2];
     ensure_cap(d_cls, cap_cls, count, bytes);
@@ -278,6 +335,8 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             a.w = static_cast<float *>(ws.w);
             a.st = ws.st;
             a.partial = ws.part_ax;
+            a.x = static_cast<float *>(ws.x);
+            a.wedge = m.gsum_wedge ? static_cast<float *>(ws.wedge) : nullptr;
             ax[otf].push_back(a);
         }
         for (int f = 0; f < 2; ++f) {
@@ -292,14 +351,34 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             order_w[m.N] = m.h_w;
         }
         cls.push_back(m.gs);
-        gsd.push_back({d_cls + q, m.gs_idx, static_cast<float *>(ws.w), ws.st});
         const int64_t nlb = m.n_groups > 0 ? gs_logical_blocks(m) : 0;
-        for (int64_t lb = 0; lb < nlb; ++lb) gs_blk.push_back(make_int2(q, (int)lb));
         const int nv = vec_blocks(m.n);
-        upd.push_back({m.n, static_cast<float *>(ws.x), static_cast<float *>(ws.r),
-                       static_cast<const float *>(ws.p), static_cast<const float *>(ws.w), m.mcode,
-                       ws.st, ws.part_vec, nv});
-        for (int vb = 0; vb < nv; ++vb) upd_blk.push_back(make_int2(q, vb));
+        if (m.gs_in_update) {
+            // the single-mesh schedule: group sums of the edge and vertex
+            // groups, update with gather (the same logical and virtual blocks)
+            const bool compact = m.gsum_wedge;
+            gsumd.push_back({d_cls + q, compact ? m.wedge_idx : m.gs_idx,
+                             compact ? m.wedge_io0 : (int64_t)0,
+                             compact ? static_cast<const float *>(ws.wedge)
+                                     : static_cast<const float *>(ws.w),
+                             static_cast<float *>(ws.gsum), ws.st});
+            for (int64_t lb = m.gs_blk_multi; lb < nlb; ++lb)
+                gsum_blk.push_back(make_int2((int)gsumd.size() - 1, (int)lb));
+            const vecb::GatherMap gm{m.surf_slot, m.slink, m.p3_magic, m.p3_shift, m.P3, m.S};
+            updg.push_back({m.n, static_cast<float *>(ws.r), static_cast<const float *>(ws.w),
+                            static_cast<const float *>(ws.gsum), m.mcode, gm, ws.st, ws.part_vec,
+                            nv});
+            for (int vb = 0; vb < nv; ++vb)
+                updg_blk.push_back(make_int2((int)updg.size() - 1, vb));
+        } else {
+            gsd.push_back({d_cls + q, m.gs_idx, static_cast<float *>(ws.w), ws.st});
+            for (int64_t lb = 0; lb < nlb; ++lb)
+                gs_blk.push_back(make_int2((int)gsd.size() - 1, (int)lb));
+            upd.push_back({m.n, static_cast<float *>(ws.r), static_cast<const float *>(ws.w),
+                           m.mcode, ws.st, ws.part_vec, nv});
+            for (int vb = 0; vb < nv; ++vb)
+                upd_blk.push_back(make_int2((int)upd.size() - 1, vb));
+        }
         for (int f = 0; f < 2; ++f)
             fin[f].push_back({ws.st, ws.part_ax, ax[f].back().vgrid, ws.part_vec, nv});
     }
@@ -312,6 +391,10 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     upload_sync(d_gs, gsd);
     ensure_cap(d_upd, cap_upd, count, bytes);
     upload_sync(d_upd, upd);
+    ensure_cap(d_gsum, cap_gsum, count, bytes);
+    upload_sync(d_gsum, gsumd);
+    ensure_cap(d_updg, cap_updg, count, bytes);
+    upload_sync(d_updg, updg);
     for (int f = 0; f < 2; ++f) {
         ensure_cap(d_fin[f], cap_fin[f], count, bytes);
         upload_sync(d_fin[f], fin[f]);
@@ -329,6 +412,12 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     n_upd_blk = (int64_t)upd_blk.size();
     ensure_cap(d_upd_blk, cap_upd_blk, upd_blk.size(), bytes);
     upload_sync(d_upd_blk, upd_blk);
+    n_gsum_blk = (int64_t)gsum_blk.size();
+    ensure_cap(d_gsum_blk, cap_gsum_blk, gsum_blk.size(), bytes);
+    upload_sync(d_gsum_blk, gsum_blk);
+    n_updg_blk = (int64_t)updg_blk.size();
+    ensure_cap(d_updg_blk, cap_updg_blk, updg_blk.size(), bytes);
+    upload_sync(d_updg_blk, updg_blk);
     for (int f = 0; f < 2; ++f) {
         for (auto &g : groups[f])
             if (g.blk) (void)hipFree(g.blk);
@@ -430,6 +519,8 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
         for (int q = 0; q < P; ++q) {
             Mesh &m = *B.meshes[q];
             Workspace &ws = cg_workspace(m, false);
+            launch_x_flush<float>(m, static_cast<float *>(ws.x), static_cast<const float *>(ws.p),
+                                  ws.st, s);
             SEM_HIP(hipMemcpyAsync(x_dev[q], ws.x, sizeof(float) * m.n, hipMemcpyDeviceToDevice, s));
             SEM_HIP(hipMemcpyAsync(ws.h_st, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
             SEM_HIP(hipStreamSynchronize(s));
@@ -521,6 +612,8 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
                     done[q] = 3;
                     continue;
                 }
+                launch_x_flush<float>(m, static_cast<float *>(w32.x),
+                                      static_cast<const float *>(w32.p), w32.st, s);
                 launch_axpy_from_f32(m.n, static_cast<double *>(w64.x), w64.dval + 0,
                                      static_cast<const float *>(w32.x), s);
                 ++outer[q];
@@ -722,6 +815,8 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
             if (h.stop == 3) {
                 r.broken = true;
             } else {
+                launch_x_flush<float>(*r.m, static_cast<float *>(w32.x),
+                                      static_cast<const float *>(w32.p), w32.st, s);
                 launch_axpy_from_f32(r.m->n, static_cast<double *>(w64.x), w64.dval + 0,
                                      static_cast<const float *>(w32.x), s);
                 ++r.outer;
