@@ -64,6 +64,11 @@ def lib():
         L.or_cg.argtypes = [C.c_long, C.c_int, _dp, _dp, _ip, C.c_long, _bp, _dp, _dp, _dp,
                             C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_cg.restype = C.c_int
+        L.or_diag_A.argtypes = [C.c_long, C.c_int, _dp, _dp, _ip, C.c_long, _dp]
+        L.or_pcg.argtypes = [C.c_long, C.c_int, _dp, _dp, _ip, C.c_long, _bp, _dp, _dp, _dp,
+                             _dp, C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                             C.c_void_p]
+        L.or_pcg.restype = C.c_int
         _lib = L
     return _lib
 
@@ -215,6 +220,33 @@ class Problem:
                          beta.ctypes.data if history else None)
         hist = {"rho": rho[:it + 1], "alpha": alpha[:it + 1], "beta": beta[:it + 1]}
         return x, it, hist
+
+    # Jacobi preconditioner (f4) --------------------------------------
+    def diag_A(self):
+        """Diagonal of the assembled operator Q^T A_L Q, in local form
+        (unmasked)."""
+        d = np.zeros(self.n)
+        lib().or_diag_A(self.E, self.N, _f64(self.D), self.G, self.glob_id, self.n_glob, d)
+        return d
+
+    def jacobi_minv(self):
+        """M^-1 of the Jacobi preconditioner: 1/diag on the free points, 0 on
+        the Dirichlet points."""
+        d = self.diag_A()
+        return np.where(self.dirichlet.astype(bool), 0.0, 1.0 / d)
+
+    def pcg(self, b, minv=None, x0=None, tol=1e-8, max_iter=10000, fixed=0):
+        """Jacobi-preconditioned Algorithm 1; returns (x, iters, hist) with
+        hist = dict(rho = <r,r,c>, alpha, beta)."""
+        minv = self.jacobi_minv() if minv is None else _f64(minv).ravel()
+        x = np.zeros(self.n) if x0 is None else self.mask(x0)
+        b = _f64(b).ravel()
+        L = (fixed if fixed > 0 else max_iter) + 1
+        rho, alpha, beta = np.zeros(L), np.zeros(L), np.zeros(L)
+        it = lib().or_pcg(self.E, self.N, _f64(self.D), self.G, self.glob_id, self.n_glob,
+                          self.dirichlet, self.m, minv, b, x, tol, max_iter, fixed,
+                          rho.ctypes.data, alpha.ctypes.data, beta.ctypes.data)
+        return x, it, {"rho": rho[:it + 1], "alpha": alpha[:it + 1], "beta": beta[:it + 1]}
 
     def true_rel_residual(self, b, x):
         r = _f64(b).ravel() - self.apply_A(x)

@@ -408,3 +408,92 @@ int or_cg(long E, int N, const double *D, const double *G, const int64_t *glob_i
     free(r); free(p); free(w); free(op.sum);
     return it;
 }
+
+/* ------------------------------------------------------------------ */
+/* f4. Jacobi preconditioner: the diagonal of the assembled operator
+ * A = Q^T A_L Q (Sec. 3, Eq. 4), in local (replicated) form.
+ * Element diagonal from the definition A_L = sum_{a,b} D_a^T G_ab D_b:
+ * (A_L)_qq = sum_{a,b} sum_q' (D_a)_{q'q} G_ab(q') (D_b)_{q'q}, where
+ * (D_r)_{q'q} = D[i'][i] if (j',k') = (j,k) and 0 otherwise (likewise D_s
+ * along j, D_t along k).  For a = b, q' runs over the line through q in
+ * direction a; for a != b the two lines meet only at q' = q.
+ * The element diagonals are then summed over the copies of every global
+ * point (gather-scatter).  diag is n doubles. */
+void or_diag_A(long E, int N, const double *D, const double *G, const int64_t *glob_id,
+               long n_glob, double *diag)
+{
+    int P = N + 1;
+    long P3 = (long)P * P * P;
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < E; ++e) {
+        const double *Ge = G + 6 * P3 * e;
+        for (int k = 0; k < P; ++k)
+            for (int j = 0; j < P; ++j)
+                for (int i = 0; i < P; ++i) {
+                    long q = i + P * (j + (long)P * k);
+                    double s = 0.0;
+                    for (int l = 0; l < P; ++l) {
+                        s += D[l * P + i] * D[l * P + i] * Ge[0 * P3 + l + P * (j + P * k)];
+                        s += D[l * P + j] * D[l * P + j] * Ge[3 * P3 + i + P * (l + P * k)];
+                        s += D[l * P + k] * D[l * P + k] * Ge[5 * P3 + i + P * (j + P * l)];
+                    }
+                    s += 2.0 * D[i * P + i] * D[j * P + j] * Ge[1 * P3 + q];
+                    s += 2.0 * D[i * P + i] * D[k * P + k] * Ge[2 * P3 + q];
+                    s += 2.0 * D[j * P + j] * D[k * P + k] * Ge[4 * P3 + q];
+                    diag[e * P3 + q] = s;
+                }
+    }
+    double *sum = (double *)malloc(sizeof(double) * n_glob);
+    or_gs(E * P3, glob_id, n_glob, diag, sum);
+    free(sum);
+}
+
+/* f4. Jacobi-preconditioned CG: Algorithm 1 with z = M^-1 r (M the
+ * diagonal of A on the free points; minv = 1/diag there and 0 on the
+ * Dirichlet points): p_i = z_{i-1} + beta p_{i-1}, alpha = <r,z>/<p,w>,
+ * beta = <r_i,z_i>/<r_{i-1},z_{i-1}>.  The stopping test is the same as
+ * or_cg's, on <r, r, c>.  Histories as or_cg, rho_hist holding <r, r, c>.
+ * Returns the number of iterations done. */
+int or_pcg(long E, int N, const double *D, const double *G, const int64_t *glob_id,
+           long n_glob, const uint8_t *dirichlet, const double *m, const double *minv,
+           const double *b, double *x, double tol, int max_iter, int fixed,
+           double *rho_hist, double *alpha_hist, double *beta_hist)
+{
+    long n = E * (long)(N + 1) * (N + 1) * (N + 1);
+    or_op op = {E, N, n, n_glob, D, G, glob_id, dirichlet,
+                (double *)malloc(sizeof(double) * n_glob)};
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    apply_A(&op, x, w);
+    for (long l = 0; l < n; ++l) r[l] = b[l] - w[l];      /* r0 = b - A x0 */
+    for (long l = 0; l < n; ++l) z[l] = minv[l] * r[l];   /* z0 = M^-1 r0 */
+    double beta = 0.0;
+    for (long l = 0; l < n; ++l) p[l] = 0.0;
+    double rz_prev = or_dot(n, r, z, m);
+    double rr0 = or_dot(n, r, r, m);
+    if (rho_hist) rho_hist[0] = rr0;
+    int it = 0;
+    int limit = fixed > 0 ? fixed : max_iter;
+    if (fixed <= 0 && rr0 == 0.0) limit = 0;
+    for (int i = 1; i <= limit; ++i) {
+        for (long l = 0; l < n; ++l) p[l] = z[l] + beta * p[l];
+        apply_A(&op, p, w);
+        double alpha = rz_prev / or_dot(n, p, w, m);
+        for (long l = 0; l < n; ++l) x[l] += alpha * p[l];
+        for (long l = 0; l < n; ++l) r[l] -= alpha * w[l];
+        for (long l = 0; l < n; ++l) z[l] = minv[l] * r[l];
+        double rz = or_dot(n, r, z, m);
+        double rr = or_dot(n, r, r, m);
+        beta = rz / rz_prev;
+        if (rho_hist) rho_hist[i] = rr;
+        if (alpha_hist) alpha_hist[i] = alpha;
+        if (beta_hist) beta_hist[i] = beta;
+        rz_prev = rz;
+        it = i;
+        if (fixed <= 0 && sqrt(rr / rr0) <= tol) break;
+    }
+    free(r); free(z); free(p); free(w); free(op.sum);
+    return it;
+}
