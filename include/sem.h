@@ -134,6 +134,16 @@ sem_status sem_dot(sem_mesh_t mesh, sem_precision prec, const void *a_dev,
                    const void *b_dev, double *out_dev, void *hip_stream);
 
 /*
+ * Diagonal of the assembled operator A = Q^T A_L Q (Eq. 4) in local form
+ * (unmasked): the element diagonals (A_L)_qq = sum_{a,b} sum_q' (D_a)_{q'q}
+ * G_ab(q') (D_b)_{q'q}, formed in FP64 from the vertices whatever G form the
+ * mesh stores, summed over the copies of every global point in ascending
+ * local index.  This is the M of the Jacobi preconditioner
+ * (SEM_PRECOND_JACOBI).  diag_dev: DEVICE double [n_local], written.
+ */
+sem_status sem_diag(sem_mesh_t mesh, double *diag_dev, void *hip_stream);
+
+/*
  * Physical coordinates of every local GLL point: xyz_dev is a DEVICE double
  * buffer [3][n_local] (x block, then y, then z).
  */
@@ -147,6 +157,17 @@ sem_status sem_coords(sem_mesh_t mesh, double *xyz_dev, void *hip_stream);
  */
 sem_status sem_rhs(sem_mesh_t mesh, sem_precision prec, const double *f_dev, void *b_dev,
                    void *hip_stream);
+
+/*
+ * Preconditioner of the CG (Sec. 2 names the preconditioner among the
+ * components of CG; Algorithm 1 itself is unpreconditioned).
+ * SEM_PRECOND_JACOBI: M = diagonal of the assembled operator A = Q^T A_L Q
+ * (Eq. 4), formed once per mesh in FP64 from the vertices: the element
+ * diagonals (A_L)_qq summed over the copies of every global point; the
+ * update then applies z = M^-1 r on the free points (0 on Dirichlet
+ * points), p = z + beta p, and alpha, beta use <r, z, c>.
+ */
+typedef enum { SEM_PRECOND_NONE = 0, SEM_PRECOND_JACOBI = 1 } sem_precond;
 
 typedef struct {
     sem_precision prec;   /* SEM_FP64, SEM_FP32, or SEM_MIXED (FP32 inner CG + FP64 outer) */
@@ -166,6 +187,9 @@ typedef struct {
                              the gather-scatter kernel and the update kernel of one CG
                              iteration, timed with HIP events on the solver's stream.
                              When set, iterations are launched without graphs. */
+    int precond;          /* sem_precond (sem_cg_solve only; batches and the server take
+                             SEM_PRECOND_NONE).  With a preconditioner the stopping test,
+                             rel_res_recursive and hist_rho stay on <r, r, c>. */
 } sem_cg_opts;
 
 typedef struct {
@@ -179,7 +203,8 @@ typedef struct {
 } sem_cg_result;
 
 /*
- * Solve A x = b with Algorithm 1 (unpreconditioned CG): A = mask o QQ^T o A_L.
+ * Solve A x = b with Algorithm 1 (CG; unpreconditioned unless opts->precond
+ * names one): A = mask o QQ^T o A_L.
  * b, x: DEVICE buffers in local form (continuous, masked), double for
  * SEM_FP64 / SEM_MIXED, float for SEM_FP32.  x holds the initial guess on
  * entry (its Dirichlet entries are zeroed) and the iterate on return.

@@ -14,10 +14,12 @@ import numpy as np
 
 __all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_set",
            "ax_shape_get", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
+           "PRECOND_NONE", "PRECOND_JACOBI",
            "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
 PRECOMPUTED, ON_THE_FLY = 0, 1
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
 G_FP32, G_FP64 = 0x1, 0x2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,7 +38,7 @@ class CgOpts(C.Structure):
                 ("max_outer", C.c_int), ("poll_every", C.c_int), ("use_graph", C.c_int),
                 ("true_residual", C.c_int), ("hist_rho", C.c_void_p),
                 ("hist_alpha", C.c_void_p), ("hist_len", C.c_int),
-                ("kernel_ms", C.c_void_p)]
+                ("kernel_ms", C.c_void_p), ("precond", C.c_int)]
 
 
 class CgResult(C.Structure):
@@ -57,7 +59,7 @@ class MeshInfo(C.Structure):
 
 _lib = None
 EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "sem_gs",
-           "sem_dot", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
+           "sem_dot", "sem_diag", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
            "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
            "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_ax_shape_set",
            "sem_ax_shape_get", "sem_last_error", "sem_version"]
@@ -85,6 +87,7 @@ def lib():
     L.sem_gs.argtypes = [vp, i32, vp, i32, vp]
     L.sem_dot.argtypes = [vp, i32, vp, vp, vp, vp]
     L.sem_coords.argtypes = [vp, vp, vp]
+    L.sem_diag.argtypes = [vp, vp, vp]
     L.sem_rhs.argtypes = [vp, i32, vp, vp, vp]
     L.sem_cg_solve.argtypes = [vp, C.POINTER(CgOpts), vp, vp, C.POINTER(CgResult), vp]
     L.sem_batch_create.argtypes = [i32, vp, C.POINTER(vp)]
@@ -220,6 +223,14 @@ class Mesh:
                              _stream(stream)))
         return o if out is not None else float(o.item())
 
+    def diag(self, stream=None):
+        """Diagonal of the assembled operator in local form (float64 device
+        tensor; the Jacobi preconditioner's M)."""
+        torch = _torch()
+        d = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(lib().sem_diag(self.handle, C.c_void_p(d.data_ptr()), _stream(stream)))
+        return d
+
     def coords(self, stream=None):
         torch = _torch()
         xyz = torch.empty(3 * self.n, dtype=torch.float64, device="cuda")
@@ -239,8 +250,9 @@ class Mesh:
                  tol: float = 1e-8, max_iter: int = 100000, fixed_iters: int = 0,
                  inner_tol: float = 0.0, max_outer: int = 0, poll_every: int = 0,
                  use_graph: bool = True, true_residual: bool = False, history: int = 0,
-                 kernel_times: bool = False, stream=None):
-        """Algorithm 1 (or its mixed-precision refinement).  Returns (x, result dict)."""
+                 kernel_times: bool = False, precond: int = PRECOND_NONE, stream=None):
+        """Algorithm 1 (or its mixed-precision refinement), optionally
+        Jacobi-preconditioned.  Returns (x, result dict)."""
         torch = _torch()
         if prec is None:
             prec = _prec_of(b)
@@ -252,7 +264,7 @@ class Mesh:
         opts = CgOpts(prec=prec, geom=geom, tol=tol, max_iter=max_iter,
                       fixed_iters=fixed_iters, inner_tol=inner_tol, max_outer=max_outer,
                       poll_every=poll_every, use_graph=1 if use_graph else 0,
-                      true_residual=1 if true_residual else 0, hist_len=0)
+                      true_residual=1 if true_residual else 0, hist_len=0, precond=precond)
         hr = ha = None
         if history > 0:
             hr = np.zeros(history)

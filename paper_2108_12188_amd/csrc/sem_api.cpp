@@ -203,6 +203,18 @@ sem_status sem_dot(sem_mesh_t mesh, sem_precision prec, const void *a_dev, const
     });
 }
 
+sem_status sem_diag(sem_mesh_t mesh, double *diag_dev, void *hip_stream) {
+    return guarded([&]() -> sem_status {
+        Mesh *m = as_mesh(mesh);
+        need(diag_dev, "diag_dev");
+        DeviceGuard dg(m->device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        launch_diag_local(*m, diag_dev, s);
+        launch_gs<double>(*m, diag_dev, s);
+        return SEM_OK;
+    });
+}
+
 sem_status sem_coords(sem_mesh_t mesh, double *xyz_dev, void *hip_stream) {
     return guarded([&]() -> sem_status {
         Mesh *m = as_mesh(mesh);
@@ -259,6 +271,8 @@ sem_status sem_cg_solve(sem_mesh_t mesh, const sem_cg_opts *opts, const void *b_
             fail(SEM_EINVAL, "unknown geometry form");
         if (opts->hist_len < 0 || ((opts->hist_rho || opts->hist_alpha) && opts->hist_len == 0))
             fail(SEM_EINVAL, "history buffers need hist_len > 0");
+        if (opts->precond != SEM_PRECOND_NONE && opts->precond != SEM_PRECOND_JACOBI)
+            fail(SEM_EINVAL, "unknown preconditioner");
         DeviceGuard dg(m->device);
         sem_cg_result r{};
         const sem_status st =
@@ -296,6 +310,8 @@ sem_status sem_batch_solve(sem_batch_t batch, const sem_cg_opts *opts, const voi
             fail(SEM_EINVAL, "tol must be positive unless fixed_iters > 0");
         if (opts->geom != SEM_G_PRECOMPUTED && opts->geom != SEM_G_ON_THE_FLY)
             fail(SEM_EINVAL, "unknown geometry form");
+        if (opts->precond != SEM_PRECOND_NONE)
+            fail(SEM_EUNSUPPORTED, "batched solves take no preconditioner");
         BatchImpl &B = *reinterpret_cast<BatchImpl *>(batch);
         const sem_status st =
             batch_solve(B, *opts, b_dev, x_dev, results, static_cast<hipStream_t>(hip_stream));
@@ -308,6 +324,8 @@ sem_status sem_server_create(const sem_cg_opts *opts, int round_iters, sem_serve
     return guarded([&]() -> sem_status {
         need(opts, "opts");
         need(out, "out");
+        if (opts->precond != SEM_PRECOND_NONE)
+            fail(SEM_EUNSUPPORTED, "the server takes no preconditioner");
         *out = reinterpret_cast<sem_server_t>(server_new(*opts, round_iters));
         return SEM_OK;
     });

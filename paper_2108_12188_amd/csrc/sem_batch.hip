@@ -529,7 +529,7 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
             res[q].iters = h.iter;
             res[q].status = h.stop;
             res[q].converged = h.stop == 1;
-            res[q].rel_res_recursive = h.rho0 > 0 ? std::sqrt(h.rho / h.rho0) : 0.0;
+            res[q].rel_res_recursive = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;
             res[q].rel_res_true = -1.0;
             breakdown |= h.stop == 3;
         }
@@ -607,7 +607,7 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
                 const CgState &h = *w32.h_st;
                 total[q] += h.iter;
                 last_stop[q] = h.stop;
-                inner_rel[q] = h.rho0 > 0 ? std::sqrt(h.rho / h.rho0) : 0.0;
+                inner_rel[q] = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;
                 if (h.stop == 3) {
                     done[q] = 3;
                     continue;
@@ -811,7 +811,7 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
             const CgState &h = *w32.h_st;
             r.total += h.iter;
             r.last_stop = h.stop;
-            r.inner_rel = h.rho0 > 0 ? std::sqrt(h.rho / h.rho0) : 0.0;
+            r.inner_rel = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;
             if (h.stop == 3) {
                 r.broken = true;
             } else {

@@ -10,6 +10,9 @@
 //   3. r -= alpha mask(w) and the partials of rho = <r, r, c>, then a
 //      one-block kernel forms beta and runs the convergence test.
 // After the last iteration a flush applies the pending x += alpha p.
+// With the Jacobi preconditioner step 3 also writes z = M^-1 r and reduces
+// <r, z, c> (which drives beta) beside <r, r, c> (the stopping test), and
+// step 1 forms p from z.
 // When every shared point lies on an element's surface (any conforming
 // mesh), step 2 only writes the sums of the groups of more than two copies
 // (edge and vertex nodes) to a compact array, and step 3 forms (QQ^T w)_l
@@ -34,8 +37,9 @@ namespace {
 void ws_free(Workspace *ws) {
     if (!ws) return;
     for (auto &kv : ws->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *dev[] = {ws->x, ws->r, ws->p, ws->w, ws->b, ws->gsum, ws->wedge, ws->part_ax, ws->part_vec,
-                   ws->st, ws->hist, ws->dval};
+    void *dev[] = {ws->x,       ws->r,        ws->p,  ws->w,    ws->b,   ws->gsum,
+                   ws->wedge,   ws->part_ax,  ws->part_vec, ws->z, ws->part_vec2, ws->st,
+                   ws->hist,    ws->dval};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     if (ws->h_st) (void)hipHostFree(ws->h_st);
@@ -98,6 +102,57 @@ Workspace &get_ws(Mesh &m, bool fp64) {
     return *slot;
 }
 
+// Jacobi preconditioner of the mesh (both precisions) and the workspace's
+// z vector and second partial set, built on first use.  M = diag(Q^T A_L Q):
+// element diagonals from the FP64 geometry, summed over the copies of each
+// global point by the gather-scatter; minv = 1/M on the free points.
+void ensure_jacobi(Mesh &m, Workspace &ws) {
+    if (!m.minv64) {
+        hipStream_t s = ws.stream;
+        double *d = nullptr, *m64 = nullptr;
+        float *m32 = nullptr;
+        auto alloc = [&](void **q, size_t bytes) {
+            if (hipMalloc(q, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                if (d) (void)hipFree(d);
+                if (m64) (void)hipFree(m64);
+                fail(SEM_ENOMEM, "Jacobi preconditioner allocation failed");
+            }
+        };
+        alloc((void **)&d, sizeof(double) * m.n);
+        alloc((void **)&m64, sizeof(double) * m.n);
+        alloc((void **)&m32, sizeof(float) * m.n);
+        launch_diag_local(m, d, s);
+        launch_gs<double>(m, d, s);
+        launch_jacobi_invert(m, d, m64, m32, s);
+        const hipError_t e = hipStreamSynchronize(s);
+        (void)hipFree(d);
+        if (e != hipSuccess) {
+            (void)hipFree(m64);
+            (void)hipFree(m32);
+            check_hip(e, "Jacobi preconditioner setup");
+        }
+        m.minv64 = m64;
+        m.minv32 = m32;
+        m.device_bytes += 12 * (size_t)m.n;
+    }
+    if (!ws.z) {
+        ws.z = ws_alloc<char>(ws, (size_t)m.n * (ws.fp64 ? 8 : 4));
+        ws.part_vec2 = ws_alloc<double>(ws, ws.cap_vec);
+    }
+}
+
+template <typename T>
+PcArgs<T> pc_args(const Mesh &m, Workspace &ws, bool pc) {
+    PcArgs<T> a{};
+    if (!pc) return a;
+    if constexpr (sizeof(T) == 8) a.minv = m.minv64;
+    else a.minv = m.minv32;
+    a.z = static_cast<T *>(ws.z);
+    a.partial2 = ws.part_vec2;
+    return a;
+}
+
 void ensure_hist(Workspace &ws, int len) {
     if (len <= ws.hist_cap) return;
     if (ws.hist) {
@@ -116,13 +171,14 @@ void ensure_hist(Workspace &ws, int len) {
 // recorded before and after each step
 // ---------------------------------------------------------------------------
 template <typename T>
-void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
+void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, bool pc, hipStream_t s,
                        hipEvent_t *ev = nullptr) {
     T *x = static_cast<T *>(ws.x), *r = static_cast<T *>(ws.r);
     T *p = static_cast<T *>(ws.p), *w = static_cast<T *>(ws.w);
     T *gsum = static_cast<T *>(ws.gsum), *wedge = static_cast<T *>(ws.wedge);
+    const PcArgs<T> pa = pc_args<T>(m, ws, pc);
     AxArgs<T> a{};
-    a.u = r;
+    a.u = pc ? pa.z : r;
     a.p = p;
     a.w = w;
     a.st = ws.st;
@@ -136,8 +192,8 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, hipStream_t s,
     if (m.gs_in_update) launch_group_sums_cg<T>(m, w, wedge, gsum, ws.st, ws.part_ax, (int)nax, s);
     else launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     if (ev) SEM_HIP(hipEventRecord(ev[2], s));
-    if (m.gs_in_update) launch_update_gather<T>(m, r, w, gsum, ws.st, ws.part_vec, s);
-    else launch_update<T>(m, r, w, ws.st, ws.part_vec, s);
+    if (m.gs_in_update) launch_update_gather<T>(m, r, w, gsum, ws.st, ws.part_vec, s, pa);
+    else launch_update<T>(m, r, w, ws.st, ws.part_vec, s, pa);
     if (ev) SEM_HIP(hipEventRecord(ev[3], s));
 }
 
@@ -147,15 +203,15 @@ struct KernelTimes {
 };
 
 template <typename T>
-void run_chunk_timed(const Mesh &m, Workspace &ws, bool otf, int chunk, int iter_before,
-                     KernelTimes &kt) {
+void run_chunk_timed(const Mesh &m, Workspace &ws, bool otf, bool pc, int chunk,
+                     int iter_before, KernelTimes &kt) {
     hipStream_t s = ws.stream;
     while ((int)ws.tev.size() < 4 * chunk) {
         hipEvent_t e = nullptr;
         SEM_HIP(hipEventCreate(&e));
         ws.tev.push_back(e);
     }
-    for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, s, &ws.tev[4 * c]);
+    for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, pc, s, &ws.tev[4 * c]);
     SEM_HIP(hipMemcpyAsync(ws.h_st, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
     const int done = std::min(chunk, ws.h_st->iter - iter_before);
@@ -169,19 +225,19 @@ void run_chunk_timed(const Mesh &m, Workspace &ws, bool otf, int chunk, int iter
 }
 
 template <typename T>
-void run_chunk(const Mesh &m, Workspace &ws, bool otf, int chunk, bool use_graph) {
+void run_chunk(const Mesh &m, Workspace &ws, bool otf, bool pc, int chunk, bool use_graph) {
     hipStream_t s = ws.stream;
     if (!use_graph) {
-        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, s);
+        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, pc, s);
         return;
     }
-    const GraphKey key{otf, chunk, ax_shape_generation()};
+    const GraphKey key{otf, chunk, ax_shape_generation(), pc};
     auto it = ws.graphs.find(key);
     if (it == ws.graphs.end()) {
         hipGraph_t g = nullptr;
         SEM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, s);
+            for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(m, ws, otf, pc, s);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(s, &junk);
@@ -232,8 +288,9 @@ struct InnerOut {
 
 // Runs Algorithm 1 on ws (x, r, p, w) for right-hand side b_dev (device, T).
 // x0_zero: the initial guess is zero (r0 = b, no operator application).
+// pc: Jacobi-preconditioned (ensure_jacobi has run for m and ws).
 template <typename T>
-InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, bool otf,
+InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, bool otf, bool pc,
                  double tol, int max_iter, int fixed, int chunk, bool use_graph, int hist_len,
                  KernelTimes *kt = nullptr) {
     hipStream_t s = ws.stream;
@@ -252,13 +309,14 @@ InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, boo
     SEM_HIP(hipMemcpyAsync(ws.st, ws.h_st, sizeof(CgState), hipMemcpyHostToDevice, s));
     T *x = static_cast<T *>(ws.x), *r = static_cast<T *>(ws.r);
     T *p = static_cast<T *>(ws.p), *w = static_cast<T *>(ws.w);
+    const PcArgs<T> pa = pc_args<T>(m, ws, pc);
     if (x0_zero) {
         SEM_HIP(hipMemsetAsync(x, 0, sizeof(T) * m.n, s));
-        launch_cg_init<T>(m, b_dev, nullptr, r, p, ws.st, ws.part_vec, s);
+        launch_cg_init<T>(m, b_dev, nullptr, r, p, ws.st, ws.part_vec, s, pa);
     } else {
         launch_mask<T>(m, x, s);
         apply_A<T>(m, otf, x, w, s);
-        launch_cg_init<T>(m, b_dev, w, r, p, ws.st, ws.part_vec, s);
+        launch_cg_init<T>(m, b_dev, w, r, p, ws.st, ws.part_vec, s, pa);
     }
     // every chunk advances the iteration count by `chunk` until the state
     // stops; a chunk that does not advance it means the device state is
@@ -272,15 +330,15 @@ InnerOut cg_core(const Mesh &m, Workspace &ws, const T *b_dev, bool x0_zero, boo
             fail(SEM_EDEVICE, "CG state did not advance (iteration " +
                                   std::to_string(ws.h_st->iter) + ")");
         last_iter = ws.h_st->iter;
-        if (kt) run_chunk_timed<T>(m, ws, otf, chunk, last_iter, *kt);
-        else run_chunk<T>(m, ws, otf, chunk, use_graph);
+        if (kt) run_chunk_timed<T>(m, ws, otf, pc, chunk, last_iter, *kt);
+        else run_chunk<T>(m, ws, otf, pc, chunk, use_graph);
     }
     // the last completed iteration's x step
     launch_x_flush<T>(m, x, p, ws.st, s);
     InnerOut o;
     o.iters = ws.h_st->iter;
     o.stop = ws.h_st->stop;
-    o.rel = ws.h_st->rho0 > 0 ? std::sqrt(ws.h_st->rho / ws.h_st->rho0) : 0.0;
+    o.rel = ws.h_st->rho0 > 0 ? std::sqrt(ws.h_st->rr / ws.h_st->rho0) : 0.0;
     return o;
 }
 
@@ -332,6 +390,8 @@ static sem_status cg_plain(Mesh &m, const sem_cg_opts &o, const void *b_user, vo
     if (!otf && (fp64 ? m.G64 == nullptr : m.G32 == nullptr))
         fail(SEM_EUNSUPPORTED, "precomputed G of this precision was not built for the mesh");
     Workspace &ws = get_ws(m, fp64);
+    const bool pc = o.precond == SEM_PRECOND_JACOBI;
+    if (pc) ensure_jacobi(m, ws);
     SEM_HIP(hipEventRecord(ws.ev, user_s));
     SEM_HIP(hipStreamWaitEvent(ws.stream, ws.ev, 0));
     const T *b = static_cast<const T *>(b_user);
@@ -339,7 +399,7 @@ static sem_status cg_plain(Mesh &m, const sem_cg_opts &o, const void *b_user, vo
     const int chunk = o.poll_every > 0 ? o.poll_every : auto_chunk(m.n, o.fixed_iters);
     const int hist_len = (o.hist_rho || o.hist_alpha) ? o.hist_len : 0;
     KernelTimes kt;
-    InnerOut io = cg_core<T>(m, ws, b, false, otf, o.tol, o.max_iter, o.fixed_iters, chunk,
+    InnerOut io = cg_core<T>(m, ws, b, false, otf, pc, o.tol, o.max_iter, o.fixed_iters, chunk,
                              o.use_graph != 0, hist_len, o.kernel_ms ? &kt : nullptr);
     if (o.kernel_ms)
         for (int k = 0; k < 3; ++k) o.kernel_ms[k] = kt.count ? kt.ms[k] / kt.count : 0.0;
@@ -373,6 +433,8 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
         fail(SEM_EUNSUPPORTED, "precomputed FP32 G was not built for the mesh");
     Workspace &w64 = get_ws(m, true);
     Workspace &w32 = get_ws(m, false);
+    const bool pc = o.precond == SEM_PRECOND_JACOBI;
+    if (pc) ensure_jacobi(m, w32);
     SEM_HIP(hipEventRecord(w64.ev, user_s));
     SEM_HIP(hipStreamWaitEvent(w64.stream, w64.ev, 0));
     hipStream_t s = w64.stream;
@@ -410,7 +472,7 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
         launch_scale_to_f32(m.n, r64, w64.dval + 0, b32, s);
         SEM_HIP(hipEventRecord(w64.ev, s));
         SEM_HIP(hipStreamWaitEvent(w32.stream, w64.ev, 0));
-        InnerOut io = cg_core<float>(m, w32, b32, true, otf, inner_tol, inner_cap, 0, chunk,
+        InnerOut io = cg_core<float>(m, w32, b32, true, otf, pc, inner_tol, inner_cap, 0, chunk,
                                      o.use_graph != 0, 0, o.kernel_ms ? &kt : nullptr);
         total += io.iters;
         last_stop = io.stop;

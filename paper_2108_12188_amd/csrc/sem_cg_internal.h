@@ -15,7 +15,9 @@ struct GraphKey {
     bool otf;
     int chunk;
     int shape_gen;
+    bool pc = false;
     bool operator<(const GraphKey &o) const {
+        if (pc != o.pc) return pc < o.pc;
         if (otf != o.otf) return otf < o.otf;
         if (chunk != o.chunk) return chunk < o.chunk;
         return shape_gen < o.shape_gen;
@@ -30,6 +32,8 @@ struct Workspace {
     void *gsum = nullptr;           // sums of the groups with m > 2 (gather in the update)
     void *wedge = nullptr;          // operator's copy of the edge and corner nodes
     double *part_ax = nullptr, *part_vec = nullptr;
+    void *z = nullptr;              // preconditioned residual (allocated on first use)
+    double *part_vec2 = nullptr;    // second partial set of the preconditioned update
     int64_t cap_ax = 0;
     int cap_vec = 0;
     CgState *st = nullptr;          // device state of this workspace's solves

@@ -66,6 +66,29 @@ __device__ __forceinline__ double dotv(const double a[3], const double b[3]) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// The six factors (G11, G12, G13, G22, G23, G33) at GLL point (i, j, k)
+// of the element with vertices v; returns |J| (weights w, points xi).
+__device__ double gfactors(const double *v, const double *xi, const double *w, int i, int j,
+                           int k, double G[6], double *wq_out = nullptr) {
+    double Jx[3], Jy[3], Jz[3];
+    jac_columns(v, xi[i], xi[j], xi[k], Jx, Jy, Jz);
+    double r0[3], r1[3], r2[3];
+    cross3(Jy, Jz, r0);
+    cross3(Jz, Jx, r1);
+    cross3(Jx, Jy, r2);
+    const double det = dotv(Jx, r0);
+    const double wq = w[i] * w[j] * w[k];
+    const double s = wq / det;
+    G[0] = s * dotv(r0, r0);
+    G[1] = s * dotv(r0, r1);
+    G[2] = s * dotv(r0, r2);
+    G[3] = s * dotv(r1, r1);
+    G[4] = s * dotv(r1, r2);
+    G[5] = s * dotv(r2, r2);
+    if (wq_out) *wq_out = wq;
+    return det;
+}
+
 __global__ void geometry_kernel(GeomArgs g) {
     const int P = g.P, P2 = P * P, P3 = P2 * P;
     const int64_t n = g.E * P3;
@@ -74,24 +97,50 @@ __global__ void geometry_kernel(GeomArgs g) {
     const int64_t e = l / P3;
     const int q = (int)(l - e * P3);
     const int i = q % P, j = (q / P) % P, k = q / P2;
-    double Jx[3], Jy[3], Jz[3];
-    jac_columns(g.vert + 24 * e, g.xi[i], g.xi[j], g.xi[k], Jx, Jy, Jz);
-    double r0[3], r1[3], r2[3];
-    cross3(Jy, Jz, r0);
-    cross3(Jz, Jx, r1);
-    cross3(Jx, Jy, r2);
-    const double det = dotv(Jx, r0);
-    const double wq = g.w[i] * g.w[j] * g.w[k];
+    double G[6], wq = 0.0;
+    const double det = gfactors(g.vert + 24 * e, g.xi, g.w, i, j, k, G, &wq);
     if (!(det > 0.0)) atomicMin(g.bad, (unsigned long long)e);
-    const double s = wq / det;
-    const double G[6] = {s * dotv(r0, r0), s * dotv(r0, r1), s * dotv(r0, r2),
-                         s * dotv(r1, r1), s * dotv(r1, r2), s * dotv(r2, r2)};
     const int64_t gb = e * 6 * P3 + q;
     if (g.G64)
         for (int c = 0; c < 6; ++c) g.G64[gb + (int64_t)c * P3] = G[c];
     if (g.G32)
         for (int c = 0; c < 6; ++c) g.G32[gb + (int64_t)c * P3] = (float)G[c];
     g.B64[l] = wq * det;
+}
+
+// Diagonal of the element operator A_L = sum_{a,b} D_a^T G_ab D_b (Eq. 4)
+// at local point q = (i, j, k): the unit vector e_q has derivative
+// D[l][i] along the i-line through q (likewise j, k), so the diagonal
+// blocks contribute sum_l D[l][i]^2 G11(l, j, k) (and the j-, k-lines),
+// and the mixed blocks, whose lines meet only at q, 2 D[i][i] D[j][j] G12(q)
+// and so on.  The factors come from the vertices (FP64), so the result
+// does not depend on which G form the mesh stores.
+__global__ void diag_local_kernel(int64_t E, int P, const double *vert, const double *xi,
+                                  const double *w, const double *D, double *diag) {
+    const int P2 = P * P, P3 = P2 * P;
+    const int64_t n = E * P3;
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const int64_t e = l / P3;
+    const int q = (int)(l - e * P3);
+    const int i = q % P, j = (q / P) % P, k = q / P2;
+    const double *v = vert + 24 * e;
+    double G[6];
+    double s = 0.0;
+    for (int t = 0; t < P; ++t) {
+        gfactors(v, xi, w, t, j, k, G);
+        s += D[t * P + i] * D[t * P + i] * G[0];
+        gfactors(v, xi, w, i, t, k, G);
+        s += D[t * P + j] * D[t * P + j] * G[3];
+        gfactors(v, xi, w, i, j, t, G);
+        s += D[t * P + k] * D[t * P + k] * G[5];
+    }
+    gfactors(v, xi, w, i, j, k, G);
+    const double di = D[i * P + i], dj = D[j * P + j], dk = D[k * P + k];
+    s += 2.0 * di * dj * G[1];
+    s += 2.0 * di * dk * G[2];
+    s += 2.0 * dj * dk * G[4];
+    diag[l] = s;
 }
 
 __global__ void coords_kernel(int64_t E, int P, const double *vert, const double *xi,
@@ -135,6 +184,13 @@ int64_t launch_geometry(Mesh &m, hipStream_t s) {
     check_hip(ce, "geometry result copy");
     check_hip(se, "geometry kernel");
     return res == ~0ull ? -1 : (int64_t)res;
+}
+
+void launch_diag_local(const Mesh &m, double *d, hipStream_t s) {
+    const int64_t nb = (m.n + 255) / 256;
+    hipLaunchKernelGGL(diag_local_kernel, dim3((unsigned)nb), dim3(256), 0, s, m.E, m.P, m.vert64,
+                       m.b64.xi, m.b64.w, m.b64.D, d);
+    check_hip(hipGetLastError(), "diagonal kernel launch");
 }
 
 void launch_coords(const Mesh &m, double *xyz, hipStream_t s) {

@@ -61,12 +61,14 @@ void check_hip(hipError_t e, const char *what);
 // the kernels that follow in stream order.
 // ---------------------------------------------------------------------------
 struct CgState {
-    double rho;        // rho_{i-1}: <r, r, c> of the current residual
-    double rho0;       // rho_0
+    double rho;        // rho_{i-1}: <r, r, c> of the current residual (<r, z, c>
+                       // with a preconditioner)
+    double rr;         // <r, r, c> of the current residual
+    double rho0;       // <r0, r0, c>
     double alpha;      // alpha_i
     double beta;       // beta_{i-1} used by the next p-update
     double pw;         // <p, w, c> of the current iteration
-    double thresh;     // stop when rho <= thresh (= tol^2 rho_0)
+    double thresh;     // stop when rr <= thresh (= tol^2 rho_0)
     int iter;          // completed iterations
     int max_iter;      // iteration cap
     int stop;          // 0 running, 1 converged, 2 cap reached, 3 breakdown
@@ -147,6 +149,10 @@ struct Mesh {
     int32_t *wedge_idx = nullptr;
     uint32_t p3_magic = 0;
     int p3_shift = 0;
+    // Jacobi preconditioner (built on first use): 1 / diag(A) on the free
+    // points, 0 on the Dirichlet points, local form
+    double *minv64 = nullptr;
+    float *minv32 = nullptr;
     Basis<float> b32;
     Basis<double> b64;
     void *basis_blob = nullptr;
@@ -217,6 +223,16 @@ struct AxArgs {
                                 // x += alpha p_old (previous iteration's step)
 };
 
+// Jacobi preconditioning in the CG update (Sec. 2 lists it among the
+// preconditioners of CG): z = minv r is written, and the block partials of
+// <r, z, c> (partial) and <r, r, c> (partial2) are reduced.
+template <typename T>
+struct PcArgs {
+    const T *minv;      // null: no preconditioner
+    T *z;
+    double *partial2;
+};
+
 // Launch configuration chosen for an order (threads, elements per block,
 // dynamic LDS bytes).
 struct AxShape {
@@ -269,7 +285,7 @@ int vec_blocks(int64_t n);
 // advanced by the next operator launch or launch_x_flush)
 template <typename T>
 void launch_update(const Mesh &m, T *r, const T *w, CgState *st, double *partial,
-                   hipStream_t s);
+                   hipStream_t s, PcArgs<T> pc = PcArgs<T>{});
 // x += alpha p when st->x_lag (the step of the last completed update)
 template <typename T>
 void launch_x_flush(const Mesh &m, T *x, const T *p, const CgState *st, hipStream_t s);
@@ -278,11 +294,18 @@ void launch_x_flush(const Mesh &m, T *x, const T *p, const CgState *st, hipStrea
 // inside the update (needs m.gs_in_update).
 template <typename T>
 void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgState *st,
-                          double *partial, hipStream_t s);
-// r = b - w (w may be null: r = b); p = 0; rho_0 = <r, r, c>; initial state
+                          double *partial, hipStream_t s, PcArgs<T> pc = PcArgs<T>{});
+// r = b - w (w may be null: r = b); p = 0; rho_0 = <r, r, c>; initial state.
+// With pc.minv: z = minv r, rho = <r, z, c>, and the threshold and the
+// reported residual use <r, r, c>.
 template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
-                    double *partial, hipStream_t s);
+                    double *partial, hipStream_t s, PcArgs<T> pc = PcArgs<T>{});
+// Jacobi: minv = 1/d on free points, 0 on Dirichlet points (both precisions)
+void launch_jacobi_invert(const Mesh &m, const double *d, double *minv64, float *minv32,
+                          hipStream_t s);
+// d_l = (A_L)_{ll} of every local point from the geometry (FP64, unassembled)
+void launch_diag_local(const Mesh &m, double *d, hipStream_t s);
 // *out = <a, b, c>
 template <typename T>
 void launch_dot(const Mesh &m, const T *a, const T *b, double *out, double *partial,

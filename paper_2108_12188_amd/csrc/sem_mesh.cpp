@@ -33,7 +33,8 @@ void upload(T *dst, const T *src, size_t count, hipStream_t s) {
 void free_mesh_arrays(Mesh *m) {
     void *ptrs[] = {m->vert64,     m->vert32,  m->G32,     m->G64,       m->B64,
                     m->mcode,      m->gs_idx,  m->dir_idx, m->surf_slot, m->slink,
-                    m->wedge_idx,  m->basis_blob, m->scratch, m->state};
+                    m->wedge_idx,  m->basis_blob, m->scratch, m->state,   m->minv64,
+                    m->minv32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }

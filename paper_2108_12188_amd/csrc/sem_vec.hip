@@ -12,11 +12,12 @@ namespace {
 
 using namespace vecb;
 
-template <typename T>
+template <typename T, bool PC>
 __global__ void __launch_bounds__(kVecThreads)
 update_kernel(int64_t n, T *__restrict__ r, const T *__restrict__ w,
-              const uint8_t *__restrict__ mcode, CgState *st, double *partial) {
-    update_body<T, false>(n, nullptr, r, nullptr, w, mcode, st, partial, blockIdx.x, gridDim.x);
+              const uint8_t *__restrict__ mcode, CgState *st, double *partial, PcArgs<T> pc) {
+    update_body<T, false, PC>(n, nullptr, r, nullptr, w, mcode, st, partial, blockIdx.x,
+                              gridDim.x, pc);
 }
 
 // x += alpha p when the state says the last update's step is pending
@@ -30,17 +31,30 @@ x_flush_kernel(int64_t n, T *__restrict__ x, const T *__restrict__ p, const CgSt
         x[q] += a * p[q];
 }
 
-template <typename T>
+template <typename T, bool PC>
 __global__ void __launch_bounds__(kVecThreads)
 update_gather_kernel(int64_t n, T *__restrict__ r, const T *__restrict__ w,
                      const T *__restrict__ gsum, const uint8_t *__restrict__ mcode,
-                     const GatherMap gm, CgState *st, double *partial) {
-    update_gather_body<T>(n, r, w, gsum, mcode, gm, st, partial, blockIdx.x, gridDim.x);
+                     const GatherMap gm, CgState *st, double *partial, PcArgs<T> pc) {
+    update_gather_body<T, PC>(n, r, w, gsum, mcode, gm, st, partial, blockIdx.x, gridDim.x, pc);
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)
-finalize_rho_kernel(CgState *st, const double *partial, int cnt) {
-    finalize_rho_body(st, partial, cnt);
+finalize_rho_kernel(CgState *st, const double *partial, int cnt, const double *partial2) {
+    finalize_rho_body(st, partial, cnt, partial2);
+}
+
+// Jacobi preconditioner from the assembled diagonal d (local form):
+// minv = 1/d on the free points, 0 on the Dirichlet points.
+__global__ void __launch_bounds__(kVecThreads)
+jacobi_invert_kernel(int64_t n, const double *__restrict__ d, const uint8_t *__restrict__ mcode,
+                     double *__restrict__ minv64, float *__restrict__ minv32) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const double v = (mcode[q] & kDirichletBit) ? 0.0 : 1.0 / d[q];
+        minv64[q] = v;
+        minv32[q] = (float)v;
+    }
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)
@@ -49,33 +63,47 @@ finalize_alpha_kernel(CgState *st, const double *part_ax, int64_t n_ax) {
 }
 
 // r0 = b - A x0 (w holds A x0, or is null for x0 = 0); p0 = 0; beta_0 = 0;
-// rho_0 = <r0, r0, c>; the threshold becomes tol^2 rho_0.
+// rho_0 = <r0, r0, c>; the threshold becomes tol^2 rho_0.  With pc.minv:
+// z0 = minv r0, rho = <r0, z0, c> (partial) and <r0, r0, c> (partial2).
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
 cg_init_kernel(int64_t n, const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ r,
                T *__restrict__ p, const uint8_t *__restrict__ mcode, CgState *st,
-               double *partial) {
+               double *partial, PcArgs<T> pc) {
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
     weights_lds(cw);
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
         const T rv = w ? b[q] - w[q] : b[q];
         r[q] = rv;
         p[q] = T(0);
-        acc += (double)rv * (double)rv * cw[mcode[q]];
+        if (pc.minv) {
+            const T zv = pc.minv[q] * rv;
+            pc.z[q] = zv;
+            acc += (double)rv * (double)zv * cw[mcode[q]];
+            acc2 += (double)rv * (double)rv * cw[mcode[q]];
+        } else {
+            acc += (double)rv * (double)rv * cw[mcode[q]];
+        }
     }
     const double s = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (pc.minv) {
+        const double s2 = block_sum_f64(acc2, red);
+        if (threadIdx.x == 0) pc.partial2[blockIdx.x] = s2;
+    }
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)
-finalize_init_kernel(CgState *st, const double *partial, int cnt) {
+finalize_init_kernel(CgState *st, const double *partial, int cnt, const double *partial2) {
     __shared__ double red[16];
-    const double rho0 = sum_partials(partial, cnt, red);
+    const double rz0 = sum_partials(partial, cnt, red);
+    const double rho0 = partial2 ? sum_partials(partial2, cnt, red) : rz0;
     if (threadIdx.x == 0) {
-        st->rho = rho0;
+        st->rho = rz0;
+        st->rr = rho0;
         st->rho0 = rho0;
         st->thresh = st->thresh * rho0;
         st->beta = 0.0;
@@ -84,7 +112,7 @@ finalize_init_kernel(CgState *st, const double *partial, int cnt) {
         st->iter = 0;
         if (st->hist_rho && st->hist_len > 0) st->hist_rho[0] = rho0;
         int stop = 0;
-        if (!isfinite(rho0)) stop = 3;
+        if (!isfinite(rho0) || !isfinite(rz0)) stop = 3;
         else if (rho0 == 0.0) stop = 1;
         else if (st->max_iter <= 0) stop = 2;
         st->stop = stop;
@@ -176,13 +204,24 @@ int vec_blocks(int64_t n) {
 
 template <typename T>
 void launch_update(const Mesh &m, T *r, const T *w, CgState *st, double *partial,
-                   hipStream_t s) {
+                   hipStream_t s, PcArgs<T> pc) {
     const int nb = vec_blocks(m.n);
-    hipLaunchKernelGGL((update_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, r, w,
-                       m.mcode, st, partial);
+    if (pc.minv)
+        hipLaunchKernelGGL((update_kernel<T, true>), dim3(nb), dim3(kVecThreads), 0, s, m.n, r, w,
+                           m.mcode, st, partial, pc);
+    else
+        hipLaunchKernelGGL((update_kernel<T, false>), dim3(nb), dim3(kVecThreads), 0, s, m.n, r,
+                           w, m.mcode, st, partial, pc);
     hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
-                       (const double *)partial, nb);
+                       (const double *)partial, nb, (const double *)pc.partial2);
     check_hip(hipGetLastError(), "update kernel launch");
+}
+
+void launch_jacobi_invert(const Mesh &m, const double *d, double *minv64, float *minv32,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(jacobi_invert_kernel, dim3(elem_blocks(m.n)), dim3(kVecThreads), 0, s,
+                       m.n, d, m.mcode, minv64, minv32);
+    check_hip(hipGetLastError(), "jacobi invert kernel launch");
 }
 
 template <typename T>
@@ -194,26 +233,30 @@ void launch_x_flush(const Mesh &m, T *x, const T *p, const CgState *st, hipStrea
 
 template <typename T>
 void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgState *st,
-                          double *partial, hipStream_t s) {
+                          double *partial, hipStream_t s, PcArgs<T> pc) {
     if (!m.gs_in_update)
         fail(SEM_EUNSUPPORTED, "mesh shares points inside elements: no gather in the update");
     const GatherMap gm{m.surf_slot, m.slink, m.p3_magic, m.p3_shift, m.P3, m.S};
     const int nb = vec_blocks(m.n);
-    hipLaunchKernelGGL((update_gather_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, r, w,
-                       gsum, m.mcode, gm, st, partial);
+    if (pc.minv)
+        hipLaunchKernelGGL((update_gather_kernel<T, true>), dim3(nb), dim3(kVecThreads), 0, s,
+                           m.n, r, w, gsum, m.mcode, gm, st, partial, pc);
+    else
+        hipLaunchKernelGGL((update_gather_kernel<T, false>), dim3(nb), dim3(kVecThreads), 0, s,
+                           m.n, r, w, gsum, m.mcode, gm, st, partial, pc);
     hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
-                       (const double *)partial, nb);
+                       (const double *)partial, nb, (const double *)pc.partial2);
     check_hip(hipGetLastError(), "update kernel launch");
 }
 
 template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
-                    double *partial, hipStream_t s) {
+                    double *partial, hipStream_t s, PcArgs<T> pc) {
     const int nb = vec_blocks(m.n);
     hipLaunchKernelGGL((cg_init_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, b, w, r, p,
-                       m.mcode, st, partial);
+                       m.mcode, st, partial, pc);
     hipLaunchKernelGGL(finalize_init_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
-                       (const double *)partial, nb);
+                       (const double *)partial, nb, (const double *)pc.partial2);
     check_hip(hipGetLastError(), "cg init kernel launch");
 }
 
@@ -265,21 +308,22 @@ void launch_mul64(int64_t n, const double *a, const double *b, double *out, hipS
 }
 
 template void launch_update<float>(const Mesh &, float *, const float *, CgState *, double *,
-                                   hipStream_t);
+                                   hipStream_t, PcArgs<float>);
 template void launch_update<double>(const Mesh &, double *, const double *, CgState *, double *,
-                                    hipStream_t);
+                                    hipStream_t, PcArgs<double>);
 template void launch_x_flush<float>(const Mesh &, float *, const float *, const CgState *,
                                     hipStream_t);
 template void launch_x_flush<double>(const Mesh &, double *, const double *, const CgState *,
                                      hipStream_t);
 template void launch_update_gather<float>(const Mesh &, float *, const float *, const float *,
-                                          CgState *, double *, hipStream_t);
+                                          CgState *, double *, hipStream_t, PcArgs<float>);
 template void launch_update_gather<double>(const Mesh &, double *, const double *,
-                                           const double *, CgState *, double *, hipStream_t);
+                                           const double *, CgState *, double *, hipStream_t,
+                                           PcArgs<double>);
 template void launch_cg_init<float>(const Mesh &, const float *, const float *, float *, float *,
-                                    CgState *, double *, hipStream_t);
+                                    CgState *, double *, hipStream_t, PcArgs<float>);
 template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,
-                                     double *, CgState *, double *, hipStream_t);
+                                     double *, CgState *, double *, hipStream_t, PcArgs<double>);
 template void launch_dot<float>(const Mesh &, const float *, const float *, double *, double *,
                                 hipStream_t);
 template void launch_dot<double>(const Mesh &, const double *, const double *, double *,

@@ -29,19 +29,21 @@ __device__ __forceinline__ void weights_lds(double *cw) {
 // [x += alpha p;] r -= alpha mask(w); rho_i = <r, r, c>  (Algorithm 1:
 // mask, fused updates and reduction; the operator leaves w unmasked).
 // WithX = false leaves x to the next operator launch (single-mesh solves).
+// PC: also z = minv r, partial <- <r, z, c>, partial2 <- <r, r, c>.
 // Virtual block vb of a grid of vgrid blocks; the partial goes to
 // partial[vb].
-template <typename T, bool WithX>
+template <typename T, bool WithX, bool PC = false>
 __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__restrict__ r,
                                             const T *__restrict__ p, const T *__restrict__ w,
                                             const uint8_t *__restrict__ mcode, CgState *st,
-                                            double *partial, int64_t vb, int64_t vgrid) {
+                                            double *partial, int64_t vb, int64_t vgrid,
+                                            PcArgs<T> pc = PcArgs<T>{}) {
     if (st->stop) return;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
     weights_lds(cw);
     const T a = (T)st->alpha;
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
@@ -56,24 +58,44 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
             for (int t = 0; t < 4; ++t) xv.v[t] += a * pv.v[t];
             reinterpret_cast<Pack4<T> *>(x)[q] = xv;
         }
+        Pack4<T> mi{}, zv{};
+        if constexpr (PC) mi = reinterpret_cast<const Pack4<T> *>(pc.minv)[q];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const T wm = (mv.v[t] & kDirichletBit) ? T(0) : wv.v[t];
             rv.v[t] -= a * wm;
             const double rd = (double)rv.v[t];
-            acc += rd * rd * cw[mv.v[t]];
+            if constexpr (PC) {
+                zv.v[t] = mi.v[t] * rv.v[t];
+                acc += rd * (double)zv.v[t] * cw[mv.v[t]];
+                acc2 += rd * rd * cw[mv.v[t]];
+            } else {
+                acc += rd * rd * cw[mv.v[t]];
+            }
         }
         reinterpret_cast<Pack4<T> *>(r)[q] = rv;
+        if constexpr (PC) reinterpret_cast<Pack4<T> *>(pc.z)[q] = zv;
     }
     for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
         const uint8_t c = mcode[q];
         if constexpr (WithX) x[q] += a * p[q];
         const T rn = r[q] - a * ((c & kDirichletBit) ? T(0) : w[q]);
         r[q] = rn;
-        acc += (double)rn * (double)rn * cw[c];
+        if constexpr (PC) {
+            const T zn = pc.minv[q] * rn;
+            pc.z[q] = zn;
+            acc += (double)rn * (double)zn * cw[c];
+            acc2 += (double)rn * (double)rn * cw[c];
+        } else {
+            acc += (double)rn * (double)rn * cw[c];
+        }
     }
     const double s = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partial[vb] = s;
+    if constexpr (PC) {
+        const double s2 = block_sum_f64(acc2, red);
+        if (threadIdx.x == 0) pc.partial2[vb] = s2;
+    }
 }
 
 // Where the sums over the copies are formed inside the update (the tables
@@ -137,13 +159,14 @@ __host__ __device__ __forceinline__ T copies_sum(T own, uint8_t code, T src) {
 // per step, each costing two dependent rounds of loads, all loads of both
 // issued before any result is used; the sum of r^2/m still runs pack by
 // pack in the thread's order q, q + stride, q + 2 stride, ...
-template <typename T>
+template <typename T, bool PC = false>
 __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
                                                    const T *__restrict__ w,
                                                    const T *__restrict__ gsum,
                                                    const uint8_t *__restrict__ mcode,
                                                    const GatherMap &gm, CgState *st,
-                                                   double *partial, int64_t vb, int64_t vgrid) {
+                                                   double *partial, int64_t vb, int64_t vgrid,
+                                                   PcArgs<T> pc = PcArgs<T>{}) {
     if (st->stop) return;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
@@ -151,7 +174,7 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
     for (int q = threadIdx.x; q < gm.P3; q += blockDim.x) slot[q] = gm.surf_slot[q];
     weights_lds(cw);
     const T a = (T)st->alpha;
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
@@ -184,14 +207,23 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const bool live = h == 0 || two;
+            Pack4<T> mi{}, zv{};
+            if constexpr (PC) mi = reinterpret_cast<const Pack4<T> *>(pc.minv)[qq[h]];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const T wg = copies_sum<T>(wv[h].v[t], mv[h].v[t], src[h][t]);
                 rv[h].v[t] -= a * wg;
                 const double rd = (double)rv[h].v[t];
-                acc += live ? rd * rd * cw[mv[h].v[t]] : 0.0;
+                if constexpr (PC) {
+                    zv.v[t] = mi.v[t] * rv[h].v[t];
+                    acc += live ? rd * (double)zv.v[t] * cw[mv[h].v[t]] : 0.0;
+                    acc2 += live ? rd * rd * cw[mv[h].v[t]] : 0.0;
+                } else {
+                    acc += live ? rd * rd * cw[mv[h].v[t]] : 0.0;
+                }
             }
             reinterpret_cast<Pack4<T> *>(r)[qq[h]] = rv[h];
+            if constexpr (PC) reinterpret_cast<Pack4<T> *>(pc.z)[qq[h]] = zv;
         }
     }
     for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
@@ -200,29 +232,45 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
         const T wg = copies_sum<T>(w[q], c, *gather_source<T>(w, gsum, c, lk, q));
         const T rn = r[q] - a * wg;
         r[q] = rn;
-        acc += (double)rn * (double)rn * cw[c];
+        if constexpr (PC) {
+            const T zn = pc.minv[q] * rn;
+            pc.z[q] = zn;
+            acc += (double)rn * (double)zn * cw[c];
+            acc2 += (double)rn * (double)rn * cw[c];
+        } else {
+            acc += (double)rn * (double)rn * cw[c];
+        }
     }
     const double s = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partial[vb] = s;
+    if constexpr (PC) {
+        const double s2 = block_sum_f64(acc2, red);
+        if (threadIdx.x == 0) pc.partial2[vb] = s2;
+    }
 }
 
 // rho_i = sum of the update partials; beta_i = rho_i / rho_{i-1}; the
 // iteration count, the history and the stopping test (Algorithm 1, last
 // two steps).  One block.
-__device__ __forceinline__ void finalize_rho_body(CgState *st, const double *partial, int cnt) {
+// partial2 (may be null): the partials of <r, r, c> when rho is the
+// preconditioned <r, z, c>; the stopping test and the history use <r, r, c>.
+__device__ __forceinline__ void finalize_rho_body(CgState *st, const double *partial, int cnt,
+                                                  const double *partial2 = nullptr) {
     if (st->stop) return;
     __shared__ double red[16];
     const double rho = sum_partials(partial, cnt, red);
+    const double rr = partial2 ? sum_partials(partial2, cnt, red) : rho;
     if (threadIdx.x == 0) {
         const double beta = rho / st->rho;
         st->beta = beta;
         st->rho = rho;
+        st->rr = rr;
         st->x_lag = 1;
         const int it = st->iter + 1;
         st->iter = it;
-        if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rho;
-        if (!isfinite(rho)) st->stop = 3;
-        else if (!st->fixed && rho <= st->thresh) st->stop = 1;
+        if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rr;
+        if (!isfinite(rho) || !isfinite(rr)) st->stop = 3;
+        else if (!st->fixed && rr <= st->thresh) st->stop = 1;
         else if (it >= st->max_iter) st->stop = 2;
     }
 }

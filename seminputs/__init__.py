@@ -30,6 +30,7 @@ import numpy as np
 __all__ = [
     "BoxMesh",
     "box_mesh",
+    "graded_z",
     "random_global_rhs",
     "batch_problems",
     "arrival_times",
@@ -173,6 +174,24 @@ def box_mesh(nx: int, ny: int, nz: int, N: int, perturb: float = 0.0,
                    dirichlet=np.ascontiguousarray(dirichlet), n_glob=int(n_glob),
                    perturb=perturb, seed=seed,
                    info={"permute": permute, "reorient": reorient})
+
+
+def graded_z(mesh: BoxMesh, s: float = 3.0) -> BoxMesh:
+    """The same mesh with its vertices moved along z by the monotone map
+    z -> (z + s z^3) / (1 + s), which keeps the faces z = 0 and z = 1: the
+    elements next to z = 0 become about 1 + 3s times thinner than those next
+    to z = 1 (a boundary-layer grading), so the diagonal of the operator
+    varies strongly over the mesh.  Coordinates are rounded to FP32 again;
+    copies of a vertex map to the same point, so the mesh stays conforming.
+    """
+    import dataclasses
+    vert = mesh.vert.copy()
+    z = vert[..., 2]
+    vert[..., 2] = (z + s * z ** 3) / (1.0 + s)
+    vert = vert.astype(np.float32).astype(np.float64)
+    info = dict(mesh.info)
+    info["graded_z"] = s
+    return dataclasses.replace(mesh, vert=np.ascontiguousarray(vert), info=info)
 
 
 def random_global_rhs(mesh: BoxMesh, seed: int = RHS_SEED) -> np.ndarray:
