@@ -53,14 +53,15 @@ def ax_bytes_per_point(N: int, geom: str, fused: bool) -> float:
     return b + (16.0 + 4.0 * (12 * N - 4) / P3 if fused else 0.0)
 
 
-def update_bytes_per_point(N: int, shared_frac: float) -> float:
+def update_bytes_per_point(N: int, shared_frac: float, jacobi: bool = False) -> float:
     """Algorithmic FP32 bytes per local point of the update with gather: r
     read and written 8, w 4, point code 1, gather table 4 S / P^3 (S surface
-    nodes per element), one gathered value per shared point."""
+    nodes per element), one gathered value per shared point; with the
+    Jacobi preconditioner also M^-1 read and z written (+8)."""
     P = N + 1
     P3 = P ** 3
     S = P3 - max(P - 2, 0) ** 3
-    return 8.0 + 4.0 + 1.0 + 4.0 * S / P3 + 4.0 * shared_frac
+    return 8.0 + 4.0 + 1.0 + 4.0 * S / P3 + 4.0 * shared_frac + (8.0 if jacobi else 0.0)
 
 
 def ax_flops_per_point(N: int, geom: str) -> float:
@@ -146,9 +147,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--geom", choices=["pre", "otf"], default="otf",
                     help="geometric-factor form of the timed solver")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6],
                     help="2: the headline FP32 CG throughput line; 1, 3, 4, 5: the other "
-                         "workloads (FP64 latency, mixed vs FP64, batched, serving)")
+                         "workloads (FP64 latency, mixed vs FP64, batched, serving); "
+                         "6: Jacobi-preconditioned CG against plain CG")
     ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
@@ -520,7 +522,124 @@ def run_config5(args):
                                          f"mixed to 1e-8, Poisson arrivals {rate}/s"}})
 
 
-SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5}
+def run_config6(args):
+    """Jacobi-preconditioned CG against plain CG.  (a) Cost of one
+    iteration: FP32, on-the-fly G, 500 fixed iterations on the 32^3 N=7
+    mesh of the headline line, per-kernel times, and the roofline of the
+    preconditioned update (it also reads M^-1 and writes z).  (b) Time to a
+    true relative residual of 1e-10 (mixed precision, on-the-fly G) with and
+    without Jacobi on the 24^3 N=9 deformed mesh (manufactured forcing) and
+    on a 24^3 N=7 mesh graded along z (elements ten times thinner at one
+    face; random continuous RHS).  (c) The oracle's PCG on this host's
+    cores, on a bounded sample of (a)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, RHS_SEED, box_mesh, graded_z, random_global_rhs
+    nel, N, iters = args.nel, args.order, args.iters
+    out = {}
+    # (a) iteration cost at the headline size
+    log(f"bench6: {nel}^3 N={N} iteration cost")
+    mesh = box_mesh(nel, nel, nel, N, perturb=0.1, seed=MESH_SEED_BASE + 2)
+    b_host = random_global_rhs(mesh, seed=RHS_SEED)
+    n = mesh.n_local
+    gm = sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=False)
+    b = torch.as_tensor(b_host.astype(np.float32), device="cuda")
+    x = torch.zeros_like(b)
+    cost = {}
+    for label, pc in (("cg", sem.PRECOND_NONE), ("pcg", sem.PRECOND_JACOBI)):
+        x.zero_()
+        gm.cg_solve(b, x=x, prec=sem.FP32, geom=sem.ON_THE_FLY, fixed_iters=20, precond=pc)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x.zero_()
+            gm.cg_solve(b, x=x, prec=sem.FP32, geom=sem.ON_THE_FLY, fixed_iters=iters,
+                        precond=pc)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        x.zero_()
+        _, prof = gm.cg_solve(b, x=x, prec=sem.FP32, geom=sem.ON_THE_FLY, fixed_iters=iters,
+                              precond=pc, kernel_times=True)
+        cost[label] = {"gdof_iter_per_s": n * iters / dt / 1e9, "ms_per_iter": 1e3 * dt / iters,
+                       "kernel_ms": prof["kernel_ms"]}
+    info = gm.info()
+    shared_frac = info["n_shared"] / n
+    upd_ms = cost["pcg"]["kernel_ms"]["update"]
+    upd_gbs = update_bytes_per_point(N, shared_frac, jacobi=True) * n / (upd_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": upd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": upd_gbs / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "update_gather_kernel<float, PC> (gather + mask + r update + z = M^-1 r "
+                      "+ <r,z,c>, <r,r,c> partials) and the one-block rho finalize, timed "
+                      "together between HIP events", "avg_ms": upd_ms}
+    out["iteration_cost"] = cost
+    # (c) oracle PCG on a bounded sample of the same mesh
+    cpu = None
+    if not args.no_cpu:
+        log("bench6: oracle PCG CPU baseline")
+        pr = oracle.Problem(mesh)
+        minv = pr.jacobi_minv()
+        k = 2
+        t0 = time.perf_counter()
+        pr.pcg(b_host, minv=minv, fixed=k)
+        t = time.perf_counter() - t0
+        if t < 5.0:
+            k = max(k, min(200, int(k * 15.0 / max(t, 1e-3))))
+            t0 = time.perf_counter()
+            pr.pcg(b_host, minv=minv, fixed=k)
+            t = time.perf_counter() - t0
+        cpu = {"value": n * k / t / 1e9, "unit": "GDOF·iter/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{k} FP64 Jacobi-PCG iterations of the oracle on the {nel}^3 N={N} "
+                         f"mesh (diagonal setup excluded); {t:.1f} s timed"}
+        del pr
+    gm.close()
+    del b, x
+    # (b) time to 1e-10
+    solves = {}
+    cases = (("deformed_24_N9", box_mesh(24, 24, 24, 9, perturb=0.1, seed=MESH_SEED_BASE + 3),
+              "manufactured"),
+             ("graded_24_N7", graded_z(box_mesh(24, 24, 24, 7, perturb=0.1,
+                                                seed=MESH_SEED_BASE + 6), s=3.0), "random"))
+    for name, m, rhs in cases:
+        log(f"bench6: time to 1e-10 on {name}")
+        g = sem.Mesh.from_box(m, g_fp32=True, g_fp64=False)
+        if rhs == "manufactured":
+            bb = g.rhs(_forcing(g.coords()), prec=sem.FP64)
+        else:
+            bb = torch.as_tensor(random_global_rhs(m, seed=RHS_SEED + 6), device="cuda")
+        row = {}
+        for label, pc in (("cg", sem.PRECOND_NONE), ("pcg", sem.PRECOND_JACOBI)):
+            g.cg_solve(bb, prec=sem.MIXED, geom=sem.ON_THE_FLY, tol=1e-3, max_iter=50,
+                       precond=pc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = g.cg_solve(bb, prec=sem.MIXED, geom=sem.ON_THE_FLY, tol=1e-10,
+                              max_iter=100000, precond=pc)
+            torch.cuda.synchronize()
+            row[label] = {"seconds": time.perf_counter() - t0, "iters": r["iters"],
+                          "outer": r["outer"], "rel_res_true": r["rel_res_true"],
+                          "converged": r["converged"]}
+        row["speedup"] = row["cg"]["seconds"] / row["pcg"]["seconds"]
+        row["n_local"] = m.n_local
+        solves[name] = row
+        g.close()
+    out["time_to_1e10"] = solves
+    value = solves["graded_24_N7"]["pcg"]["seconds"]
+    return _emit({"metric": "time to 1e-10 true residual with Jacobi-PCG (mixed, on-the-fly G), "
+                            "24^3 N=7 graded mesh",
+                  "value": value, "unit": "s", "higher_is_better": False,
+                  "speedup_vs_cg": solves["graded_24_N7"]["speedup"], "runs": out,
+                  "dtype": "f32+f64", "data": "synthetic",
+                  "config": {"workload": "Jacobi-PCG vs CG: iteration cost on 32^3 N=7, time to "
+                                         "1e-10 on 24^3 N=9 deformed and 24^3 N=7 graded"},
+                  "roofline": roof, "cpu_baseline": cpu})
+
+
+SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5, 6: run_config6}
 
 
 if __name__ == "__main__":

@@ -159,8 +159,9 @@ sem_status sem_rhs(sem_mesh_t mesh, sem_precision prec, const double *f_dev, voi
                    void *hip_stream);
 
 /*
- * Preconditioner of the CG (Sec. 2 names the preconditioner among the
- * components of CG; Algorithm 1 itself is unpreconditioned).
+ * Preconditioner of the CG (Sec. 3.2 introduces CG in its usual
+ * preconditioned form and takes the unpreconditioned Algorithm 1 as the
+ * first step; Sec. 10 leaves preconditioning open).
  * SEM_PRECOND_JACOBI: M = diagonal of the assembled operator A = Q^T A_L Q
  * (Eq. 4), formed once per mesh in FP64 from the vertices: the element
  * diagonals (A_L)_qq summed over the copies of every global point; the

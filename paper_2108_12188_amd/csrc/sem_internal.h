@@ -223,8 +223,8 @@ struct AxArgs {
                                 // x += alpha p_old (previous iteration's step)
 };
 
-// Jacobi preconditioning in the CG update (Sec. 2 lists it among the
-// preconditioners of CG): z = minv r is written, and the block partials of
+// Jacobi preconditioning in the CG update (preconditioned CG, Sec. 3.2;
+// Algorithm 1 is its unpreconditioned case): z = minv r is written, and the block partials of
 // <r, z, c> (partial) and <r, r, c> (partial2) are reduced.
 template <typename T>
 struct PcArgs {
