@@ -155,6 +155,8 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
     ap.add_argument("--no-tune", action="store_true", help="ignore the tuned tile shapes")
+    ap.add_argument("--engine", choices=["default", "valu", "mfma"], default="default",
+                    help="contraction engine of the FP32 local operator at the bench order")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference kernel of known "
                          "size for HBM counter calibration)")
@@ -184,6 +186,11 @@ def main(argv=None):
     if not args.no_tune:
         from paper_2108_12188_amd import tune
         log(f"bench: {tune.apply()} tuned tile shapes applied")
+    if args.engine != "default":
+        eng = sem.ENGINE_VALU if args.engine == "valu" else sem.ENGINE_MFMA
+        for g in (sem.PRECOMPUTED, sem.ON_THE_FLY):
+            sem.ax_engine_set(args.order, sem.FP32, g, eng)
+        log(f"bench: operator engine {args.engine} at N={args.order}")
     if args.config != 2:
         return SUITES[args.config](args)
     nel, N, iters = args.nel, args.order, args.iters

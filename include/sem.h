@@ -276,6 +276,26 @@ sem_status sem_ax_shape_set(int order_N, sem_precision prec, sem_geom geom, int 
 sem_status sem_ax_shape_get(int order_N, sem_precision prec, sem_geom geom, int *elems_per_block,
                             int *threads, size_t *lds_bytes);
 
+/*
+ * Contraction engine of the local operator for an order, precision and
+ * G form: SEM_AX_ENGINE_VALU runs the D contractions as FP32/FP64 FMAs
+ * (one thread per (i, j) column, sem_ax_shape_set picks elements per
+ * block); SEM_AX_ENGINE_MFMA runs them on the FP32 matrix cores (16-block
+ * 4x4x1 MFMA, one element per 64-lane workgroup; available for SEM_FP32 at
+ * N = 7, else SEM_EUNSUPPORTED).  The two engines accumulate every
+ * contraction in the same order with fused multiply-adds, so their results
+ * are bitwise identical.  SEM_AX_ENGINE_DEFAULT restores the built-in
+ * choice.  Process-wide, used by later launches.  For the autotuner.
+ */
+typedef enum {
+    SEM_AX_ENGINE_DEFAULT = 0,
+    SEM_AX_ENGINE_VALU = 1,
+    SEM_AX_ENGINE_MFMA = 2
+} sem_ax_engine;
+sem_status sem_ax_engine_set(int order_N, sem_precision prec, sem_geom geom, int engine);
+/* The engine later launches use (SEM_AX_ENGINE_VALU or SEM_AX_ENGINE_MFMA). */
+sem_status sem_ax_engine_get(int order_N, sem_precision prec, sem_geom geom, int *engine);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *sem_last_error(void);
 

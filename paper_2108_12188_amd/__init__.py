@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 __all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_set",
-           "ax_shape_get", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
+           "ax_shape_get", "ax_engine_set", "ax_engine_get", "ENGINE_DEFAULT", "ENGINE_VALU",
+           "ENGINE_MFMA", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
            "PRECOND_NONE", "PRECOND_JACOBI",
            "lib", "library_path", "version"]
 
@@ -62,7 +63,8 @@ EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "se
            "sem_dot", "sem_diag", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
            "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
            "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_ax_shape_set",
-           "sem_ax_shape_get", "sem_last_error", "sem_version"]
+           "sem_ax_shape_get", "sem_ax_engine_set", "sem_ax_engine_get", "sem_last_error",
+           "sem_version"]
 
 
 def library_path() -> str:
@@ -103,6 +105,8 @@ def lib():
     L.sem_ax_shape_set.argtypes = [i32, i32, i32, i32]
     L.sem_ax_shape_get.argtypes = [i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_size_t)]
+    L.sem_ax_engine_set.argtypes = [i32, i32, i32, i32]
+    L.sem_ax_engine_get.argtypes = [i32, i32, i32, C.POINTER(C.c_int)]
     L.sem_last_error.restype = C.c_char_p
     L.sem_last_error.argtypes = []
     L.sem_version.restype = C.c_char_p
@@ -110,7 +114,8 @@ def lib():
     for name in ("sem_mesh_create", "sem_mesh_info", "sem_ax", "sem_gs", "sem_dot",
                  "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve",
                  "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint",
-                 "sem_ax_shape_set", "sem_ax_shape_get"):
+                 "sem_ax_shape_set", "sem_ax_shape_get", "sem_ax_engine_set",
+                 "sem_ax_engine_get", "sem_diag"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -355,6 +360,20 @@ def ax_shape_get(N: int, prec: int, geom: int) -> dict:
     e, t, l = C.c_int(), C.c_int(), C.c_size_t()
     _check(lib().sem_ax_shape_get(N, prec, geom, C.byref(e), C.byref(t), C.byref(l)))
     return {"elems_per_block": e.value, "threads": t.value, "lds_bytes": int(l.value)}
+
+
+ENGINE_DEFAULT, ENGINE_VALU, ENGINE_MFMA = 0, 1, 2
+
+
+def ax_engine_set(N: int, prec: int, geom: int, engine: int):
+    """Contraction engine of the local operator (VALU FMA or matrix cores)."""
+    _check(lib().sem_ax_engine_set(N, prec, geom, engine))
+
+
+def ax_engine_get(N: int, prec: int, geom: int) -> int:
+    e = C.c_int()
+    _check(lib().sem_ax_engine_get(N, prec, geom, C.byref(e)))
+    return e.value
 
 
 def mesh_footprint(n_elem: int, N: int, g_fp32: bool = True, g_fp64: bool = False,

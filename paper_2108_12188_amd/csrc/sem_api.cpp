@@ -386,6 +386,33 @@ sem_status sem_ax_shape_set(int order_N, sem_precision prec, sem_geom geom, int 
     });
 }
 
+sem_status sem_ax_engine_set(int order_N, sem_precision prec, sem_geom geom, int engine) {
+    return guarded([&]() -> sem_status {
+        if (order_N < 1 || order_N > kMaxOrder) fail(SEM_EUNSUPPORTED, "order not built");
+        check_prec(prec);
+        if (geom != SEM_G_PRECOMPUTED && geom != SEM_G_ON_THE_FLY)
+            fail(SEM_EINVAL, "unknown geometry form");
+        if (engine != SEM_AX_ENGINE_DEFAULT && engine != SEM_AX_ENGINE_VALU &&
+            engine != SEM_AX_ENGINE_MFMA)
+            fail(SEM_EINVAL, "unknown engine");
+        if (engine == SEM_AX_ENGINE_MFMA && !ax_mfma_available(order_N, prec == SEM_FP64))
+            fail(SEM_EUNSUPPORTED, "the matrix-core engine is built for FP32 at N = 7 only");
+        ax_engine_set(order_N, prec == SEM_FP64, geom == SEM_G_ON_THE_FLY, engine);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_ax_engine_get(int order_N, sem_precision prec, sem_geom geom, int *engine) {
+    return guarded([&]() -> sem_status {
+        need(engine, "engine");
+        if (order_N < 1 || order_N > kMaxOrder) fail(SEM_EUNSUPPORTED, "order not built");
+        check_prec(prec);
+        const AxShape sh = ax_shape(order_N, prec == SEM_FP64, geom == SEM_G_ON_THE_FLY, 0);
+        *engine = sh.mfma ? SEM_AX_ENGINE_MFMA : SEM_AX_ENGINE_VALU;
+        return SEM_OK;
+    });
+}
+
 sem_status sem_ax_shape_get(int order_N, sem_precision prec, sem_geom geom, int *elems_per_block,
                             int *threads, size_t *lds_bytes) {
     return guarded([&]() -> sem_status {

@@ -25,7 +25,7 @@ SEM_DECL_ORDER(11)
 #undef SEM_DECL_ORDER
 
 #define SEM_DECL_BATCH(N)                                                                      \
-    void ax_batch_order_##N##_f32(bool, const AxArgs<float> *, const int2 *, int64_t, int,    \
+    void ax_batch_order_##N##_f32(bool, bool, const AxArgs<float> *, const int2 *, int64_t, int, \
                                   const double *, const double *, const double *, hipStream_t);
 SEM_DECL_BATCH(1)
 SEM_DECL_BATCH(2)
@@ -40,8 +40,8 @@ SEM_DECL_BATCH(10)
 SEM_DECL_BATCH(11)
 #undef SEM_DECL_BATCH
 
-using FnB = void (*)(bool, const AxArgs<float> *, const int2 *, int64_t, int, const double *,
-                     const double *, const double *, hipStream_t);
+using FnB = void (*)(bool, bool, const AxArgs<float> *, const int2 *, int64_t, int,
+                     const double *, const double *, const double *, hipStream_t);
 static const FnB kFnB[kMaxOrder + 1] = {
     nullptr,           ax_batch_order_1_f32, ax_batch_order_2_f32, ax_batch_order_3_f32,
     ax_batch_order_4_f32, ax_batch_order_5_f32, ax_batch_order_6_f32, ax_batch_order_7_f32,
@@ -58,9 +58,15 @@ using Fn64 = void (*)(bool, AxMode, const AxArgs<double> &, const double *, cons
 #define SEM_AX_FUSED_MAX_BLOCKS 2048
 #endif
 constexpr int64_t kAxFusedMaxBlocks = SEM_AX_FUSED_MAX_BLOCKS;
+// the matrix-core form's blocks are single waves: 4 times as many
+#ifndef SEM_AX_MFMA_MAX_BLOCKS
+#define SEM_AX_MFMA_MAX_BLOCKS 8192
+#endif
+constexpr int64_t kAxMfmaMaxBlocks = SEM_AX_MFMA_MAX_BLOCKS;
 
-static int64_t ax_grid(int64_t ntiles, AxMode mode) {
-    if (mode == AxMode::CgFused && ntiles > kAxFusedMaxBlocks) return kAxFusedMaxBlocks;
+static int64_t ax_grid(int64_t ntiles, AxMode mode, bool mfma) {
+    const int64_t cap = mfma ? kAxMfmaMaxBlocks : kAxFusedMaxBlocks;
+    if (mode == AxMode::CgFused && ntiles > cap) return cap;
     return ntiles;
 }
 
@@ -84,6 +90,7 @@ static const int kEpb64[kMaxOrder + 1] = {0, 64, 28, 16, 10, 7, 5, 4, 3, 3, 2, 1
 // indexed [on-the-fly][fp64][N], and a generation counter that tells cached
 // graphs and batch tables that a shape changed.
 static std::atomic<int> g_epb[2][2][kMaxOrder + 1];
+static std::atomic<int> g_engine[2][2][kMaxOrder + 1];
 static std::atomic<int> g_shape_gen{0};
 
 int ax_shape_generation() { return g_shape_gen.load(); }
@@ -93,9 +100,27 @@ void ax_shape_set(int N, bool fp64, bool otf, int epb) {
     g_shape_gen.fetch_add(1);
 }
 
+bool ax_mfma_available(int N, bool fp64) { return N == 7 && !fp64; }
+
+void ax_engine_set(int N, bool fp64, bool otf, int engine) {
+    g_engine[otf ? 1 : 0][fp64 ? 1 : 0][N].store(engine);
+    g_shape_gen.fetch_add(1);
+}
+
 AxShape ax_shape(int N, bool fp64, bool otf, int epb_override) {
     const int P = N + 1, P2 = P * P, P3 = P2 * P;
     const size_t tsz = fp64 ? 8 : 4;
+    const int engine = g_engine[otf ? 1 : 0][fp64 ? 1 : 0][N].load();
+    if (engine == kAxEngineMfma && ax_mfma_available(N, fp64)) {
+        // one element per 64-lane block: two padded tiles (slices of 72
+        // floats) and the staging of r, p and the vertices
+        AxShape s;
+        s.epb = 1;
+        s.threads = 64;
+        s.lds = 4 * (2 * (size_t)P * 72 + 2 * (size_t)P3 + 32);
+        s.mfma = true;
+        return s;
+    }
     int epb = epb_override > 0 ? epb_override : g_epb[otf ? 1 : 0][fp64 ? 1 : 0][N].load();
     if (epb <= 0) epb = fp64 ? kEpb64[N] : kEpb32[N];
     // clamp to the kernel limits (FP32 CG-fused tiles of odd N also stage
@@ -109,6 +134,7 @@ AxShape ax_shape(int N, bool fp64, bool otf, int epb_override) {
     s.epb = epb;
     s.threads = ((epb * P2 + 63) / 64) * 64;
     s.lds = lds(epb);
+    s.mfma = false;
     return s;
 }
 
@@ -116,6 +142,7 @@ template <>
 void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hipStream_t s) {
     const AxShape sh = ax_shape(m.N, false, otf, a.epb);
     a.epb = sh.epb;
+    a.mfma = sh.mfma ? 1 : 0;
     a.E = m.E;
     a.D = m.b32.D;
     a.Dt = m.b32.Dt;
@@ -124,7 +151,8 @@ void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hip
     a.vert = m.vert32;
     if (!otf) a.G = m.G32;
     const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
-    kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), ax_grid(ntiles, mode), s);
+    kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(),
+               ax_grid(ntiles, mode, sh.mfma), s);
     check_hip(hipGetLastError(), "ax kernel launch (fp32)");
 }
 
@@ -132,6 +160,7 @@ template <>
 void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, hipStream_t s) {
     const AxShape sh = ax_shape(m.N, true, otf, a.epb);
     a.epb = sh.epb;
+    a.mfma = 0;
     a.E = m.E;
     a.D = m.b64.D;
     a.Dt = m.b64.Dt;
@@ -140,13 +169,15 @@ void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, h
     a.vert = m.vert64;
     if (!otf) a.G = m.G64;
     const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
-    kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(), ax_grid(ntiles, mode), s);
+    kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(),
+               ax_grid(ntiles, mode, false), s);
     check_hip(hipGetLastError(), "ax kernel launch (fp64)");
 }
 
 void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
     const AxShape sh = ax_shape(m.N, false, otf, 0);
     a.epb = sh.epb;
+    a.mfma = sh.mfma ? 1 : 0;
     a.E = m.E;
     a.D = m.b32.D;
     a.Dt = m.b32.Dt;
@@ -154,20 +185,20 @@ void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
     a.wq = m.b32.w;
     a.vert = m.vert32;
     a.G = otf ? nullptr : m.G32;
-    a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused);
+    a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma);
 }
 
-void launch_ax_batch(int N, bool otf, const AxArgs<float> *descs, const int2 *blk, int64_t nblk,
-                     int epb, const double *D, const double *xi, const double *w,
+void launch_ax_batch(int N, bool otf, bool mfma, const AxArgs<float> *descs, const int2 *blk,
+                     int64_t nblk, int epb, const double *D, const double *xi, const double *w,
                      hipStream_t s) {
     if (nblk <= 0) return;
-    kFnB[N](otf, descs, blk, nblk, epb, D, xi, w, s);
+    kFnB[N](otf, mfma, descs, blk, nblk, epb, D, xi, w, s);
     check_hip(hipGetLastError(), "batched ax kernel launch");
 }
 
 int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override) {
     const AxShape sh = ax_shape(m.N, fp64, otf, epb_override);
-    return ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused);
+    return ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma);
 }
 
 }  // namespace sem

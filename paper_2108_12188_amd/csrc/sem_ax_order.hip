@@ -135,6 +135,43 @@ __device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T
     return g;
 }
 
+// The pointwise step of A_L at level k of a column: (vr, vs, vt) = G (ur, us, ut)
+// with G rebuilt from the column geometry (on the fly) or read from HBM
+// (precomputed: gq when prefetched, else Ge = this column's factors).
+template <typename T, bool OTF, bool kPre>
+__device__ __forceinline__ void point_flux(const ColumnGeom<T> &cg, const BasisK<T> &bk, int k,
+                                           const T (&gq)[kPre ? 6 : 1][kPre ? kP : 1],
+                                           const T *__restrict__ Ge, T ur, T us, T ut, T &vr,
+                                           T &vs, T &vt) {
+    constexpr int P2 = kP * kP, P3 = P2 * kP;
+    if constexpr (OTF) {
+        const T gam = bk.xi[k];
+        const Vec3<T> r0 = axpy3(gam, cg.R01, cg.R00);
+        const Vec3<T> r1 = axpy3(gam, cg.R11, cg.R10);
+        const Vec3<T> r2 = axpy3(gam, axpy3(gam, cg.R22, cg.R21), cg.R20);
+        const T det = cg.d0 + gam * (cg.d1 + gam * cg.d2);
+        const T s = cg.wij * bk.w[k] * rcp<T>(det);
+        const Vec3<T> g{r0.x * ur + r1.x * us + r2.x * ut, r0.y * ur + r1.y * us + r2.y * ut,
+                        r0.z * ur + r1.z * us + r2.z * ut};
+        vr = s * dot3(r0, g);
+        vs = s * dot3(r1, g);
+        vt = s * dot3(r2, g);
+    } else {
+        T g11, g12, g13, g22, g23, g33;
+        if constexpr (kPre) {
+            g11 = gq[0][k], g12 = gq[1][k], g13 = gq[2][k];
+            g22 = gq[3][k], g23 = gq[4][k], g33 = gq[5][k];
+        } else {
+            const T *G = Ge + k * P2;
+            g11 = G[0], g12 = G[P3], g13 = G[2 * P3];
+            g22 = G[3 * P3], g23 = G[4 * P3], g33 = G[5 * P3];
+        }
+        vr = g11 * ur + g12 * us + g13 * ut;
+        vs = g12 * ur + g22 * us + g23 * ut;
+        vt = g13 * ur + g23 * us + g33 * ut;
+    }
+}
+
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double red[16];
     return block_sum_f64(v, red);
@@ -374,33 +411,8 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                     ut += bk.D[k * P + l] * uc[l];
                 }
                 T vr, vs, vt;
-                if constexpr (OTF) {
-                    const T gam = bk.xi[k];
-                    const Vec3<T> r0 = axpy3(gam, cg.R01, cg.R00);
-                    const Vec3<T> r1 = axpy3(gam, cg.R11, cg.R10);
-                    const Vec3<T> r2 = axpy3(gam, axpy3(gam, cg.R22, cg.R21), cg.R20);
-                    const T det = cg.d0 + gam * (cg.d1 + gam * cg.d2);
-                    const T s = cg.wij * bk.w[k] * rcp<T>(det);
-                    const Vec3<T> g{r0.x * ur + r1.x * us + r2.x * ut,
-                                    r0.y * ur + r1.y * us + r2.y * ut,
-                                    r0.z * ur + r1.z * us + r2.z * ut};
-                    vr = s * dot3(r0, g);
-                    vs = s * dot3(r1, g);
-                    vt = s * dot3(r2, g);
-                } else {
-                    T g11, g12, g13, g22, g23, g33;
-                    if constexpr (kPre) {
-                        g11 = gq[0][k], g12 = gq[1][k], g13 = gq[2][k];
-                        g22 = gq[3][k], g23 = gq[4][k], g33 = gq[5][k];
-                    } else {
-                        const T *Ge = a.G + e * (6 * P3) + col + k * P2;
-                        g11 = Ge[0], g12 = Ge[P3], g13 = Ge[2 * P3];
-                        g22 = Ge[3 * P3], g23 = Ge[4 * P3], g33 = Ge[5 * P3];
-                    }
-                    vr = g11 * ur + g12 * us + g13 * ut;
-                    vs = g12 * ur + g22 * us + g23 * ut;
-                    vt = g13 * ur + g23 * us + g33 * ut;
-                }
+                point_flux<T, OTF, kPre>(cg, bk, k, gq, OTF ? nullptr : a.G + e * (6 * P3) + col,
+                                         ur, us, ut, vr, vs, vt);
                 sb[k * P2 + col] = vr;
                 vsr[k] = vs;
                 vtr[k] = vt;
@@ -416,13 +428,16 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         if (valid) {
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                T wv = T(0);
+                // three chains, one per direction, summed (r + s) + t (the
+                // order of the matrix-core form, which gives the same bits)
+                T wr = T(0), ws = T(0), wt = T(0);
 #pragma unroll
                 for (int l = 0; l < P; ++l) {
-                    wv += DiT[l] * sb[k * P2 + j * P + l];
-                    wv += DjT[l] * sa[k * P2 + l * P + i];
-                    wv += bk.D[l * P + k] * vtr[l];
+                    wr += DiT[l] * sb[k * P2 + j * P + l];
+                    ws += DjT[l] * sa[k * P2 + l * P + i];
+                    wt += bk.D[l * P + k] * vtr[l];
                 }
+                const T wv = (wr + ws) + wt;
                 if constexpr (FUSED) {
                     acc += (double)uc[k] * (double)wv;
                     // compact copy of the edge and corner nodes
@@ -441,6 +456,263 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         const double s = block_sum(acc);
         if (threadIdx.x == 0) a.partial[vb] = s;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core form (FP32, N = 7): one wave per element, so P^2 = 64 columns
+// fill the wave exactly and no barrier is needed (a wave's LDS accesses
+// complete in issue order).  Every contraction with D or D^T runs on the
+// 16-block 4x4x1 FP32 MFMA: block b of a wave multiplies the 4-vector held
+// by its lanes 4b..4b+3 (operand A) with each of those lanes' own value
+// (operand B), so after 8 steps l = 0..7 on the two row quads t = 0, 1,
+// lane q holds sum_l M[4t + r][l] x_q[l] (r = 0..3) for its own 8-vector
+// x_q: the whole 8 x 8 product of M with the lane's vector.  The
+// accumulation is one fused multiply-add per step in the order l = 0..7,
+// which is bitwise the VALU loop of ax_body.  For the i- and j-directions
+// the lanes take the element's pencils along that direction from a padded
+// LDS tile (slice stride 72 floats: the column, i-pencil and j-pencil
+// access patterns are all free of bank conflicts), and the results return
+// to the column layout through the same tile.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaSlice = 72;                       // padded (i, j) slice, floats
+constexpr int kMfmaTile = kP * kMfmaSlice;           // padded element tile, floats
+
+template <bool OTF, bool FUSED>
+__host__ __device__ constexpr size_t ax_mfma_lds_bytes() {
+    constexpr size_t P3 = (size_t)kP * kP * kP;
+    return 4 * (2 * (size_t)kMfmaTile + (FUSED ? 2 * P3 + 32 : 0));
+}
+
+// Exchange through LDS inside one wave: the wave's earlier LDS accesses
+// complete before its later ones issue, and the compiler moves no memory
+// access across this point (lanes read what other lanes of the wave wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kWaitLgkmcnt0);
+    __asm__ volatile("" ::: "memory");
+}
+
+// out = M x for the lane's own 8-vector x; lane q holds rows 4t + (q & 3)
+// of M in m[t][0..7].
+__device__ __forceinline__ void mfma_apply8(const float (&m)[2][kP], const float (&x)[kP],
+                                            float (&out)[kP]) {
+    v4f c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < kP; ++l) {
+        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[0][l], x[l], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[1][l], x[l], c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out[r] = c0[r];
+        out[4 + r] = c1[r];
+    }
+}
+
+template <bool OTF, bool FUSED>
+__device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const BasisK<float> &bk,
+                                             int64_t ntiles, int64_t vb, int64_t vgrid) {
+    if constexpr (kP == 8) {
+        using T = float;
+        constexpr int P = kP, P2 = P * P, P3 = P2 * P, PS = kMfmaSlice;
+        constexpr bool kDma = FUSED;
+        extern __shared__ __align__(16) unsigned char lds_raw[];
+        float *const sA = reinterpret_cast<float *>(lds_raw);
+        float *const sB = sA + kMfmaTile;
+        // staging (fused): r, p and vertices of the next element; x of the
+        // next element lands in sB, which is free between elements
+        float *const sR = sB + kMfmaTile;
+        float *const sP = sR + P3;
+        float *const sV = sP + P3;
+        float *const sX = sB;
+
+        if constexpr (FUSED) {
+            if (a.st->stop) return;
+        }
+        const int q = threadIdx.x;        // column (i, j) = (q & 7, q >> 3)
+        const int i = q & 7, j = q >> 3;
+        // pencil lanes: along i, lane q is (j, k) = (q & 7, q >> 3); along j,
+        // lane q is (i, k) = (q & 7, q >> 3)
+        const int ipen = 8 * (q & 7) + PS * (q >> 3);   // + i
+        const int jpen = (q & 7) + PS * (q >> 3);        // + 8 j
+        float Dm[2][P], DTm[2][P];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                Dm[t][l] = a.D[(4 * t + (q & 3)) * P + l];
+                DTm[t][l] = a.Dt[(4 * t + (q & 3)) * P + l];
+            }
+        T beta = T(0);
+        bool xlag = false;
+        T aprev = T(0);
+        if constexpr (FUSED) {
+            beta = (T)a.st->beta;
+            xlag = a.x != nullptr && a.st->x_lag != 0;
+            aprev = (T)a.st->alpha;
+        }
+        const int ecb = edge_column_base(kOrder, i, j);
+        const bool ecorner = (i == 0 || i == P - 1) && (j == 0 || j == P - 1);
+        T xi_i = T(0), eta_j = T(0), wij = T(0);
+        if constexpr (OTF) {
+            xi_i = a.xi[i];
+            eta_j = a.xi[j];
+            wij = a.wq[i] * a.wq[j];
+        }
+        auto stage = [&](int64_t e) {
+            if constexpr (kDma) {
+                dma_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR, P3);
+                dma_to_lds(reinterpret_cast<const float *>(a.p) + e * P3, sP, P3);
+                if constexpr (OTF) dma_to_lds(reinterpret_cast<const float *>(a.vert) + e * 24, sV, 24);
+            }
+        };
+        auto stage_x = [&](int64_t e) {
+            if constexpr (kDma) {
+                if (xlag) dma_to_lds(reinterpret_cast<const float *>(a.x) + e * P3, sX, P3);
+            }
+        };
+        if constexpr (kDma) {
+            if (vb < ntiles) {
+                stage(vb);
+                stage_x(vb);
+            }
+        }
+
+        double acc = 0.0;
+        for (int64_t e = vb; e < ntiles; e += vgrid) {
+            const int64_t base = e * P3 + q;
+            T *const wep = (FUSED && a.wedge && ecb >= 0) ? a.wedge + e * edge_slots(kOrder) + ecb
+                                                          : nullptr;
+            if constexpr (kDma) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+
+            T uc[P];
+            if constexpr (kDma) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) uc[k] = sR[q + k * P2] + beta * sP[q + k * P2];
+#pragma unroll
+                for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                if (xlag) {
+#pragma unroll
+                    for (int k = 0; k < P; ++k)
+                        a.x[base + k * P2] = sX[q + k * P2] + aprev * sP[q + k * P2];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) sA[q + k * PS] = uc[k];
+            wave_lds_sync();
+
+            ColumnGeom<T> cg;
+            if constexpr (OTF) {
+                if constexpr (kDma) cg = column_geom<T>(sV, xi_i, eta_j, wij);
+                else cg = column_geom<T>(a.vert + e * 24, xi_i, eta_j, wij);
+            }
+            constexpr bool kPre = !OTF && prefetch_g<T>();
+            T gq[kPre ? 6 : 1][kPre ? P : 1];
+            if constexpr (kPre) {
+                const T *Ge = a.G + e * (6 * P3) + q;
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+#pragma unroll
+                    for (int k = 0; k < P; ++k) gq[c][k] = Ge[c * P3 + k * P2];
+            }
+            // every read of this element's staging is done: stage the next
+            if constexpr (kDma) {
+                wave_lds_sync();
+                if (e + vgrid < ntiles) stage(e + vgrid);
+            }
+
+            // gradient: k in the column's registers, i and j on pencils
+            T ut[P], pi[P], pj[P], dri[P], dsj[P];
+            mfma_apply8(Dm, uc, ut);
+            {
+                const float4 lo = *reinterpret_cast<const float4 *>(sA + ipen);
+                const float4 hi = *reinterpret_cast<const float4 *>(sA + ipen + 4);
+                pi[0] = lo.x, pi[1] = lo.y, pi[2] = lo.z, pi[3] = lo.w;
+                pi[4] = hi.x, pi[5] = hi.y, pi[6] = hi.z, pi[7] = hi.w;
+            }
+#pragma unroll
+            for (int l = 0; l < P; ++l) pj[l] = sA[jpen + 8 * l];
+            mfma_apply8(Dm, pi, dri);
+            mfma_apply8(Dm, pj, dsj);
+            *reinterpret_cast<float4 *>(sB + ipen) = make_float4(dri[0], dri[1], dri[2], dri[3]);
+            *reinterpret_cast<float4 *>(sB + ipen + 4) = make_float4(dri[4], dri[5], dri[6], dri[7]);
+#pragma unroll
+            for (int l = 0; l < P; ++l) sA[jpen + 8 * l] = dsj[l];
+            wave_lds_sync();
+
+            // pointwise G, back in the column layout
+            T vt[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const T ur = sB[q + k * PS], us = sA[q + k * PS];
+                T vr, vs;
+                point_flux<T, OTF, kPre>(cg, bk, k, gq, OTF ? nullptr : a.G + e * (6 * P3) + q,
+                                         ur, us, ut[k], vr, vs, vt[k]);
+                sB[q + k * PS] = vr;
+                sA[q + k * PS] = vs;
+            }
+            wave_lds_sync();
+
+            // divergence: D^T along k in registers, along i and j on pencils
+            T wt[P];
+            mfma_apply8(DTm, vt, wt);
+            {
+                const float4 lo = *reinterpret_cast<const float4 *>(sB + ipen);
+                const float4 hi = *reinterpret_cast<const float4 *>(sB + ipen + 4);
+                pi[0] = lo.x, pi[1] = lo.y, pi[2] = lo.z, pi[3] = lo.w;
+                pi[4] = hi.x, pi[5] = hi.y, pi[6] = hi.z, pi[7] = hi.w;
+            }
+#pragma unroll
+            for (int l = 0; l < P; ++l) pj[l] = sA[jpen + 8 * l];
+            mfma_apply8(DTm, pi, dri);
+            mfma_apply8(DTm, pj, dsj);
+            *reinterpret_cast<float4 *>(sB + ipen) = make_float4(dri[0], dri[1], dri[2], dri[3]);
+            *reinterpret_cast<float4 *>(sB + ipen + 4) = make_float4(dri[4], dri[5], dri[6], dri[7]);
+#pragma unroll
+            for (int l = 0; l < P; ++l) sA[jpen + 8 * l] = dsj[l];
+            wave_lds_sync();
+
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const T wv = (sB[q + k * PS] + sA[q + k * PS]) + wt[k];
+                if constexpr (FUSED) {
+                    acc += (double)uc[k] * (double)wv;
+                    if (wep && (k == 0 || k == P - 1 || ecorner))
+                        wep[k == 0 ? 0 : (k == P - 1 ? 1 : 1 + k)] = wv;
+                }
+                a.w[base + k * P2] = wv;
+            }
+            // every read of sB is done before the next element's x lands there
+            if constexpr (kDma) {
+                wave_lds_sync();
+                if (e + vgrid < ntiles) stage_x(e + vgrid);
+            }
+        }
+        if constexpr (FUSED) {
+            const double sum = block_sum(acc);
+            if (threadIdx.x == 0) a.partial[vb] = sum;
+        }
+    }
+}
+
+template <bool OTF, bool FUSED>
+__global__ void __launch_bounds__(64, 4)
+ax_mfma_kernel(const AxArgs<float> a, const BasisK<float> bk, int64_t ntiles) {
+    ax_mfma_body<OTF, FUSED>(a, bk, ntiles, blockIdx.x, gridDim.x);
+}
+
+template <bool OTF>
+__global__ void __launch_bounds__(64, 4)
+ax_mfma_batch_kernel(const AxArgs<float> *__restrict__ descs, const int2 *__restrict__ blk,
+                     const BasisK<float> bk) {
+    const int2 pv = blk[blockIdx.x];
+    const AxArgs<float> a = descs[pv.x];
+    ax_mfma_body<OTF, true>(a, bk, a.E, pv.y, a.vgrid);
 }
 
 template <typename T, bool OTF, bool FUSED>
@@ -475,6 +747,15 @@ BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
 
 template <typename T, bool OTF, bool FUSED>
 void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 && kP == 8) {
+        if (a.mfma) {
+            // one element per wave-sized block
+            const size_t lds = ax_mfma_lds_bytes<OTF, FUSED>();
+            hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid), dim3(64), lds, s,
+                               a, bk, a.E);
+            return;
+        }
+    }
     const int threads = ((a.epb * kP * kP + 63) / 64) * 64;
     const size_t lds = ax_lds_bytes<T, OTF, FUSED>(a.epb);
     const int64_t ntiles = (a.E + a.epb - 1) / a.epb;
@@ -502,10 +783,23 @@ static void ax_entry(bool otf, AxMode mode, const AxArgs<T> &a, const double *D,
 }
 
 template <typename T>
-static void ax_batch_entry(bool otf, const AxArgs<T> *descs, const int2 *blk, int64_t nblk,
-                           int epb, const double *D, const double *xi, const double *w,
-                           hipStream_t s) {
+static void ax_batch_entry(bool otf, bool mfma, const AxArgs<T> *descs, const int2 *blk,
+                           int64_t nblk, int epb, const double *D, const double *xi,
+                           const double *w, hipStream_t s) {
     const BasisK<T> bk = make_basis<T>(D, xi, w);
+    if constexpr (sizeof(T) == 4 && kP == 8) {
+        if (mfma) {
+            const size_t lds_otf = ax_mfma_lds_bytes<true, true>();
+            const size_t lds_pre = ax_mfma_lds_bytes<false, true>();
+            if (otf)
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<true>), dim3((unsigned)nblk), dim3(64),
+                                   lds_otf, s, descs, blk, bk);
+            else
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<false>), dim3((unsigned)nblk), dim3(64),
+                                   lds_pre, s, descs, blk, bk);
+            return;
+        }
+    }
     const int threads = ((epb * kP * kP + 63) / 64) * 64;
     const size_t lds_otf = ax_lds_bytes<T, true, true>(epb);
     const size_t lds_pre = ax_lds_bytes<T, false, true>(epb);
@@ -517,11 +811,11 @@ static void ax_batch_entry(bool otf, const AxArgs<T> *descs, const int2 *blk, in
                            lds_pre, s, descs, blk, bk);
 }
 
-void SEM_CAT3(ax_batch_order_, SEM_ORDER, _f32)(bool otf, const AxArgs<float> *descs,
+void SEM_CAT3(ax_batch_order_, SEM_ORDER, _f32)(bool otf, bool mfma, const AxArgs<float> *descs,
                                                  const int2 *blk, int64_t nblk, int epb,
                                                  const double *D, const double *xi,
                                                  const double *w, hipStream_t s) {
-    ax_batch_entry<float>(otf, descs, blk, nblk, epb, D, xi, w, s);
+    ax_batch_entry<float>(otf, mfma, descs, blk, nblk, epb, D, xi, w, s);
 }
 
 void SEM_CAT3(ax_order_, SEM_ORDER, _f32)(bool otf, AxMode mode, const AxArgs<float> &a,

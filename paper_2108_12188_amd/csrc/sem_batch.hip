@@ -150,6 +150,7 @@ struct BatchImpl {
     struct OrderGroup {
         int N;
         int epb;
+        bool mfma = false;
         int2 *blk = nullptr;
         int64_t nblk = 0;
     };
@@ -205,7 +206,7 @@ struct BatchImpl {
         if (count() == 0) return;
         const int f = otf ? 1 : 0;
         for (const auto &g : groups[f]) {
-            launch_ax_batch(g.N, otf, d_ax[f], g.blk, g.nblk, g.epb, order_D[g.N].data(),
+            launch_ax_batch(g.N, otf, g.mfma, d_ax[f], g.blk, g.nblk, g.epb, order_D[g.N].data(),
                             order_xi[g.N].data(), order_w[g.N].data(), s);
         }
         if (n_gs_blk > 0)
@@ -323,6 +324,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     std::vector<int2> gs_blk, upd_blk, gsum_blk, updg_blk;
     std::map<int, std::vector<int2>> order_blk[2];
     std::map<int, int> order_epb[2];
+    std::map<int, bool> order_mfma[2];
     ensure_cap(d_cls, cap_cls, count, bytes);
     for (int q = 0; q < count; ++q) {
         Mesh &m = *ms[q];
@@ -342,6 +344,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
         for (int f = 0; f < 2; ++f) {
             const AxArgs<float> &af = ax[f].back();
             order_epb[f][m.N] = af.epb;
+            order_mfma[f][m.N] = af.mfma != 0;
             for (int64_t vb = 0; vb < af.vgrid; ++vb)
                 order_blk[f][m.N].push_back(make_int2(q, (int)vb));
         }
@@ -426,6 +429,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             OrderGroup g;
             g.N = kv.first;
             g.epb = order_epb[f][kv.first];
+            g.mfma = order_mfma[f][kv.first];
             g.nblk = (int64_t)kv.second.size();
             g.blk = dalloc<int2>(kv.second.size(), bytes);
             upload_sync(g.blk, kv.second);

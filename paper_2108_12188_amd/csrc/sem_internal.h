@@ -221,6 +221,8 @@ struct AxArgs {
                                 // nodes, [E][edge_slots(N)]
     T *x;                       // CgFused, may be null: solution; when st->x_lag,
                                 // x += alpha p_old (previous iteration's step)
+    int mfma;                   // host side: launch the matrix-core form (FP32,
+                                // N = 7; one element per wave-sized block)
 };
 
 // Jacobi preconditioning in the CG update (preconditioned CG, Sec. 3.2;
@@ -239,9 +241,15 @@ struct AxShape {
     int epb;
     int threads;
     size_t lds;
+    bool mfma;                  // matrix-core form (epb 1, one wave per block)
 };
 AxShape ax_shape(int N, bool fp64, bool otf, int epb_override);
 void ax_shape_set(int N, bool fp64, bool otf, int epb);
+// Contraction engine per order, precision and G form: 0 default, 1 VALU FMA,
+// 2 matrix cores (FP32, N = 7 only).
+constexpr int kAxEngineDefault = 0, kAxEngineValu = 1, kAxEngineMfma = 2;
+bool ax_mfma_available(int N, bool fp64);
+void ax_engine_set(int N, bool fp64, bool otf, int engine);
 int ax_shape_generation();
 
 // Fills the basis / geometry pointers and the shape from the mesh; the
@@ -253,8 +261,8 @@ int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override);
 void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a);
 // One FP32 CG-fused operator launch over many problems of order N:
 // blk[b] = (descriptor index, virtual block).
-void launch_ax_batch(int N, bool otf, const AxArgs<float> *descs, const int2 *blk, int64_t nblk,
-                     int epb, const double *D, const double *xi, const double *w,
+void launch_ax_batch(int N, bool otf, bool mfma, const AxArgs<float> *descs, const int2 *blk,
+                     int64_t nblk, int epb, const double *D, const double *xi, const double *w,
                      hipStream_t s);
 
 // gather-scatter / mask / vector kernels (sem_gs.hip, sem_vec.hip)
