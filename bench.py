@@ -245,8 +245,17 @@ def main(argv=None):
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS}
     roof["flops_tflops_paper"] = ax_flops_per_point(N, args.geom) * n / (ax_ms * 1e-3) / 1e12
-    roof["kernel"] = "ax_kernel<float, %s, CgFused> (p-update + previous x step + A_L + <p,w,c> partials)" % (
+    mfma = sem.ax_engine_get(N, sem.FP32, geom) == sem.ENGINE_MFMA
+    roof["kernel"] = "%s<%s, CgFused> (p-update + previous x step + A_L + <p,w,c> partials)" % (
+        "ax_mfma_kernel" if mfma else "ax_kernel<float>",
         "precomputed G" if args.geom == "pre" else "on-the-fly G")
+    roof["engine"] = "mfma" if mfma else "valu"
+    if mfma:
+        # the six D / D^T contractions on the 4x4x1 MFMA: 96 instructions of
+        # 512 flops per element
+        E = n // (N + 1) ** 3
+        roof["mfma_tflops"] = 96 * 512 * E / (ax_ms * 1e-3) / 1e12
+        roof["mfma_frac"] = roof["mfma_tflops"] / FP32_PEAK_TFLOPS
     roof["avg_ms"] = ax_ms
     roof["traffic"] = read_traffic(f"cg_fused_{args.geom}_N{N}", n)
 
@@ -271,6 +280,15 @@ def main(argv=None):
         torch.cuda.synchronize()
         extra["cg_fp32_%s_gdof" % ("otf" if args.geom == "pre" else "pre")] = \
             n * iters / (time.perf_counter() - t1) / 1e9
+        # the same fused operator on the other contraction engine (the
+        # choice rests on this comparison at this order)
+        if mfma:
+            sem.ax_engine_set(N, sem.FP32, geom, sem.ENGINE_VALU)
+            x.zero_()
+            _, pv = gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=min(iters, 200),
+                                kernel_times=True)
+            sem.ax_engine_set(N, sem.FP32, geom, sem.ENGINE_DEFAULT)
+            extra["ax_fused_valu_engine_ms"] = pv["kernel_ms"]["ax"]
         # plain FP64 CG on the same mesh (precomputed FP64 G)
         del u
         gm64 = sem.Mesh.from_box(mesh, g_fp32=False, g_fp64=True)

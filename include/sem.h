@@ -285,7 +285,8 @@ sem_status sem_ax_shape_get(int order_N, sem_precision prec, sem_geom geom, int 
  * N = 7, else SEM_EUNSUPPORTED).  The two engines accumulate every
  * contraction in the same order with fused multiply-adds, so their results
  * are bitwise identical.  SEM_AX_ENGINE_DEFAULT restores the built-in
- * choice.  Process-wide, used by later launches.  For the autotuner.
+ * choice (the matrix cores where available).  Process-wide, used by later
+ * launches.  For the autotuner.
  */
 typedef enum {
     SEM_AX_ENGINE_DEFAULT = 0,

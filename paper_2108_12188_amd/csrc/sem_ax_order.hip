@@ -205,6 +205,7 @@ __host__ __device__ constexpr size_t ax_lds_bytes(int epb) {
 
 // s_waitcnt immediates (gfx9 encoding): vmcnt(0) alone, lgkmcnt(0) alone
 constexpr int kWaitVmcnt0 = 0x0F70;
+constexpr int kWaitVmcnt8 = 0x0F78;
 constexpr int kWaitLgkmcnt0 = 0xC07F;
 
 // Barrier for LDS traffic only: the wave's own LDS accesses complete
@@ -220,14 +221,15 @@ __device__ __forceinline__ void lds_barrier() {
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 
-// The block copies nf floats (a multiple of 4; src and dst 16-byte aligned)
-// from global memory to LDS: every wave moves 64 x 16 bytes per
-// instruction, lane q of a wave landing at the wave's (uniform) LDS base +
-// 16 q.  Completion is tracked by vmcnt.
-__device__ __forceinline__ void dma_to_lds(const float *src, float *dst, int nf) {
+// The block's nwave waves copy nf floats (a multiple of 4; src and dst
+// 16-byte aligned) from global memory to LDS: every wave moves 64 x 16
+// bytes per instruction, lane q of a wave landing at the wave's (uniform)
+// LDS base + 16 q.  Completion is tracked by vmcnt.  (The wave count is an
+// argument: the block size lives in memory, and loading it would make the
+// wave wait for all of its outstanding stores.)
+__device__ __forceinline__ void dma_to_lds(const float *src, float *dst, int nf, int nwave) {
     const int pieces = nf >> 2;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int nwave = (int)((blockDim.x + 63) >> 6);
     const int lane = (int)(threadIdx.x & 63);
     for (int q0 = wave * 64; q0 < pieces; q0 += nwave * 64) {
         if (q0 + lane < pieces)
@@ -260,6 +262,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
     const int t = threadIdx.x;
     const int el = t / P2;
     const int col = t - el * P2;
+    const int nwave = (a.epb * P2 + 63) >> 6;   // the launch's block size in waves
     const int i = col % P;
     const int j = col / P;
     T *const sa = sA + el * P3;
@@ -303,17 +306,19 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         if constexpr (kDma) {
             const int64_t e0 = tl * a.epb;
             const int nval = (int)(a.E - e0 < a.epb ? a.E - e0 : a.epb);
-            dma_to_lds(reinterpret_cast<const float *>(a.u) + e0 * P3, sR, nval * P3);
-            dma_to_lds(reinterpret_cast<const float *>(a.p) + e0 * P3, sP, nval * P3);
+            dma_to_lds(reinterpret_cast<const float *>(a.u) + e0 * P3, sR, nval * P3, nwave);
+            dma_to_lds(reinterpret_cast<const float *>(a.p) + e0 * P3, sP, nval * P3, nwave);
             if constexpr (OTF)
-                dma_to_lds(reinterpret_cast<const float *>(a.vert) + e0 * 24, sV, nval * 24);
+                dma_to_lds(reinterpret_cast<const float *>(a.vert) + e0 * 24, sV, nval * 24,
+                           nwave);
         }
     };
     auto stage_x = [&](int64_t tl) {
         if constexpr (kDma) {
             const int64_t e0 = tl * a.epb;
             const int nval = (int)(a.E - e0 < a.epb ? a.E - e0 : a.epb);
-            if (xlag) dma_to_lds(reinterpret_cast<const float *>(a.x) + e0 * P3, sX, nval * P3);
+            if (xlag)
+                dma_to_lds(reinterpret_cast<const float *>(a.x) + e0 * P3, sX, nval * P3, nwave);
         }
     };
     if constexpr (kDma) {
@@ -462,27 +467,45 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
 // Matrix-core form (FP32, N = 7): one wave per element, so P^2 = 64 columns
 // fill the wave exactly and no barrier is needed (a wave's LDS accesses
 // complete in issue order).  Every contraction with D or D^T runs on the
-// 16-block 4x4x1 FP32 MFMA: block b of a wave multiplies the 4-vector held
-// by its lanes 4b..4b+3 (operand A) with each of those lanes' own value
-// (operand B), so after 8 steps l = 0..7 on the two row quads t = 0, 1,
-// lane q holds sum_l M[4t + r][l] x_q[l] (r = 0..3) for its own 8-vector
-// x_q: the whole 8 x 8 product of M with the lane's vector.  The
-// accumulation is one fused multiply-add per step in the order l = 0..7,
-// which is bitwise the VALU loop of ax_body.  For the i- and j-directions
-// the lanes take the element's pencils along that direction from a padded
-// LDS tile (slice stride 72 floats: the column, i-pencil and j-pencil
-// access patterns are all free of bank conflicts), and the results return
-// to the column layout through the same tile.
+// 16-block 4x4x1 FP32 MFMA: block b of a wave multiplies the 4-vector of
+// operand A with each of its lanes' own value (operand B), so after 8
+// steps l = 0..7 on the two row quads, lane q holds sum_l M[r][l] x_q[l]
+// for r = 0..7 and its own 8-vector x_q: the whole 8 x 8 product of M with
+// the lane's vector.  The accumulation is one fused multiply-add per step
+// in the order l = 0..7, which is bitwise the VALU loop of ax_body.  For
+// the i- and j-directions the lanes take the element's pencils along that
+// direction from an LDS tile, and the results return to the column layout
+// through the same tile.
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaSlice = 72;                       // padded (i, j) slice, floats
-constexpr int kMfmaTile = kP * kMfmaSlice;           // padded element tile, floats
+// One wave copies one element's P^3 = 512 floats from global memory to LDS:
+// two 16-byte-per-lane direct loads, tracked by vmcnt.  The source base is
+// made wave-uniform (scalar base + the lane's constant offset), so the
+// loads hold no per-lane 64-bit address registers.
+__device__ __forceinline__ void dma_elem_to_lds(const float *src, float *dst) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t pa = reinterpret_cast<uint64_t>(src);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)pa);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
+    const float *su = reinterpret_cast<const float *>(((uint64_t)hi << 32) | lo);
+    // the immediate offset (1024 bytes) applies to the global and the LDS
+    // address alike
+    __builtin_amdgcn_global_load_lds((glb_void_t *)(su + 4 * lane), (lds_void_t *)dst, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((glb_void_t *)(su + 4 * lane), (lds_void_t *)dst, 16, 1024, 0);
+}
 
-template <bool OTF, bool FUSED>
-__host__ __device__ constexpr size_t ax_mfma_lds_bytes() {
-    constexpr size_t P3 = (size_t)kP * kP * kP;
-    return 4 * (2 * (size_t)kMfmaTile + (FUSED ? 2 * P3 + 32 : 0));
+// Element tile in LDS (512 floats): point (i, j, k) at
+//   (i ^ 4 (j >> 2)) + 8 (j ^ (k & 3)) + 64 k.
+// With 32 banks of 4 bytes, and 16-byte accesses served 8 lanes at a time,
+// the three access patterns are conflict-free: a column access (lanes over
+// (i, j) at one k) covers a whole slice; a j-pencil access (lanes over
+// (i, k) at one j) puts the 4 levels k of a 32-lane half on 4 different
+// rows j ^ (k & 3); and the 16-byte i-pencil accesses of 8 lanes (one k,
+// j = 0..7) hit 8 different 4-bank groups because rows j >= 4 swap their
+// two halves.
+__host__ __device__ constexpr int mfma_slot(int i, int j, int k) {
+    return (i ^ (4 * (j >> 2))) + 8 * (j ^ (k & 3)) + 64 * k;
 }
 
 // Exchange through LDS inside one wave: the wave's earlier LDS accesses
@@ -494,15 +517,19 @@ __device__ __forceinline__ void wave_lds_sync() {
     __asm__ volatile("" ::: "memory");
 }
 
-// out = M x for the lane's own 8-vector x; lane q holds rows 4t + (q & 3)
-// of M in m[t][0..7].
-__device__ __forceinline__ void mfma_apply8(const float (&m)[2][kP], const float (&x)[kP],
+// out = M x for the lane's own 8-vector x.  The rows of M come from one
+// register per step l: every block takes operand A from the 4 lanes of
+// block AB (rows 0..3 of M) and AB + 1 (rows 4..7) through the MFMA's
+// A-operand broadcast (CBSZ = 4: all 16 blocks; ABID selects the block).
+// Lanes 0..7 hold the rows of D, lanes 8..15 the rows of D^T (AB = 0, 2).
+template <int AB>
+__device__ __forceinline__ void mfma_apply8(const float (&m)[kP], const float (&x)[kP],
                                             float (&out)[kP]) {
     v4f c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int l = 0; l < kP; ++l) {
-        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[0][l], x[l], c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[1][l], x[l], c1, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[l], x[l], c0, 4, AB, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[l], x[l], c1, 4, AB + 1, 0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -511,40 +538,58 @@ __device__ __forceinline__ void mfma_apply8(const float (&m)[2][kP], const float
     }
 }
 
+// The lane's pencil along i (lane q is (j, k) = (q & 7, q >> 3)) and along
+// j (lane q is (i, k) = (q & 7, q >> 3)): tile offsets.
+struct MfmaPencils {
+    int ilo, ihi;          // the two 16-byte halves i = 0..3 and 4..7
+    int j0, j1, jx;        // element l along j: (l < 4 ? j0 : j1) + ((8 l) ^ jx)
+    __device__ __forceinline__ int jslot(int l) const { return (l < 4 ? j0 : j1) + ((8 * l) ^ jx); }
+};
+
+__device__ __forceinline__ MfmaPencils mfma_pencils(int q) {
+    const int a = q & 7, k = q >> 3;
+    MfmaPencils pc;
+    const int row = 8 * (a ^ (k & 3)) + 64 * k;      // i-pencil: row j = a at level k
+    const int sw = a >> 2;
+    pc.ilo = row + 4 * sw;
+    pc.ihi = row + 4 * (1 - sw);
+    pc.j0 = a + 64 * k;                               // j-pencil: column i = a at level k
+    pc.j1 = (a ^ 4) + 64 * k;
+    pc.jx = 8 * (k & 3);
+    return pc;
+}
+
 template <bool OTF, bool FUSED>
 __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const BasisK<float> &bk,
                                              int64_t ntiles, int64_t vb, int64_t vgrid) {
     if constexpr (kP == 8) {
         using T = float;
-        constexpr int P = kP, P2 = P * P, P3 = P2 * P, PS = kMfmaSlice;
+        constexpr int P = kP, P2 = P * P, P3 = P2 * P;
         constexpr bool kDma = FUSED;
-        extern __shared__ __align__(16) unsigned char lds_raw[];
-        float *const sA = reinterpret_cast<float *>(lds_raw);
-        float *const sB = sA + kMfmaTile;
-        // staging (fused): r, p and vertices of the next element; x of the
-        // next element lands in sB, which is free between elements
-        float *const sR = sB + kMfmaTile;
-        float *const sP = sR + P3;
-        float *const sV = sP + P3;
-        float *const sX = sB;
+        // Separate LDS objects: the compiler can then tell which accesses
+        // the staging loads in flight may touch (with one array every tile
+        // access would wait for them).  2 tiles + 3 staging buffers of
+        // 2 KB: 16 waves of a CU fit in its 160 KB.
+        __shared__ __align__(16) float sA[P3];
+        __shared__ __align__(16) float sB[P3];
+        __shared__ __align__(16) float sR[FUSED ? P3 : 4];   // next element's r
+        __shared__ __align__(16) float sP[FUSED ? P3 : 4];   // next element's p
+        __shared__ __align__(16) float sX[FUSED ? P3 : 4];   // next element's x
 
         if constexpr (FUSED) {
             if (a.st->stop) return;
         }
         const int q = threadIdx.x;        // column (i, j) = (q & 7, q >> 3)
         const int i = q & 7, j = q >> 3;
-        // pencil lanes: along i, lane q is (j, k) = (q & 7, q >> 3); along j,
-        // lane q is (i, k) = (q & 7, q >> 3)
-        const int ipen = 8 * (q & 7) + PS * (q >> 3);   // + i
-        const int jpen = (q & 7) + PS * (q >> 3);        // + 8 j
-        float Dm[2][P], DTm[2][P];
+        const int cq = q ^ ((q >> 5) << 2);                  // mfma_slot(i, j, 0) ^ row swizzle
+        auto cslot = [&](int k) { return (cq ^ (8 * (k & 3))) + 64 * k; };   // = mfma_slot(i, j, k)
+        const MfmaPencils pc = mfma_pencils(q);
+        // operand-A table: lane r < 8 holds row r of D, lane 8 + r row r of
+        // D^T, at step l in Dtab[l] (other lanes unused)
+        float Dtab[P];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int l = 0; l < P; ++l) {
-                Dm[t][l] = a.D[(4 * t + (q & 3)) * P + l];
-                DTm[t][l] = a.Dt[(4 * t + (q & 3)) * P + l];
-            }
+        for (int l = 0; l < P; ++l)
+            Dtab[l] = q < 8 ? a.D[q * P + l] : (q < 16 ? a.Dt[(q - 8) * P + l] : 0.f);
         T beta = T(0);
         bool xlag = false;
         T aprev = T(0);
@@ -561,23 +606,22 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
             eta_j = a.xi[j];
             wij = a.wq[i] * a.wq[j];
         }
+        // vertices of an element: lane m < 24 loads coordinate m (one
+        // register), broadcast to the wave with readlane when used
+        auto load_vert = [&](int64_t e) -> float {
+            return q < 24 ? a.vert[e * 24 + q] : 0.f;
+        };
         auto stage = [&](int64_t e) {
             if constexpr (kDma) {
-                dma_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR, P3);
-                dma_to_lds(reinterpret_cast<const float *>(a.p) + e * P3, sP, P3);
-                if constexpr (OTF) dma_to_lds(reinterpret_cast<const float *>(a.vert) + e * 24, sV, 24);
+                dma_elem_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR);
+                dma_elem_to_lds(reinterpret_cast<const float *>(a.p) + e * P3, sP);
+                if (xlag) dma_elem_to_lds(reinterpret_cast<const float *>(a.x) + e * P3, sX);
             }
         };
-        auto stage_x = [&](int64_t e) {
-            if constexpr (kDma) {
-                if (xlag) dma_to_lds(reinterpret_cast<const float *>(a.x) + e * P3, sX, P3);
-            }
-        };
-        if constexpr (kDma) {
-            if (vb < ntiles) {
-                stage(vb);
-                stage_x(vb);
-            }
+        float vnext = 0.f;
+        if (vb < ntiles) {
+            if constexpr (kDma) stage(vb);
+            if constexpr (OTF) vnext = load_vert(vb);
         }
 
         double acc = 0.0;
@@ -585,7 +629,16 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
             const int64_t base = e * P3 + q;
             T *const wep = (FUSED && a.wedge && ecb >= 0) ? a.wedge + e * edge_slots(kOrder) + ecb
                                                           : nullptr;
-            if constexpr (kDma) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            // this element's staged data has landed: on the first element
+            // every load; later, all but the previous element's last 8
+            // vector-memory operations (its w stores, issued after the
+            // staging loads; vector-memory operations complete in order)
+            if constexpr (kDma) {
+                if (e == vb) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+                else __builtin_amdgcn_s_waitcnt(kWaitVmcnt8);
+                __asm__ volatile("" ::: "memory");
+            }
+            const float vcur = vnext;
 
             T uc[P];
             if constexpr (kDma) {
@@ -603,14 +656,9 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
                 for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
             }
 #pragma unroll
-            for (int k = 0; k < P; ++k) sA[q + k * PS] = uc[k];
+            for (int k = 0; k < P; ++k) sA[cslot(k)] = uc[k];
             wave_lds_sync();
 
-            ColumnGeom<T> cg;
-            if constexpr (OTF) {
-                if constexpr (kDma) cg = column_geom<T>(sV, xi_i, eta_j, wij);
-                else cg = column_geom<T>(a.vert + e * 24, xi_i, eta_j, wij);
-            }
             constexpr bool kPre = !OTF && prefetch_g<T>();
             T gq[kPre ? 6 : 1][kPre ? P : 1];
             if constexpr (kPre) {
@@ -620,66 +668,80 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
 #pragma unroll
                     for (int k = 0; k < P; ++k) gq[c][k] = Ge[c * P3 + k * P2];
             }
-            // every read of this element's staging is done: stage the next
-            if constexpr (kDma) {
-                wave_lds_sync();
-                if (e + vgrid < ntiles) stage(e + vgrid);
-            }
 
             // gradient: k in the column's registers, i and j on pencils
             T ut[P], pi[P], pj[P], dri[P], dsj[P];
-            mfma_apply8(Dm, uc, ut);
+            mfma_apply8<0>(Dtab, uc, ut);
             {
-                const float4 lo = *reinterpret_cast<const float4 *>(sA + ipen);
-                const float4 hi = *reinterpret_cast<const float4 *>(sA + ipen + 4);
+                const float4 lo = *reinterpret_cast<const float4 *>(sA + pc.ilo);
+                const float4 hi = *reinterpret_cast<const float4 *>(sA + pc.ihi);
                 pi[0] = lo.x, pi[1] = lo.y, pi[2] = lo.z, pi[3] = lo.w;
                 pi[4] = hi.x, pi[5] = hi.y, pi[6] = hi.z, pi[7] = hi.w;
             }
 #pragma unroll
-            for (int l = 0; l < P; ++l) pj[l] = sA[jpen + 8 * l];
-            mfma_apply8(Dm, pi, dri);
-            mfma_apply8(Dm, pj, dsj);
-            *reinterpret_cast<float4 *>(sB + ipen) = make_float4(dri[0], dri[1], dri[2], dri[3]);
-            *reinterpret_cast<float4 *>(sB + ipen + 4) = make_float4(dri[4], dri[5], dri[6], dri[7]);
+            for (int l = 0; l < P; ++l) pj[l] = sA[pc.jslot(l)];
+            mfma_apply8<0>(Dtab, pi, dri);
+            mfma_apply8<0>(Dtab, pj, dsj);
+            *reinterpret_cast<float4 *>(sB + pc.ilo) = make_float4(dri[0], dri[1], dri[2], dri[3]);
+            *reinterpret_cast<float4 *>(sB + pc.ihi) = make_float4(dri[4], dri[5], dri[6], dri[7]);
 #pragma unroll
-            for (int l = 0; l < P; ++l) sA[jpen + 8 * l] = dsj[l];
+            for (int l = 0; l < P; ++l) sA[pc.jslot(l)] = dsj[l];
             wave_lds_sync();
+            // every read of this element's staging is long done: stage the next
+            if constexpr (kDma) {
+                if (e + vgrid < ntiles) stage(e + vgrid);
+            }
+            if constexpr (OTF) {
+                if (e + vgrid < ntiles) vnext = load_vert(e + vgrid);
+            }
+
+            // column geometry (after the gradient: fewer registers live)
+            ColumnGeom<T> cg;
+            if constexpr (OTF) {
+                T ve[24];
+#pragma unroll
+                for (int m = 0; m < 24; ++m)
+                    ve[m] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vcur), m));
+                cg = column_geom<T>(ve, xi_i, eta_j, wij);
+            }
 
             // pointwise G, back in the column layout
             T vt[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const T ur = sB[q + k * PS], us = sA[q + k * PS];
+                const int cs = cslot(k);
+                const T ur = sB[cs], us = sA[cs];
                 T vr, vs;
                 point_flux<T, OTF, kPre>(cg, bk, k, gq, OTF ? nullptr : a.G + e * (6 * P3) + q,
                                          ur, us, ut[k], vr, vs, vt[k]);
-                sB[q + k * PS] = vr;
-                sA[q + k * PS] = vs;
+                sB[cs] = vr;
+                sA[cs] = vs;
             }
             wave_lds_sync();
 
             // divergence: D^T along k in registers, along i and j on pencils
             T wt[P];
-            mfma_apply8(DTm, vt, wt);
+            mfma_apply8<2>(Dtab, vt, wt);
             {
-                const float4 lo = *reinterpret_cast<const float4 *>(sB + ipen);
-                const float4 hi = *reinterpret_cast<const float4 *>(sB + ipen + 4);
+                const float4 lo = *reinterpret_cast<const float4 *>(sB + pc.ilo);
+                const float4 hi = *reinterpret_cast<const float4 *>(sB + pc.ihi);
                 pi[0] = lo.x, pi[1] = lo.y, pi[2] = lo.z, pi[3] = lo.w;
                 pi[4] = hi.x, pi[5] = hi.y, pi[6] = hi.z, pi[7] = hi.w;
             }
 #pragma unroll
-            for (int l = 0; l < P; ++l) pj[l] = sA[jpen + 8 * l];
-            mfma_apply8(DTm, pi, dri);
-            mfma_apply8(DTm, pj, dsj);
-            *reinterpret_cast<float4 *>(sB + ipen) = make_float4(dri[0], dri[1], dri[2], dri[3]);
-            *reinterpret_cast<float4 *>(sB + ipen + 4) = make_float4(dri[4], dri[5], dri[6], dri[7]);
+            for (int l = 0; l < P; ++l) pj[l] = sA[pc.jslot(l)];
+            mfma_apply8<2>(Dtab, pi, dri);
+            mfma_apply8<2>(Dtab, pj, dsj);
+            *reinterpret_cast<float4 *>(sB + pc.ilo) = make_float4(dri[0], dri[1], dri[2], dri[3]);
+            *reinterpret_cast<float4 *>(sB + pc.ihi) = make_float4(dri[4], dri[5], dri[6], dri[7]);
 #pragma unroll
-            for (int l = 0; l < P; ++l) sA[jpen + 8 * l] = dsj[l];
+            for (int l = 0; l < P; ++l) sA[pc.jslot(l)] = dsj[l];
             wave_lds_sync();
 
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const T wv = (sB[q + k * PS] + sA[q + k * PS]) + wt[k];
+                const int cs = cslot(k);
+                const T wv = (sB[cs] + sA[cs]) + wt[k];
                 if constexpr (FUSED) {
                     acc += (double)uc[k] * (double)wv;
                     if (wep && (k == 0 || k == P - 1 || ecorner))
@@ -687,15 +749,12 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
                 }
                 a.w[base + k * P2] = wv;
             }
-            // every read of sB is done before the next element's x lands there
-            if constexpr (kDma) {
-                wave_lds_sync();
-                if (e + vgrid < ntiles) stage_x(e + vgrid);
-            }
         }
         if constexpr (FUSED) {
-            const double sum = block_sum(acc);
-            if (threadIdx.x == 0) a.partial[vb] = sum;
+            // the block is one wave: a shuffle reduction in a fixed order
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (threadIdx.x == 0) a.partial[vb] = acc;
         }
     }
 }
@@ -750,8 +809,7 @@ void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s
     if constexpr (sizeof(T) == 4 && kP == 8) {
         if (a.mfma) {
             // one element per wave-sized block
-            const size_t lds = ax_mfma_lds_bytes<OTF, FUSED>();
-            hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid), dim3(64), lds, s,
+            hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid), dim3(64), 0, s,
                                a, bk, a.E);
             return;
         }
@@ -789,14 +847,13 @@ static void ax_batch_entry(bool otf, bool mfma, const AxArgs<T> *descs, const in
     const BasisK<T> bk = make_basis<T>(D, xi, w);
     if constexpr (sizeof(T) == 4 && kP == 8) {
         if (mfma) {
-            const size_t lds_otf = ax_mfma_lds_bytes<true, true>();
-            const size_t lds_pre = ax_mfma_lds_bytes<false, true>();
+            // static LDS only
             if (otf)
-                hipLaunchKernelGGL((ax_mfma_batch_kernel<true>), dim3((unsigned)nblk), dim3(64),
-                                   lds_otf, s, descs, blk, bk);
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<true>), dim3((unsigned)nblk), dim3(64), 0,
+                                   s, descs, blk, bk);
             else
                 hipLaunchKernelGGL((ax_mfma_batch_kernel<false>), dim3((unsigned)nblk), dim3(64),
-                                   lds_pre, s, descs, blk, bk);
+                                   0, s, descs, blk, bk);
             return;
         }
     }
