@@ -1,11 +1,12 @@
-"""Autotuner of the local-operator tile shape (elements per workgroup).
+"""Autotuner of the local operator: contraction engine and tile shape.
 
 For every (order, precision, geometric-factor form) the tuner times the
 CG-fused operator kernel -- the kernel of the solver's iteration -- for
-every shape the kernel accepts (one thread per (i, j) column, at most 512
-threads and 64 KiB of LDS), with HIP events inside sem_cg_solve, and keeps
-the fastest.  Results are stored as JSON keyed by GPU architecture and
-applied with sem_ax_shape_set.
+every shape the VALU engine accepts (one thread per (i, j) column, at most
+512 threads and 64 KiB of LDS) and, where it is built, the matrix-core
+engine (one element per 64-lane workgroup), with HIP events inside
+sem_cg_solve, and keeps the fastest.  Results are stored as JSON keyed by
+GPU architecture and applied with sem_ax_engine_set / sem_ax_shape_set.
 
     python -m paper_2108_12188_amd.tune            # tune N = 5, 7, 9 and save
 """
@@ -39,7 +40,8 @@ def candidates(N: int, fp64: bool):
 
 
 def tune_one(N: int, prec: str, geom: str, target_points: int = 8_000_000, iters: int = 20):
-    """Returns (best epb, {epb: mean fused-operator ms})."""
+    """Returns (best candidate, {candidate: mean fused-operator ms}); a
+    candidate is "valu:<elements per block>" or "mfma"."""
     import numpy as np
     import torch
 
@@ -53,13 +55,24 @@ def tune_one(N: int, prec: str, geom: str, target_points: int = 8_000_000, iters
     dt = torch.float64 if fp64 else torch.float32
     b = torch.as_tensor(random_global_rhs(mesh).astype(np.float64), dtype=dt, device="cuda")
     times = {}
-    for epb in candidates(N, fp64):
-        sem.ax_shape_set(N, _PREC[prec], _GEOM[geom], epb)
+
+    def run(key):
         gm.cg_solve(b, prec=_PREC[prec], geom=_GEOM[geom], fixed_iters=3)
         _, r = gm.cg_solve(b, prec=_PREC[prec], geom=_GEOM[geom], fixed_iters=iters,
                            kernel_times=True)
-        times[epb] = r["kernel_ms"]["ax"]
+        times[key] = r["kernel_ms"]["ax"]
+
+    sem.ax_engine_set(N, _PREC[prec], _GEOM[geom], sem.ENGINE_VALU)
+    for epb in candidates(N, fp64):
+        sem.ax_shape_set(N, _PREC[prec], _GEOM[geom], epb)
+        run(f"valu:{epb}")
     sem.ax_shape_set(N, _PREC[prec], _GEOM[geom], 0)
+    try:
+        sem.ax_engine_set(N, _PREC[prec], _GEOM[geom], sem.ENGINE_MFMA)
+        run("mfma")
+    except sem.SemError:
+        pass                                  # not built for this order / precision
+    sem.ax_engine_set(N, _PREC[prec], _GEOM[geom], sem.ENGINE_DEFAULT)
     gm.close()
     best = min(times, key=times.get)
     return best, times
@@ -76,20 +89,16 @@ def autotune(orders=(5, 7, 9), precs=("fp32",), geoms=("pre", "otf"), path: str 
         for prec in precs:
             for geom in geoms:
                 best, times = tune_one(N, prec, geom)
-                entries.append({"N": N, "prec": prec, "geom": geom, "elems_per_block": best,
-                                "ax_ms": {str(k): v for k, v in times.items()}})
-                print(f"tune N={N} {prec} {geom}: best {best} "
-                      f"({times[best] * 1e3:.1f} us; default {times.get(_default(N, prec), 0) * 1e3:.1f} us)",
+                engine = "mfma" if best == "mfma" else "valu"
+                epb = 1 if best == "mfma" else int(best.split(":")[1])
+                entries.append({"N": N, "prec": prec, "geom": geom, "engine": engine,
+                                "elems_per_block": epb, "ax_ms": times})
+                print(f"tune N={N} {prec} {geom}: best {best} ({times[best] * 1e3:.1f} us)",
                       flush=True)
     data = {"arch": arch(), "entries": entries}
     with open(path, "w") as f:
         json.dump(data, f, indent=1)
     return data
-
-
-def _default(N: int, prec: str) -> int:
-    import paper_2108_12188_amd as sem
-    return sem.ax_shape_get(N, _PREC[prec], 0)["elems_per_block"]
 
 
 def apply(path: str = CACHE) -> int:
@@ -102,12 +111,19 @@ def apply(path: str = CACHE) -> int:
     if data.get("arch") != arch():
         return 0
     for e in data.get("entries", []):
-        sem.ax_shape_set(e["N"], _PREC[e["prec"]], _GEOM[e["geom"]], e["elems_per_block"])
+        p, g = _PREC[e["prec"]], _GEOM[e["geom"]]
+        engine = e.get("engine")              # absent: keep the built-in engine
+        if engine == "mfma":
+            sem.ax_engine_set(e["N"], p, g, sem.ENGINE_MFMA)
+        else:
+            if engine == "valu":
+                sem.ax_engine_set(e["N"], p, g, sem.ENGINE_VALU)
+            sem.ax_shape_set(e["N"], p, g, e["elems_per_block"])
     return len(data.get("entries", []))
 
 
 def main(argv=None):
-    ap = argparse.ArgumentParser(description="tile-shape autotuner")
+    ap = argparse.ArgumentParser(description="operator engine and tile-shape autotuner")
     ap.add_argument("--orders", default="5,7,9")
     ap.add_argument("--precs", default="fp32")
     ap.add_argument("--out", default=CACHE)
