@@ -176,7 +176,11 @@ typedef struct {
     double tol;           /* stop when ||r||_c / ||r0||_c <= tol (MIXED: true FP64 residual / ||b||_c) */
     int max_iter;         /* iteration cap (MIXED: cap on inner iterations per outer step) */
     int fixed_iters;      /* > 0: run exactly this many iterations, no convergence test */
-    double inner_tol;     /* MIXED: relative tolerance of each inner FP32 solve (0 -> 1e-5) */
+    double inner_tol;     /* MIXED: tightest relative tolerance of an inner FP32 solve
+                             (0 -> 1e-5); each inner solve stops at
+                             max(inner_tol, 0.1 tol / rel), rel the current outer
+                             relative residual, so the last step solves only as far
+                             as tol requires */
     int max_outer;        /* MIXED: cap on outer refinement steps (0 -> 20) */
     int poll_every;       /* iterations per graph launch between host checks (0 -> auto) */
     int use_graph;        /* 1: replay captured HIP graphs; 0: plain launches */

@@ -595,7 +595,7 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
                 Workspace &w64 = cg_workspace(m, true);
                 float *b32 = static_cast<float *>(w32.b);
                 launch_scale_to_f32(m.n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
-                set_state(m, true, inner_tol, inner_cap, 0, s);
+                set_state(m, true, refine_inner_tol(inner_tol, o.tol, rel[q]), inner_cap, 0, s);
                 SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * m.n, s));
                 launch_cg_init<float>(m, b32, nullptr, static_cast<float *>(w32.r),
                                       static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
@@ -779,7 +779,8 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
             Workspace &w32 = cg_workspace(*r.m, false);
             float *b32 = static_cast<float *>(w32.b);
             launch_scale_to_f32(r.m->n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
-            set_state(*r.m, true, sv.inner_tol, sv.inner_cap, 0, s);
+            set_state(*r.m, true, refine_inner_tol(sv.inner_tol, sv.o.tol, r.rel), sv.inner_cap,
+                      0, s);
             SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * r.m->n, s));
             launch_cg_init<float>(*r.m, b32, nullptr, static_cast<float *>(w32.r),
                                   static_cast<float *>(w32.p), w32.st, w32.part_vec, s);

@@ -472,7 +472,8 @@ static sem_status cg_mixed(Mesh &m, const sem_cg_opts &o, const double *b, doubl
         launch_scale_to_f32(m.n, r64, w64.dval + 0, b32, s);
         SEM_HIP(hipEventRecord(w64.ev, s));
         SEM_HIP(hipStreamWaitEvent(w32.stream, w64.ev, 0));
-        InnerOut io = cg_core<float>(m, w32, b32, true, otf, pc, inner_tol, inner_cap, 0, chunk,
+        InnerOut io = cg_core<float>(m, w32, b32, true, otf, pc,
+                                     refine_inner_tol(inner_tol, o.tol, rel), inner_cap, 0, chunk,
                                      o.use_graph != 0, 0, o.kernel_ms ? &kt : nullptr);
         total += io.iters;
         last_stop = io.stop;

@@ -167,6 +167,18 @@ struct Mesh {
 
 Mesh *as_mesh(sem_mesh_t m);
 
+// Relative tolerance of one inner FP32 solve of the mixed-precision
+// refinement when the outer relative residual is rel and the target is tol:
+// the reduction still needed, with a factor 10 to spare, but never tighter
+// than the configured inner tolerance (nor looser than 1/2).  The last
+// outer step then solves only as far as the target requires.
+inline double refine_inner_tol(double inner_tol, double tol, double rel) {
+    double t = rel > 0.0 ? 0.1 * tol / rel : inner_tol;
+    if (t < inner_tol) t = inner_tol;
+    if (t > 0.5) t = 0.5;
+    return t;
+}
+
 // Host tables of a mesh's scatter map (sem_tables.cpp; no device calls).
 struct HostTables {
     int64_t n_glob = 0, n_groups = 0, n_shared = 0, n_dir = 0;
