@@ -367,7 +367,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
                              static_cast<float *>(ws.gsum), ws.st});
             for (int64_t lb = m.gs_blk_multi; lb < nlb; ++lb)
                 gsum_blk.push_back(make_int2((int)gsumd.size() - 1, (int)lb));
-            const vecb::GatherMap gm{m.surf_slot, m.slink, m.p3_magic, m.p3_shift, m.P3, m.S};
+            const vecb::GatherMap gm{m.gsrc};
             updg.push_back({m.n, static_cast<float *>(ws.r), static_cast<const float *>(ws.w),
                             static_cast<const float *>(ws.gsum), m.mcode, gm, ws.st, ws.part_vec,
                             nv});

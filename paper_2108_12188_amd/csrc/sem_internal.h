@@ -128,17 +128,13 @@ struct Mesh {
     int32_t *gs_idx = nullptr;    // [n_shared], class-major, groups of M ascending indices
     int32_t *dir_idx = nullptr;   // [n_dir]
     // Shared sums inside the CG update (used when every shared point lies on
-    // the surface of its element's P^3 block): surf_slot[loc] ranks local
-    // node loc among the S surface nodes of an element (-1 inside);
-    // slink[e][slot] is the other copy of a pair (m = 2) or the rank of a
-    // larger group among the n_groups_multi groups with m > 2, whose sums a
-    // gather-scatter variant over blocks gs_blk_multi.. writes to a compact
-    // array.  Local index l = e P3 + loc, with e = (l * p3_magic) >> p3_shift.
+    // the surface of its element's P^3 block): gsrc[l] is the other copy of
+    // a pair (m = 2), the rank of a larger group among the n_groups_multi
+    // groups with m > 2 (whose sums a gather-scatter variant over blocks
+    // gs_blk_multi.. writes to a compact array), else l itself.
     bool gs_in_update = false;
-    int S = 0;
     int64_t n_groups_multi = 0, gs_blk_multi = 0;
-    int16_t *surf_slot = nullptr;  // [P3]
-    int32_t *slink = nullptr;      // [E][S]
+    int32_t *gsrc = nullptr;       // [n]
     // When every copy of a group with m > 2 is an edge or corner node of its
     // element (edge_slot), the CG operator also writes those nodes' values
     // to a compact [E][edge_slots(N)] array and the group sums read it:
@@ -147,8 +143,6 @@ struct Mesh {
     bool gsum_wedge = false;
     int64_t wedge_io0 = 0;
     int32_t *wedge_idx = nullptr;
-    uint32_t p3_magic = 0;
-    int p3_shift = 0;
     // Jacobi preconditioner (built on first use): 1 / diag(A) on the free
     // points, 0 on the Dirichlet points, local form
     double *minv64 = nullptr;
@@ -187,16 +181,12 @@ struct HostTables {
     std::vector<int32_t> gs_idx;    // class-major ascending member lists
     std::vector<int32_t> dir_idx;   // Dirichlet local points
     bool gs_in_update = false;      // every shared point on its element's surface
-    int S = 0;                      // surface nodes per element
     int64_t n_groups_multi = 0;     // groups with more than two copies
     int64_t gs_blk_multi = 0;       // their first gather-scatter block
     bool gsum_wedge = false;        // every copy of those groups an edge or corner node
     int64_t wedge_io0 = 0;          // gs_idx offset of the first such group
     std::vector<int32_t> wedge_idx; // copies' positions in the compact edge array
-    std::vector<int16_t> slot;      // [P3] surface slot or -1
-    std::vector<int32_t> slink;     // [E][S] (only when gs_in_update)
-    uint32_t p3_magic = 0;
-    int p3_shift = 0;
+    std::vector<int32_t> gsrc;      // [n] (only when gs_in_update), see Mesh::gsrc
 };
 // Validates glob_id / dirichlet (fail() on error) and fills t.
 void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, HostTables &t);

@@ -32,7 +32,7 @@ void upload(T *dst, const T *src, size_t count, hipStream_t s) {
 
 void free_mesh_arrays(Mesh *m) {
     void *ptrs[] = {m->vert64,     m->vert32,  m->G32,     m->G64,       m->B64,
-                    m->mcode,      m->gs_idx,  m->dir_idx, m->surf_slot, m->slink,
+                    m->mcode,      m->gs_idx,  m->dir_idx, m->gsrc,
                     m->wedge_idx,  m->basis_blob, m->scratch, m->state,   m->minv64,
                     m->minv32};
     for (void *p : ptrs)
@@ -64,7 +64,7 @@ size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec) {
     b += n * 8;                                    // mass
     b += n * 1;                                    // point codes
     b += n * 4 * 2;                                // group index list and Dirichlet list (bounds)
-    b += (size_t)E * surface_nodes(N) * 4 + P3 * 2;   // tables of the gather in the update
+    b += n * 4;                                        // table of the gather in the update
     b += n / 3 * 4;                                    // edge-array positions (bound)
     if (flags & SEM_MESH_G_FP32) b += n * 24;
     if (flags & SEM_MESH_G_FP64) b += n * 48;
@@ -109,13 +109,10 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     m->n_shared = t.n_shared;
     m->n_dir = t.n_dir;
     m->gs_in_update = t.gs_in_update;
-    m->S = t.S;
     m->n_groups_multi = t.n_groups_multi;
     m->gs_blk_multi = t.gs_blk_multi;
     m->gsum_wedge = t.gsum_wedge;
     m->wedge_io0 = t.wedge_io0;
-    m->p3_magic = t.p3_magic;
-    m->p3_shift = t.p3_shift;
 
     // ---- basis ---------------------------------------------------------------
     gll_points(N, m->h_xi, m->h_w);
@@ -131,10 +128,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         m->mcode = dev_alloc<uint8_t>(*m, (size_t)n);
         m->gs_idx = dev_alloc<int32_t>(*m, t.gs_idx.size());
         m->dir_idx = dev_alloc<int32_t>(*m, t.dir_idx.size());
-        if (t.gs_in_update) {
-            m->surf_slot = dev_alloc<int16_t>(*m, t.slot.size());
-            m->slink = dev_alloc<int32_t>(*m, t.slink.size());
-        }
+        if (t.gs_in_update) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
         if (t.gsum_wedge) m->wedge_idx = dev_alloc<int32_t>(*m, t.wedge_idx.size());
         // basis blob: FP64 D, Dt, xi, w then FP32 D, Dt, xi, w
         const size_t PP = (size_t)P * P;
@@ -169,8 +163,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         upload(m->gs_idx, t.gs_idx.data(), t.gs_idx.size(), s);
         upload(m->dir_idx, t.dir_idx.data(), t.dir_idx.size(), s);
         if (t.gs_in_update) {
-            upload(m->surf_slot, t.slot.data(), t.slot.size(), s);
-            upload(m->slink, t.slink.data(), t.slink.size(), s);
+            upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
         }
         if (t.gsum_wedge) upload(m->wedge_idx, t.wedge_idx.data(), t.wedge_idx.size(), s);
         upload(b64, h64.data(), nd, s);

@@ -20,33 +20,6 @@ int surface_nodes(int N) {
     return P * P * P - (Pi > 0 ? Pi * Pi * Pi : 0);
 }
 
-// Rank of every local node among the surface nodes of its element, in
-// ascending local index (-1 for interior nodes).
-static std::vector<int16_t> surface_slots(int N) {
-    const int P = N + 1;
-    std::vector<int16_t> slot((size_t)P * P * P, -1);
-    int16_t s = 0;
-    for (int k = 0; k < P; ++k)
-        for (int j = 0; j < P; ++j)
-            for (int i = 0; i < P; ++i)
-                if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N)
-                    slot[i + P * (j + P * k)] = s++;
-    return slot;
-}
-
-// Division of l < 2^31 by d (1 <= d < 2^16) as (l * magic) >> shift with
-// shift = 31 + ceil(log2 d) and magic = ceil(2^shift / d) < 2^32: the
-// rounding excess magic * d - 2^shift is below d <= 2^(shift - 31), so the
-// error term l (magic d - 2^shift) / (d 2^shift) stays below 1/d and
-// never crosses an integer.
-static void division_magic(uint32_t d, uint32_t &magic, int &shift) {
-    int lg = 0;
-    while ((1u << lg) < d) ++lg;
-    shift = 31 + lg;
-    const unsigned __int128 one = 1;
-    magic = (uint32_t)(((one << shift) + d - 1) / d);
-}
-
 void gs_classes_finish(GsClasses &c) {
     int64_t blk = 0;
     for (int q = 0; q < c.ncls; ++q) {
@@ -199,29 +172,28 @@ void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, Host
     for (int64_t l = 0; l < n; ++l)
         if (mcode[l] & kDirichletBit) dir_idx.push_back((int32_t)l);
 
-    // Tables of the gather inside the CG update: possible when every shared
+    // Table of the gather inside the CG update, used when every shared
     // point lies on its element's surface (true of every conforming mesh:
-    // shared nodes are face, edge and vertex nodes).  The entry of a pair
+    // shared nodes are face, edge and vertex nodes; a mesh tying interior
+    // nodes takes the separate gather-scatter pass).  The entry of a pair
     // point is its partner's local index; that of a point in a larger group
     // is the group's rank among the groups with m > 2, in class order (the
-    // order of the group-sum kernel's output).
-    t.slot = surface_slots(N);
-    const std::vector<int16_t> &slot = t.slot;
-    const int S = surface_nodes(N);
+    // order of the group-sum kernel's output); any other point holds its own
+    // index.  One entry per point: the update loads 4 at once.
     bool ok = true;
-    for (int64_t l = 0; l < n && ok; ++l)
-        if ((mcode[l] & kMultMask) > 1 && slot[l % P3] < 0) ok = false;
-    t.slink.clear();
+    for (int64_t l = 0; l < n && ok; ++l) {
+        if ((mcode[l] & kMultMask) <= 1) continue;
+        const int loc = (int)(l % P3), i = loc % P, j = (loc / P) % P, k = loc / (P * P);
+        if (!(i == 0 || i == N || j == 0 || j == N || k == 0 || k == N)) ok = false;
+    }
+    t.gsrc.clear();
     if (ok) {
-        t.slink.assign((size_t)E * S, 0);
-        for (int64_t l = 0; l < n; ++l) {
-            const int sl = slot[l % P3];
-            if (sl >= 0) t.slink[(size_t)(l / P3) * S + sl] = plink[l];
-        }
+        t.gsrc.resize((size_t)n);
+        for (int64_t l = 0; l < n; ++l)
+            t.gsrc[l] = (mcode[l] & kMultMask) > 1 ? plink[l] : (int32_t)l;
     }
     std::vector<int32_t>().swap(plink);
     t.gs_in_update = ok;
-    t.S = S;
 
     // compact edge-array positions of the copies of the groups with m > 2
     t.gsum_wedge = false;
@@ -253,7 +225,6 @@ void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, Host
         t.gsum_wedge = all_edge;
         if (!all_edge) t.wedge_idx.clear();
     }
-    division_magic((uint32_t)P3, t.p3_magic, t.p3_shift);
 
 }
 

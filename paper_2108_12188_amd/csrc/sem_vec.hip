@@ -236,7 +236,7 @@ void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgStat
                           double *partial, hipStream_t s, PcArgs<T> pc) {
     if (!m.gs_in_update)
         fail(SEM_EUNSUPPORTED, "mesh shares points inside elements: no gather in the update");
-    const GatherMap gm{m.surf_slot, m.slink, m.p3_magic, m.p3_shift, m.P3, m.S};
+    const GatherMap gm{m.gsrc};
     const int nb = vec_blocks(m.n);
     if (pc.minv)
         hipLaunchKernelGGL((update_gather_kernel<T, true>), dim3(nb), dim3(kVecThreads), 0, s,

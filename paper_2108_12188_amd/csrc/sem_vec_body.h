@@ -98,27 +98,12 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
     }
 }
 
-// Where the sums over the copies are formed inside the update (the tables
-// of the mesh, see Mesh::slink).
+// Where the sums over the copies are formed inside the update: per local
+// point the partner of a pair point, the group rank of a point in a larger
+// group, else the point's own index (see Mesh::gsrc).
 struct GatherMap {
-    const int16_t *surf_slot;    // [P3]
-    const int32_t *slink;        // [E][S]
-    uint32_t p3_magic;
-    int p3_shift;
-    int P3;
-    int S;
+    const int32_t *gsrc;         // [n]
 };
-
-// Entry of the gather table for local point l: the partner of a pair point,
-// the group rank of a point in a larger group (its element's first entry
-// for nodes inside the element, so the load is always in bounds).  slot:
-// the surface-slot table (in LDS on the device).
-__host__ __device__ __forceinline__ int32_t node_link(uint32_t l, const GatherMap &g,
-                                                      const int16_t *slot) {
-    const uint32_t e = (uint32_t)(((uint64_t)l * g.p3_magic) >> g.p3_shift);
-    const int sl = slot[l - e * (uint32_t)g.P3];
-    return g.slink[(size_t)e * g.S + (sl > 0 ? sl : 0)];
-}
 
 // Code of a pair point off the Dirichlet boundary: m = 2, flag clear.
 constexpr uint8_t kPairCode = 2;
@@ -156,9 +141,10 @@ __host__ __device__ __forceinline__ T copies_sum(T own, uint8_t code, T src) {
 // modified).  Same grid, same per-thread order and the same sums as
 // gather-scatter + update_body, so the results are bitwise those of the
 // two-pass form.  All loads are unconditional: two packs (q, q + stride)
-// per step, each costing two dependent rounds of loads, all loads of both
-// issued before any result is used; the sum of r^2/m still runs pack by
-// pack in the thread's order q, q + stride, q + 2 stride, ...
+// per step, each costing two dependent rounds of loads (r, w, the codes and
+// the 4 gather-table entries of a pack, then the 4 gathered values), all
+// loads of both packs issued before any result is used; the sum of r^2/m
+// still runs pack by pack in the thread's order q, q + stride, ...
 template <typename T, bool PC = false>
 __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
                                                    const T *__restrict__ w,
@@ -170,8 +156,6 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
     if (st->stop) return;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
-    __shared__ int16_t slot[kMaxP * kMaxP * kMaxP];
-    for (int q = threadIdx.x; q < gm.P3; q += blockDim.x) slot[q] = gm.surf_slot[q];
     weights_lds(cw);
     const T a = (T)st->alpha;
     double acc = 0.0, acc2 = 0.0;
@@ -186,9 +170,8 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
         Code4 mv[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const uint32_t l0 = (uint32_t)(4 * qq[h]);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) lk[h][t] = node_link(l0 + t, gm, slot);
+            const int4 g4 = reinterpret_cast<const int4 *>(gm.gsrc)[qq[h]];
+            lk[h][0] = g4.x, lk[h][1] = g4.y, lk[h][2] = g4.z, lk[h][3] = g4.w;
             rv[h] = reinterpret_cast<const Pack4<T> *>(r)[qq[h]];
             wv[h] = reinterpret_cast<const Pack4<T> *>(w)[qq[h]];
             mv[h] = reinterpret_cast<const Code4 *>(mcode)[qq[h]];
@@ -228,7 +211,7 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
     }
     for (int64_t q = 4 * n4 + tid; q < n; q += stride) {
         const uint8_t c = mcode[q];
-        const int32_t lk = node_link((uint32_t)q, gm, slot);
+        const int32_t lk = gm.gsrc[q];
         const T wg = copies_sum<T>(w[q], c, *gather_source<T>(w, gsum, c, lk, q));
         const T rn = r[q] - a * wg;
         r[q] = rn;

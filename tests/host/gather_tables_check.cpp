@@ -64,8 +64,6 @@ int main(int argc, char **argv) {
     sem::HostTables t;
     sem::build_tables(E, N, gid.data(), dir.data(), t);
     int64_t l = -1;
-    CHECK(t.S == sem::surface_nodes(N), "S");
-    CHECK((int)t.slot.size() == P3, "slot table size");
 
     // reference: copies of every global id in ascending local index
     std::map<int64_t, std::vector<int64_t>> copies;
@@ -148,22 +146,20 @@ int main(int argc, char **argv) {
                 }
             }
         }
-        const sem::vecb::GatherMap gm{t.slot.data(), t.slink.data(), t.p3_magic, t.p3_shift, P3,
-                                      t.S};
+        const sem::vecb::GatherMap gm{t.gsrc.data()};
+        CHECK(t.gsrc.size() == (size_t)n, "gather table size %zu", t.gsrc.size());
         for (l = 0; l < n; ++l) {
-            const uint32_t e = (uint32_t)(((uint64_t)l * t.p3_magic) >> t.p3_shift);
-            CHECK(e == (uint64_t)(l / P3), "element %u by multiply-shift, %lld by division", e,
-                  (long long)(l / P3));
-            const int sl = t.slot[l - (int64_t)e * P3];
-            CHECK(sl >= -1 && sl < t.S, "slot %d", sl);
-            CHECK((size_t)e * t.S + (sl > 0 ? sl : 0) < t.slink.size(), "gather table index");
-            const int32_t lk = sem::vecb::node_link((uint32_t)l, gm, t.slot.data());
+            const int loc = (int)(l % P3), li = loc % P, lj = (loc / P) % P, lk_ = loc / (P * P);
+            const bool surface = li == 0 || li == N || lj == 0 || lj == N || lk_ == 0 || lk_ == N;
+            const int32_t lk = gm.gsrc[l];
+            CHECK(lk >= 0 && lk < n, "gather table entry %d", lk);
             const uint8_t code = t.mcode[l];
             const int m = code & sem::kMultMask;
             const std::vector<int64_t> &cp = copies[gid[l]];
             CHECK((int)cp.size() == m, "multiplicity %d, copies %zu", m, cp.size());
             if (m != 1 && m != 2 && m != 4 && m != 8) ++odd_m;
-            if (m >= 2) CHECK(sl >= 0, "shared point not on the element surface");
+            if (m >= 2) CHECK(surface, "shared point not on the element surface");
+            if (m <= 1) CHECK(lk == l, "own entry %d for point %lld", lk, (long long)l);
             if (m == 2) {
                 const int64_t other = cp[0] == l ? cp[1] : cp[0];
                 CHECK(lk == other, "partner %d, expected %lld", lk, (long long)other);
