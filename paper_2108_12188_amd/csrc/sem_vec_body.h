@@ -9,7 +9,15 @@ namespace sem {
 namespace vecb {
 
 constexpr int kVecThreads = 256;
-constexpr int kVecMaxBlocks = 2048;
+#ifndef SEM_VEC_MAX_BLOCKS
+#define SEM_VEC_MAX_BLOCKS 2048
+#endif
+constexpr int kVecMaxBlocks = SEM_VEC_MAX_BLOCKS;
+// packs of 4 points a thread of the gather update keeps in flight per step
+#ifndef SEM_UPD_PACKS
+#define SEM_UPD_PACKS 2
+#endif
+constexpr int kUpdPacks = SEM_UPD_PACKS;
 
 template <typename T>
 struct alignas(4 * sizeof(T)) Pack4 {
@@ -162,34 +170,39 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
-    for (int64_t q = tid; q < n4; q += 2 * stride) {
-        const bool two = q + stride < n4;
-        const int64_t qq[2] = {q, two ? q + stride : q};
-        int32_t lk[2][4];
-        Pack4<T> rv[2], wv[2];
-        Code4 mv[2];
+    constexpr int K = kUpdPacks;
+    for (int64_t q = tid; q < n4; q += K * stride) {
+        int64_t qq[K];
+        bool live[K];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < K; ++h) {
+            live[h] = q + h * stride < n4;
+            qq[h] = live[h] ? q + h * stride : q;
+        }
+        int32_t lk[K][4];
+        Pack4<T> rv[K], wv[K];
+        Code4 mv[K];
+#pragma unroll
+        for (int h = 0; h < K; ++h) {
             const int4 g4 = reinterpret_cast<const int4 *>(gm.gsrc)[qq[h]];
             lk[h][0] = g4.x, lk[h][1] = g4.y, lk[h][2] = g4.z, lk[h][3] = g4.w;
             rv[h] = reinterpret_cast<const Pack4<T> *>(r)[qq[h]];
             wv[h] = reinterpret_cast<const Pack4<T> *>(w)[qq[h]];
             mv[h] = reinterpret_cast<const Code4 *>(mcode)[qq[h]];
         }
-        T src[2][4];
+        T src[K][4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < K; ++h)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 src[h][t] = *gather_source<T>(w, gsum, mv[h].v[t], lk[h][t],
                                               (int64_t)(4 * qq[h] + t));
-        // without a second pack (!two) the first is computed twice: the
-        // second copy stores the same values and adds exactly 0 to the sum
-        // (every result is consumed on every path, so no load of this step
-        // is still pending when the next step reuses its registers)
+        // a pack past the end (!live) repeats the first: it stores the same
+        // values and adds exactly 0 to the sums (every result is consumed on
+        // every path, so no load of this step is still pending when the next
+        // step reuses its registers)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const bool live = h == 0 || two;
+        for (int h = 0; h < K; ++h) {
             Pack4<T> mi{}, zv{};
             if constexpr (PC) mi = reinterpret_cast<const Pack4<T> *>(pc.minv)[qq[h]];
 #pragma unroll
@@ -199,10 +212,10 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
                 const double rd = (double)rv[h].v[t];
                 if constexpr (PC) {
                     zv.v[t] = mi.v[t] * rv[h].v[t];
-                    acc += live ? rd * (double)zv.v[t] * cw[mv[h].v[t]] : 0.0;
-                    acc2 += live ? rd * rd * cw[mv[h].v[t]] : 0.0;
+                    acc += live[h] ? rd * (double)zv.v[t] * cw[mv[h].v[t]] : 0.0;
+                    acc2 += live[h] ? rd * rd * cw[mv[h].v[t]] : 0.0;
                 } else {
-                    acc += live ? rd * rd * cw[mv[h].v[t]] : 0.0;
+                    acc += live[h] ? rd * rd * cw[mv[h].v[t]] : 0.0;
                 }
             }
             reinterpret_cast<Pack4<T> *>(r)[qq[h]] = rv[h];
