@@ -167,3 +167,32 @@ def test_mfma_mixed_and_batch():
                 assert torch.equal(xs[q], xq), (geom, q)
     for g in gms:
         g.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 1, 1), (3, 5, 1)], ids=["E1", "E7", "E15"])
+def test_mfma_small_and_odd_meshes(shape):
+    """One element (a single wave-sized block), and odd element counts: the
+    operator and 15 CG iterations bitwise equal to the VALU engine, the CG
+    iterates against the oracle."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"mfma small mesh {shape}")
+    mesh = box_mesh(*shape, 7, perturb=0.1 if min(shape) > 1 else 0.0, seed=81, reorient=True)
+    pr = oracle.Problem(mesh)
+    gm = sem.Mesh.from_box(mesh)
+    u = to_dev(random_local(mesh.n_local, seed=82).astype(np.float32), torch.float32)
+    b = random_global_rhs(mesh, seed=83)
+    bd = to_dev(b, torch.float32)
+    out = {}
+    for eng in (sem.ENGINE_VALU, sem.ENGINE_MFMA):
+        with engine(sem, eng):
+            w = gm.ax(u, geom=sem.ON_THE_FLY)
+            x, r = gm.cg_solve(bd, prec=sem.FP32, geom=sem.ON_THE_FLY, fixed_iters=15,
+                               history=16)
+        out[eng] = (w, x, r)
+    assert torch.equal(out[sem.ENGINE_VALU][0], out[sem.ENGINE_MFMA][0])
+    assert torch.equal(out[sem.ENGINE_VALU][1], out[sem.ENGINE_MFMA][1])
+    xo, _, hist = pr.cg(b, fixed=15)
+    np.testing.assert_allclose(out[sem.ENGINE_MFMA][2]["hist_rho"][:11], hist["rho"][:11],
+                               rtol=1e-4)
+    gm.close()
