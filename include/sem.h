@@ -285,11 +285,13 @@ sem_status sem_ax_shape_get(int order_N, sem_precision prec, sem_geom geom, int 
  * G form: SEM_AX_ENGINE_VALU runs the D contractions as FP32/FP64 FMAs
  * (one thread per (i, j) column, sem_ax_shape_set picks elements per
  * block); SEM_AX_ENGINE_MFMA runs them on the FP32 matrix cores (16-block
- * 4x4x1 MFMA, one element per 64-lane workgroup; available for SEM_FP32 at
- * N = 7, else SEM_EUNSUPPORTED).  The two engines accumulate every
+ * 4x4x1 MFMA, one element per workgroup of 64 (N = 7) or 128 (N = 9)
+ * threads; available for SEM_FP32 at N = 7 and N = 9, else
+ * SEM_EUNSUPPORTED).  The two engines accumulate every
  * contraction in the same order with fused multiply-adds, so their results
  * are bitwise identical.  SEM_AX_ENGINE_DEFAULT restores the built-in
- * choice (the matrix cores where available).  Process-wide, used by later
+ * choice: the matrix cores at N = 7 in both G forms and at N = 9 with G on
+ * the fly, the VALU engine elsewhere.  Process-wide, used by later
  * launches.  For the autotuner.
  */
 typedef enum {

@@ -396,7 +396,7 @@ sem_status sem_ax_engine_set(int order_N, sem_precision prec, sem_geom geom, int
             engine != SEM_AX_ENGINE_MFMA)
             fail(SEM_EINVAL, "unknown engine");
         if (engine == SEM_AX_ENGINE_MFMA && !ax_mfma_available(order_N, prec == SEM_FP64))
-            fail(SEM_EUNSUPPORTED, "the matrix-core engine is built for FP32 at N = 7 only");
+            fail(SEM_EUNSUPPORTED, "the matrix-core engine is built for FP32 at N = 7 and 9 only");
         ax_engine_set(order_N, prec == SEM_FP64, geom == SEM_G_ON_THE_FLY, engine);
         return SEM_OK;
     });

@@ -64,8 +64,9 @@ constexpr int64_t kAxFusedMaxBlocks = SEM_AX_FUSED_MAX_BLOCKS;
 #endif
 constexpr int64_t kAxMfmaMaxBlocks = SEM_AX_MFMA_MAX_BLOCKS;
 
-static int64_t ax_grid(int64_t ntiles, AxMode mode, bool mfma) {
-    const int64_t cap = mfma ? kAxMfmaMaxBlocks : kAxFusedMaxBlocks;
+static int64_t ax_grid(int64_t ntiles, AxMode mode, bool mfma, int threads = 64) {
+    // matrix-core blocks: the same number of waves whatever their size
+    const int64_t cap = mfma ? kAxMfmaMaxBlocks * 64 / threads : kAxFusedMaxBlocks;
     if (mode == AxMode::CgFused && ntiles > cap) return cap;
     return ntiles;
 }
@@ -100,7 +101,7 @@ void ax_shape_set(int N, bool fp64, bool otf, int epb) {
     g_shape_gen.fetch_add(1);
 }
 
-bool ax_mfma_available(int N, bool fp64) { return N == 7 && !fp64; }
+bool ax_mfma_available(int N, bool fp64) { return (N == 7 || N == 9) && !fp64; }
 
 void ax_engine_set(int N, bool fp64, bool otf, int engine) {
     g_engine[otf ? 1 : 0][fp64 ? 1 : 0][N].store(engine);
@@ -113,14 +114,20 @@ AxShape ax_shape(int N, bool fp64, bool otf, int epb_override) {
     // default: the matrix cores where they are built (FP32, N = 7: the
     // fused operator is 14% faster there than with VALU FMA)
     const int engine = g_engine[otf ? 1 : 0][fp64 ? 1 : 0][N].load();
-    const bool mfma = engine == kAxEngineMfma || (engine == kAxEngineDefault);
+    // built-in choice: the matrix cores wherever they measured faster than
+    // the best VALU tile (N = 7 in both G forms, N = 9 with G on the fly;
+    // at N = 9 with G read from HBM two VALU elements per block are ahead)
+    const bool mfma = engine == kAxEngineMfma ||
+                      (engine == kAxEngineDefault && !(N == 9 && !otf));
     if (mfma && ax_mfma_available(N, fp64)) {
-        // one element per 64-lane block: two padded tiles (slices of 72
-        // floats) and the staging of r, p and the vertices
+        // one element per block (one wave at N = 7, two at N = 9): the
+        // operator tiles (two unpadded at N = 7, three of slices of 106
+        // floats at N = 9) and the staging of r, p, x and the vertices
         AxShape s;
         s.epb = 1;
-        s.threads = 64;
-        s.lds = 4 * (2 * (size_t)P * 72 + 2 * (size_t)P3 + 32);
+        s.threads = N == 9 ? 128 : 64;
+        s.lds = N == 9 ? 4 * (3 * (size_t)P * 106 + 3 * (size_t)P3 + 32)
+                       : 4 * (5 * (size_t)P3);
         s.mfma = true;
         return s;
     }
@@ -155,7 +162,7 @@ void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hip
     if (!otf) a.G = m.G32;
     const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
     kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(),
-               ax_grid(ntiles, mode, sh.mfma), s);
+               ax_grid(ntiles, mode, sh.mfma, sh.threads), s);
     check_hip(hipGetLastError(), "ax kernel launch (fp32)");
 }
 
@@ -188,7 +195,7 @@ void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
     a.wq = m.b32.w;
     a.vert = m.vert32;
     a.G = otf ? nullptr : m.G32;
-    a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma);
+    a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma, sh.threads);
 }
 
 void launch_ax_batch(int N, bool otf, bool mfma, const AxArgs<float> *descs, const int2 *blk,
@@ -201,7 +208,7 @@ void launch_ax_batch(int N, bool otf, bool mfma, const AxArgs<float> *descs, con
 
 int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override) {
     const AxShape sh = ax_shape(m.N, fp64, otf, epb_override);
-    return ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma);
+    return ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma, sh.threads);
 }
 
 }  // namespace sem

@@ -135,6 +135,13 @@ __device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T
     return g;
 }
 
+// a * b + c with one rounding.
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 // The pointwise step of A_L at level k of a column: (vr, vs, vt) = G (ur, us, ut)
 // with G rebuilt from the column geometry (on the fly) or read from HBM
 // (precomputed: gq when prefetched, else Ge = this column's factors).
@@ -166,9 +173,11 @@ __device__ __forceinline__ void point_flux(const ColumnGeom<T> &cg, const BasisK
             g11 = G[0], g12 = G[P3], g13 = G[2 * P3];
             g22 = G[3 * P3], g23 = G[4 * P3], g33 = G[5 * P3];
         }
-        vr = g11 * ur + g12 * us + g13 * ut;
-        vs = g12 * ur + g22 * us + g23 * ut;
-        vt = g13 * ur + g23 * us + g33 * ut;
+        // fused multiply-adds in a fixed order, so that every kernel (and
+        // both engines) rounds this product the same way
+        vr = fmadd(g13, ut, fmadd(g12, us, g11 * ur));
+        vs = fmadd(g23, ut, fmadd(g22, us, g12 * ur));
+        vt = fmadd(g33, ut, fmadd(g23, us, g13 * ur));
     }
 }
 
@@ -759,19 +768,266 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form for N = 9: P^2 = 100 columns, one element per block of
+// two waves (threads 100..127 shadow thread 99: they compute its values
+// and store nothing).  The contractions are those of ax_mfma_body with
+// three row quads (rows 10, 11 of the operand table are zero): lanes 0..11
+// of each wave hold the rows of D, lanes 12..23 those of D^T.  The waves
+// exchange pencils through LDS with barriers.  Tile: point (i, j, k) at
+// i + 10 j + 106 k (a column access covers consecutive words; a j-pencil
+// access of 32 lanes (i, k) lands on 32 consecutive banks because
+// 106 = 10 mod 32).  Same accumulation order as the VALU engine.
+// ---------------------------------------------------------------------------
+template <int AB>
+__device__ __forceinline__ void mfma_apply10(const float (&m)[kP], const float (&x)[kP],
+                                             float (&out)[kP]) {
+    v4f c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f}, c2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < kP; ++l) {
+        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[l], x[l], c0, 4, AB, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[l], x[l], c1, 4, AB + 1, 0);
+        c2 = __builtin_amdgcn_mfma_f32_4x4x1f32(m[l], x[l], c2, 4, AB + 2, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out[r] = c0[r];
+        out[4 + r] = c1[r];
+        if (8 + r < kP) out[8 + r] = c2[r];
+    }
+}
+
 template <bool OTF, bool FUSED>
-__global__ void __launch_bounds__(64, 4)
+__device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const BasisK<float> &bk,
+                                               int64_t ntiles, int64_t vb, int64_t vgrid) {
+    if constexpr (kP == 10) {
+        using T = float;
+        constexpr int P = kP, P2 = P * P, P3 = P2 * P, S = 106;
+        constexpr bool kDma = FUSED;
+        __shared__ __align__(16) float sA[P * S];
+        __shared__ __align__(16) float sB[P * S];
+        __shared__ __align__(16) float sC[P * S];
+        __shared__ __align__(16) float sR[FUSED ? P3 : 4];   // next element's r
+        __shared__ __align__(16) float sP[FUSED ? P3 : 4];   // next element's p
+        __shared__ __align__(16) float sX[FUSED ? P3 : 4];   // next element's x
+        __shared__ __align__(16) float sV[FUSED ? 32 : 4];   // next element's vertices
+
+        if constexpr (FUSED) {
+            if (a.st->stop) return;
+        }
+        const int t = threadIdx.x;
+        const bool active = t < P2;
+        const int c = active ? t : P2 - 1;             // column, i-pencil or j-pencil index
+        const int i = c % P, j = c / P;                 // column (i, j)
+        const int qw = t & 63;                          // lane in the wave
+        // operand-A table: lane r < 12 of each wave holds row r of D, lane
+        // 12 + r row r of D^T (rows 10, 11 zero), at step l in Dtab[l]
+        float Dtab[P];
+#pragma unroll
+        for (int l = 0; l < P; ++l)
+            Dtab[l] = qw < P ? a.D[qw * P + l]
+                             : (qw >= 12 && qw < 12 + P ? a.Dt[(qw - 12) * P + l] : 0.f);
+        // pencils: along i, index c is (j, k) = (c % P, c / P); along j,
+        // index c is (i, k) = (c % P, c / P)
+        const int ipen = P * (c % P) + S * (c / P);     // + i
+        const int jpen = (c % P) + S * (c / P);         // + P j
+        T beta = T(0);
+        bool xlag = false;
+        T aprev = T(0);
+        if constexpr (FUSED) {
+            beta = (T)a.st->beta;
+            xlag = a.x != nullptr && a.st->x_lag != 0;
+            aprev = (T)a.st->alpha;
+        }
+        const int ecb = edge_column_base(kOrder, i, j);
+        const bool ecorner = (i == 0 || i == P - 1) && (j == 0 || j == P - 1);
+        T xi_i = T(0), eta_j = T(0), wij = T(0);
+        if constexpr (OTF) {
+            xi_i = a.xi[i];
+            eta_j = a.xi[j];
+            wij = a.wq[i] * a.wq[j];
+        }
+        auto stage = [&](int64_t e) {
+            if constexpr (kDma) {
+                dma_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR, P3, 2);
+                dma_to_lds(reinterpret_cast<const float *>(a.p) + e * P3, sP, P3, 2);
+                if (xlag) dma_to_lds(reinterpret_cast<const float *>(a.x) + e * P3, sX, P3, 2);
+            }
+        };
+        auto stage_vert = [&](int64_t e) {
+            if constexpr (kDma && OTF)
+                dma_to_lds(reinterpret_cast<const float *>(a.vert) + e * 24, sV, 24, 2);
+        };
+        if constexpr (kDma) {
+            if (vb < ntiles) {
+                stage(vb);
+                stage_vert(vb);
+            }
+        }
+
+        double acc = 0.0;
+        for (int64_t e = vb; e < ntiles; e += vgrid) {
+            const int64_t base = e * P3 + c;
+            T *const wep = (FUSED && active && a.wedge && ecb >= 0)
+                               ? a.wedge + e * edge_slots(kOrder) + ecb
+                               : nullptr;
+            if constexpr (kDma) {
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+                lds_barrier();                          // every wave's share has landed
+            }
+            T uc[P];
+            if constexpr (kDma) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) uc[k] = sR[c + k * P2] + beta * sP[c + k * P2];
+                if (active) {
+#pragma unroll
+                    for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                    if (xlag) {
+#pragma unroll
+                        for (int k = 0; k < P; ++k)
+                            a.x[base + k * P2] = sX[c + k * P2] + aprev * sP[c + k * P2];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
+            }
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) sA[c + k * S] = uc[k];
+            }
+            lds_barrier();                              // (1) sA holds u; staging reads done
+            // every read of this element's r, p, x staging is done: stage the next
+            if constexpr (kDma) {
+                if (e + vgrid < ntiles) stage(e + vgrid);
+            }
+            constexpr bool kPre = !OTF && prefetch_g<T>();
+            T gq[kPre ? 6 : 1][kPre ? P : 1];
+            if constexpr (kPre) {
+                const T *Ge = a.G + e * (6 * P3) + c;
+#pragma unroll
+                for (int cc = 0; cc < 6; ++cc)
+#pragma unroll
+                    for (int k = 0; k < P; ++k) gq[cc][k] = Ge[cc * P3 + k * P2];
+            }
+
+            // gradient: i- and j-pencils of sA into sB and sC
+            T ut[P];
+            mfma_apply10<0>(Dtab, uc, ut);
+            {
+                T pi[P], pj[P], dri[P], dsj[P];
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    pi[l] = sA[ipen + l];
+                    pj[l] = sA[jpen + P * l];
+                }
+                mfma_apply10<0>(Dtab, pi, dri);
+                mfma_apply10<0>(Dtab, pj, dsj);
+                if (active) {
+#pragma unroll
+                    for (int l = 0; l < P; ++l) {
+                        sB[ipen + l] = dri[l];
+                        sC[jpen + P * l] = dsj[l];
+                    }
+                }
+            }
+            lds_barrier();                              // (2)
+
+            // column geometry, then G pointwise: each thread rewrites only
+            // its own column's slots, in place
+            ColumnGeom<T> cg;
+            if constexpr (OTF) {
+                if constexpr (kDma) cg = column_geom<T>(sV, xi_i, eta_j, wij);
+                else cg = column_geom<T>(a.vert + e * 24, xi_i, eta_j, wij);
+            }
+            T vt[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int cs = c + k * S;
+                const T ur = sB[cs], us = sC[cs];
+                T vr, vs;
+                point_flux<T, OTF, kPre>(cg, bk, k, gq, OTF ? nullptr : a.G + e * (6 * P3) + c,
+                                         ur, us, ut[k], vr, vs, vt[k]);
+                if (active) {
+                    sB[cs] = vr;
+                    sC[cs] = vs;
+                }
+            }
+            lds_barrier();                              // (3) the vertices were read too
+            if constexpr (kDma) {
+                if (e + vgrid < ntiles) stage_vert(e + vgrid);
+            }
+
+            // divergence: i-pencils of sB into sA, j-pencils of sC kept
+            // until every pencil read of sC is done
+            T wt[P];
+            mfma_apply10<3>(Dtab, vt, wt);
+            {
+                T pi[P], pj[P], dri[P], dsj[P];
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    pi[l] = sB[ipen + l];
+                    pj[l] = sC[jpen + P * l];
+                }
+                mfma_apply10<3>(Dtab, pi, dri);
+                mfma_apply10<3>(Dtab, pj, dsj);
+                if (active) {
+#pragma unroll
+                    for (int l = 0; l < P; ++l) sA[ipen + l] = dri[l];
+                }
+                lds_barrier();                          // (4)
+                if (active) {
+#pragma unroll
+                    for (int l = 0; l < P; ++l) sB[jpen + P * l] = dsj[l];
+                }
+            }
+            lds_barrier();                              // (5)
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const int cs = c + k * S;
+                    const T wv = (sA[cs] + sB[cs]) + wt[k];
+                    if constexpr (FUSED) {
+                        acc += (double)uc[k] * (double)wv;
+                        if (wep && (k == 0 || k == P - 1 || ecorner))
+                            wep[k == 0 ? 0 : (k == P - 1 ? 1 : 1 + k)] = wv;
+                    }
+                    a.w[base + k * P2] = wv;
+                }
+            }
+            lds_barrier();                              // (6) the next element rewrites sA
+        }
+        if constexpr (FUSED) {
+            const double sum = block_sum(acc);
+            if (threadIdx.x == 0) a.partial[vb] = sum;
+        }
+    }
+}
+
+// Matrix-core kernels: N = 7 on single-wave blocks, N = 9 on two-wave blocks.
+constexpr int kMfmaThreads = kP == 10 ? 128 : 64;
+constexpr int kMfmaWaves = kP == 10 ? 3 : 4;
+
+template <bool OTF, bool FUSED>
+__device__ __forceinline__ void ax_mfma_any(const AxArgs<float> &a, const BasisK<float> &bk,
+                                            int64_t ntiles, int64_t vb, int64_t vgrid) {
+    if constexpr (kP == 10) ax_mfma10_body<OTF, FUSED>(a, bk, ntiles, vb, vgrid);
+    else ax_mfma_body<OTF, FUSED>(a, bk, ntiles, vb, vgrid);
+}
+
+template <bool OTF, bool FUSED>
+__global__ void __launch_bounds__(kMfmaThreads, kMfmaWaves)
 ax_mfma_kernel(const AxArgs<float> a, const BasisK<float> bk, int64_t ntiles) {
-    ax_mfma_body<OTF, FUSED>(a, bk, ntiles, blockIdx.x, gridDim.x);
+    ax_mfma_any<OTF, FUSED>(a, bk, ntiles, blockIdx.x, gridDim.x);
 }
 
 template <bool OTF>
-__global__ void __launch_bounds__(64, 4)
+__global__ void __launch_bounds__(kMfmaThreads, kMfmaWaves)
 ax_mfma_batch_kernel(const AxArgs<float> *__restrict__ descs, const int2 *__restrict__ blk,
                      const BasisK<float> bk) {
     const int2 pv = blk[blockIdx.x];
     const AxArgs<float> a = descs[pv.x];
-    ax_mfma_body<OTF, true>(a, bk, a.E, pv.y, a.vgrid);
+    ax_mfma_any<OTF, true>(a, bk, a.E, pv.y, a.vgrid);
 }
 
 template <typename T, bool OTF, bool FUSED>
@@ -806,11 +1062,11 @@ BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
 
 template <typename T, bool OTF, bool FUSED>
 void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s) {
-    if constexpr (sizeof(T) == 4 && kP == 8) {
+    if constexpr (sizeof(T) == 4 && (kP == 8 || kP == 10)) {
         if (a.mfma) {
-            // one element per wave-sized block
-            hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid), dim3(64), 0, s,
-                               a, bk, a.E);
+            // one element per block (one wave at N = 7, two at N = 9)
+            hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid),
+                               dim3(kMfmaThreads), 0, s, a, bk, a.E);
             return;
         }
     }
@@ -845,15 +1101,15 @@ static void ax_batch_entry(bool otf, bool mfma, const AxArgs<T> *descs, const in
                            int64_t nblk, int epb, const double *D, const double *xi,
                            const double *w, hipStream_t s) {
     const BasisK<T> bk = make_basis<T>(D, xi, w);
-    if constexpr (sizeof(T) == 4 && kP == 8) {
+    if constexpr (sizeof(T) == 4 && (kP == 8 || kP == 10)) {
         if (mfma) {
             // static LDS only
             if (otf)
-                hipLaunchKernelGGL((ax_mfma_batch_kernel<true>), dim3((unsigned)nblk), dim3(64), 0,
-                                   s, descs, blk, bk);
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<true>), dim3((unsigned)nblk),
+                                   dim3(kMfmaThreads), 0, s, descs, blk, bk);
             else
-                hipLaunchKernelGGL((ax_mfma_batch_kernel<false>), dim3((unsigned)nblk), dim3(64),
-                                   0, s, descs, blk, bk);
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<false>), dim3((unsigned)nblk),
+                                   dim3(kMfmaThreads), 0, s, descs, blk, bk);
             return;
         }
     }

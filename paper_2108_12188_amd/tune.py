@@ -4,8 +4,8 @@ For every (order, precision, geometric-factor form) the tuner times the
 CG-fused operator kernel -- the kernel of the solver's iteration -- for
 every shape the VALU engine accepts (one thread per (i, j) column, at most
 512 threads and 64 KiB of LDS) and, where it is built, the matrix-core
-engine (one element per 64-lane workgroup), with HIP events inside
-sem_cg_solve, and keeps the fastest.  Results are stored as JSON keyed by
+engine (one element per workgroup of one or two waves), with HIP events
+inside sem_cg_solve, and keeps the fastest.  Results are stored as JSON keyed by
 GPU architecture and applied with sem_ax_engine_set / sem_ax_shape_set.
 
     python -m paper_2108_12188_amd.tune            # tune N = 5, 7, 9 and save

@@ -1,8 +1,8 @@
-"""The matrix-core engine of the local operator (FP32, N = 7): every
-contraction with D or D^T on the 16-block 4x4x1 MFMA, one element per
-64-lane workgroup.  It accumulates in the order of the VALU engine with
-fused multiply-adds, so its results must be bitwise those of the VALU
-engine (operator alone, CG with the fused operator, batches); the VALU
+"""The matrix-core engine of the local operator (FP32, N = 7 and N = 9):
+every contraction with D or D^T on the 16-block 4x4x1 MFMA, one element
+per workgroup of one (N = 7) or two (N = 9) waves.  It accumulates in the
+order of the VALU engine with fused multiply-adds, so its results must be
+bitwise those of the VALU engine (operator alone, CG with the fused operator, batches); the VALU
 engine itself is held to the oracle by the other operator tests, and the
 matrix-core results are also checked against the oracle here."""
 import contextlib
@@ -18,16 +18,18 @@ pytestmark = pytest.mark.gpu
 
 
 @contextlib.contextmanager
-def engine(sem, eng):
-    """Run the block with the operator engine `eng` at N = 7 (both G forms),
-    restoring the built-in choice after it."""
-    for g in (sem.PRECOMPUTED, sem.ON_THE_FLY):
-        sem.ax_engine_set(7, sem.FP32, g, eng)
+def engine(sem, eng, orders=(7, 9)):
+    """Run the block with the operator engine `eng` at the given orders
+    (both G forms), restoring the built-in choice after it."""
+    for N in orders:
+        for g in (sem.PRECOMPUTED, sem.ON_THE_FLY):
+            sem.ax_engine_set(N, sem.FP32, g, eng)
     try:
         yield
     finally:
-        for g in (sem.PRECOMPUTED, sem.ON_THE_FLY):
-            sem.ax_engine_set(7, sem.FP32, g, sem.ENGINE_DEFAULT)
+        for N in orders:
+            for g in (sem.PRECOMPUTED, sem.ON_THE_FLY):
+                sem.ax_engine_set(N, sem.FP32, g, sem.ENGINE_DEFAULT)
 
 
 def test_engine_selection_and_errors():
@@ -36,9 +38,17 @@ def test_engine_selection_and_errors():
         assert sem.ax_engine_get(7, sem.FP32, sem.ON_THE_FLY) == sem.ENGINE_MFMA
         sh = sem.ax_shape_get(7, sem.FP32, sem.ON_THE_FLY)
         assert sh["elems_per_block"] == 1 and sh["threads"] == 64
+        sh = sem.ax_shape_get(9, sem.FP32, sem.ON_THE_FLY)
+        assert sh["elems_per_block"] == 1 and sh["threads"] == 128
     with engine(sem, sem.ENGINE_VALU):
         assert sem.ax_engine_get(7, sem.FP32, sem.PRECOMPUTED) == sem.ENGINE_VALU
-    for N, prec in ((5, sem.FP32), (7, sem.FP64), (9, sem.FP32)):
+    # the built-in choice: matrix cores where they time faster than VALU
+    for N, g, eng in ((7, sem.PRECOMPUTED, sem.ENGINE_MFMA), (7, sem.ON_THE_FLY, sem.ENGINE_MFMA),
+                      (9, sem.ON_THE_FLY, sem.ENGINE_MFMA), (9, sem.PRECOMPUTED, sem.ENGINE_VALU),
+                      (5, sem.ON_THE_FLY, sem.ENGINE_VALU)):
+        assert sem.ax_engine_get(N, sem.FP32, g) == eng, (N, g)
+    assert sem.ax_engine_get(7, sem.FP64, sem.ON_THE_FLY) == sem.ENGINE_VALU
+    for N, prec in ((5, sem.FP32), (7, sem.FP64), (9, sem.FP64), (11, sem.FP32)):
         with pytest.raises(sem.SemError) as ei:
             sem.ax_engine_set(N, prec, sem.ON_THE_FLY, sem.ENGINE_MFMA)
         assert ei.value.code == -6
@@ -47,16 +57,16 @@ def test_engine_selection_and_errors():
     assert ei.value.code == -1
 
 
+@pytest.mark.parametrize("N", [7, 9])
 @pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
-def test_mfma_operator_bitwise_equals_valu(geom):
-    """sem_ax on a deformed, permuted, reoriented 5x4x3 mesh (60 elements,
-    more than one wave-sized block per CU on no axis), random and smooth
-    inputs: the two engines agree bit for bit, and both meet the FP32 bound
-    against the oracle."""
+def test_mfma_operator_bitwise_equals_valu(geom, N):
+    """sem_ax on a deformed, permuted, reoriented 5x4x3 mesh (60 elements),
+    random and smooth inputs: the two engines agree bit for bit, and both
+    meet the FP32 bound against the oracle."""
     import torch
     import paper_2108_12188_amd as sem
-    say(f"mfma operator geom={geom}")
-    mesh = box_mesh(5, 4, 3, 7, perturb=0.1, seed=71, permute=True, reorient=True)
+    say(f"mfma operator N={N} geom={geom}")
+    mesh = box_mesh(5, 4, 3, N, perturb=0.1, seed=71, permute=True, reorient=True)
     pr = oracle.Problem(mesh)
     gm = sem.Mesh.from_box(mesh)
     x, y, z = pr.coords()
@@ -101,17 +111,18 @@ def test_mfma_operator_large_sampled():
     gm.close()
 
 
+@pytest.mark.parametrize("N", [7, 9])
 @pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
 @pytest.mark.parametrize("precond", [0, 1], ids=["cg", "jacobi"])
-def test_mfma_cg_bitwise_equals_valu(geom, precond):
+def test_mfma_cg_bitwise_equals_valu(geom, precond, N):
     """FP32 CG (fused operator: p-update, lagged x step, edge copy, alpha
     partials) for 40 fixed iterations: solution and rho history bitwise
     equal between the engines, alpha to FP64 rounding; the first 10
     iterations follow the oracle to 1e-4."""
     import torch
     import paper_2108_12188_amd as sem
-    say(f"mfma cg geom={geom} precond={precond}")
-    mesh = box_mesh(6, 5, 4, 7, perturb=0.1, seed=73, permute=True, reorient=True)
+    say(f"mfma cg N={N} geom={geom} precond={precond}")
+    mesh = box_mesh(6, 5, 4, N, perturb=0.1, seed=73, permute=True, reorient=True)
     gm = sem.Mesh.from_box(mesh)
     b = random_global_rhs(mesh, seed=74)
     bd = to_dev(b, torch.float32)
@@ -151,7 +162,7 @@ def test_mfma_mixed_and_batch():
     assert torch.equal(res[sem.ENGINE_VALU][0], res[sem.ENGINE_MFMA][0])
     assert res[sem.ENGINE_MFMA][1]["converged"] == 1
     gm.close()
-    shapes = [((3, 2, 2), 7), ((4, 3, 2), 5), ((2, 3, 2), 7), ((5, 2, 3), 7)]
+    shapes = [((3, 2, 2), 7), ((4, 3, 2), 5), ((2, 3, 2), 9), ((5, 2, 3), 7), ((3, 3, 2), 9)]
     boxes = [box_mesh(*sh, N, perturb=0.1, seed=80 + q, reorient=True, permute=True)
              for q, (sh, N) in enumerate(shapes)]
     gms = [sem.Mesh.from_box(bx) for bx in boxes]
@@ -169,15 +180,16 @@ def test_mfma_mixed_and_batch():
         g.close()
 
 
+@pytest.mark.parametrize("N", [7, 9])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (7, 1, 1), (3, 5, 1)], ids=["E1", "E7", "E15"])
-def test_mfma_small_and_odd_meshes(shape):
+def test_mfma_small_and_odd_meshes(shape, N):
     """One element (a single wave-sized block), and odd element counts: the
     operator and 15 CG iterations bitwise equal to the VALU engine, the CG
     iterates against the oracle."""
     import torch
     import paper_2108_12188_amd as sem
-    say(f"mfma small mesh {shape}")
-    mesh = box_mesh(*shape, 7, perturb=0.1 if min(shape) > 1 else 0.0, seed=81, reorient=True)
+    say(f"mfma small mesh {shape} N={N}")
+    mesh = box_mesh(*shape, N, perturb=0.1 if min(shape) > 1 else 0.0, seed=81, reorient=True)
     pr = oracle.Problem(mesh)
     gm = sem.Mesh.from_box(mesh)
     u = to_dev(random_local(mesh.n_local, seed=82).astype(np.float32), torch.float32)
@@ -195,4 +207,31 @@ def test_mfma_small_and_odd_meshes(shape):
     xo, _, hist = pr.cg(b, fixed=15)
     np.testing.assert_allclose(out[sem.ENGINE_MFMA][2]["hist_rho"][:11], hist["rho"][:11],
                                rtol=1e-4)
+    gm.close()
+
+
+def test_mfma_n9_operator_large_sampled():
+    """24^3 elements N = 9 (13.8 M points, the mixed-precision workload's
+    mesh): bitwise equal to the VALU engine everywhere, and 32 sampled
+    elements against the oracle one by one."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say("mfma operator 24^3 N=9")
+    mesh = box_mesh(24, 24, 24, 9, perturb=0.1, seed=2111)
+    gm = sem.Mesh.from_box(mesh)
+    u = random_local(mesh.n_local, seed=78).astype(np.float32)
+    ud = to_dev(u, torch.float32)
+    rng = np.random.default_rng(1)
+    elems = np.sort(rng.choice(mesh.E, 32, replace=False))
+    elems[-1] = mesh.E - 1
+    ref = oracle_ax_elems(mesh, u.astype(np.float64), elems)
+    for geom in (0, 1):
+        with engine(sem, sem.ENGINE_VALU):
+            wv = gm.ax(ud, geom=geom)
+        with engine(sem, sem.ENGINE_MFMA):
+            wm = gm.ax(ud, geom=geom)
+        torch.cuda.synchronize()
+        assert torch.equal(wv, wm), geom
+        w = to_host(wm).reshape(mesh.E, -1)[elems]
+        assert rel_norm(w, ref) < 1e-5, geom
     gm.close()
