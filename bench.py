@@ -113,11 +113,43 @@ def cpu_baseline(mesh, b, budget_s: float = 15.0):
         pr.cg(b, fixed=iters, history=False)
         t = time.perf_counter() - t0
     n = mesh.n_local
-    return {"value": n * iters / t / 1e9, "unit": "GDOF·iter/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same solve on one host thread, 2 iterations (the oracle's results
+    # do not depend on its thread count)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        pr.cg(b, fixed=2, history=False)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": n * iters / t / 1e9, "unit": "GDOF·iter/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{iters} FP64 CG iterations of the oracle (plus its initial residual) on "
                       f"the same 32^3 N=7 mesh and RHS; {t:.1f} s timed, setup {setup:.1f} s "
-                      f"excluded"}
+                      f"excluded",
+            "one_thread_value": n * 2 / t1 / 1e9,
+            "one_thread_sample": f"2 iterations (plus the initial residual) on 1 thread, "
+                                 f"{t1:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def time_ax(gm, u, geom, reps=50):
@@ -147,10 +179,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--geom", choices=["pre", "otf"], default="otf",
                     help="geometric-factor form of the timed solver")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6],
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6, 7],
                     help="2: the headline FP32 CG throughput line; 1, 3, 4, 5: the other "
                          "workloads (FP64 latency, mixed vs FP64, batched, serving); "
-                         "6: Jacobi-preconditioned CG against plain CG")
+                         "6: Jacobi-preconditioned CG against plain CG; 7: FP32 CG "
+                         "throughput against the element count")
     ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
@@ -664,7 +697,60 @@ def run_config6(args):
                   "roofline": roof, "cpu_baseline": cpu})
 
 
-SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5, 6: run_config6}
+def run_config7(args):
+    """FP32 CG throughput against the element count (the analogue of the
+    paper's plots over mesh sizes, Sec. 7): near-cubic boxes of 2^7 ... 2^15
+    hexahedra (4x4x8 up to 32^3), N = 7, deformed by +-10%, a random
+    continuous RHS, 500 fixed iterations, on-the-fly and precomputed G; the
+    median of 3 solves after a warm-up."""
+    import numpy as np
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, RHS_SEED, box_mesh, random_global_rhs
+    N, iters = args.order, args.iters
+    points = []
+    for ex in range(7, 16):
+        a = ex // 3
+        b_ = (ex - a) // 2
+        dims = (1 << a, 1 << b_, 1 << (ex - a - b_))
+        mesh = box_mesh(*dims, N, perturb=0.1, seed=MESH_SEED_BASE + 2)
+        n = mesh.n_local
+        gm = sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=False)
+        b = torch.as_tensor(random_global_rhs(mesh, seed=RHS_SEED).astype(np.float32),
+                            device="cuda")
+        x = torch.zeros_like(b)
+        row = {"elements": 1 << ex, "dims": list(dims), "n_local": n}
+        for gname, geom in (("otf", sem.ON_THE_FLY), ("pre", sem.PRECOMPUTED)):
+            gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=50)
+            ts = []
+            for _ in range(3):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=iters)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = sorted(ts)[1]
+            row[f"{gname}_gdof_iter_per_s"] = n * iters / t / 1e9
+            row[f"{gname}_us_per_iter"] = t / iters * 1e6
+        log(f"bench7: E={1 << ex} {dims}: otf {row['otf_gdof_iter_per_s']:.1f} "
+            f"({row['otf_us_per_iter']:.1f} us/iter), pre {row['pre_gdof_iter_per_s']:.1f} "
+            f"GDOF*iter/s")
+        points.append(row)
+        gm.close()
+        del b, x
+    top = points[-1]
+    return _emit({"metric": "FP32 CG GDOF·iter/s against the element count, N=7, 500 iterations",
+                  "value": top["otf_gdof_iter_per_s"], "unit": "GDOF·iter/s",
+                  "higher_is_better": True, "n_gpus": 1, "points": points,
+                  "dtype": "f32", "data": "synthetic",
+                  "config": {"workload": "near-cubic boxes of 128 ... 32768 hexahedra, N=7, "
+                                         "+-10% deformed, random continuous RHS"}})
+
+
+SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5, 6: run_config6,
+          7: run_config7}
 
 
 if __name__ == "__main__":

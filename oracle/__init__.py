@@ -47,6 +47,8 @@ def lib():
         L = C.CDLL(_LIB)
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
+        L.or_set_num_threads.restype = None
         L.or_gll.argtypes = [C.c_int, _dp, _dp]
         L.or_gll.restype = C.c_int
         L.or_deriv.argtypes = [C.c_int, _dp, _dp]
@@ -75,6 +77,11 @@ def lib():
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (for timing)."""
+    lib().or_set_num_threads(int(k))
 
 
 def _f64(a):

@@ -48,6 +48,18 @@ int or_num_threads(void)
 #endif
 }
 
+/* sets the threads of the OpenMP loops that follow (k >= 1; for timing:
+   every result of this file is independent of the thread count, the dot
+   sums fixed blocks of 512 terms) */
+void or_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* O1. GLL points and weights (Sec. 3, Eq. 3): xi_0 = -1, xi_N = 1, the
  * interior points are the roots of L_N', the weights are

@@ -83,6 +83,25 @@ def test_cg_recurrences_are_consistent():
     assert abs(pr.dot(r_true, r_true) - rho[-1]) <= 1e-8 * rho[0]
 
 
+def test_cg_independent_of_thread_count():
+    # the oracle's timing on one host thread runs the same arithmetic: every
+    # parallel loop is element- or block-local and the dot sums fixed blocks
+    mesh = box_mesh(3, 2, 2, 5, perturb=0.1, seed=4)
+    pr = oracle.Problem(mesh)
+    b = random_global_rhs(mesh, seed=5)
+    k0 = oracle.num_threads()
+    x_all, _, h_all = pr.cg(b, fixed=8)
+    oracle.set_num_threads(1)
+    try:
+        assert oracle.num_threads() == 1
+        x_one, _, h_one = pr.cg(b, fixed=8)
+    finally:
+        oracle.set_num_threads(k0)
+    assert oracle.num_threads() == k0
+    assert np.array_equal(x_all, x_one)
+    assert np.array_equal(h_all["rho"], h_one["rho"])
+
+
 def test_cg_zero_rhs_returns_zero():
     mesh = box_mesh(2, 1, 1, 3)
     pr = oracle.Problem(mesh)
