@@ -53,15 +53,17 @@ def ax_bytes_per_point(N: int, geom: str, fused: bool) -> float:
     return b + (16.0 + 4.0 * (12 * N - 4) / P3 if fused else 0.0)
 
 
-def update_bytes_per_point(N: int, shared_frac: float, jacobi: bool = False) -> float:
+def update_bytes_per_point(N: int, shared_frac: float, jacobi: bool = False,
+                           table_free: bool = True) -> float:
     """Algorithmic FP32 bytes per local point of the update with gather: r
-    read and written 8, w 4, point code 1, gather table 4 S / P^3 (S surface
-    nodes per element), one gathered value per shared point; with the
-    Jacobi preconditioner also M^-1 read and z written (+8)."""
-    P = N + 1
-    P3 = P ** 3
-    S = P3 - max(P - 2, 0) ** 3
-    return 8.0 + 4.0 + 1.0 + 4.0 * S / P3 + 4.0 * shared_frac + (8.0 if jacobi else 0.0)
+    read and written 8, w 4, one gathered value per shared point, and the
+    gather's description: with the table-free form the element's 8-byte
+    face and edge-slot records, 8 (6 + 12N - 4) / P^3; with the per-point
+    table a 4-byte entry and a 1-byte code per point.  With the Jacobi
+    preconditioner also M^-1 read and z written (+8)."""
+    P3 = (N + 1) ** 3
+    desc = 8.0 * (6 + 12 * N - 4) / P3 if table_free else 5.0
+    return 8.0 + 4.0 + 4.0 * shared_frac + desc + (8.0 if jacobi else 0.0)
 
 
 def ax_flops_per_point(N: int, geom: str) -> float:
@@ -627,12 +629,16 @@ def run_config6(args):
     info = gm.info()
     shared_frac = info["n_shared"] / n
     upd_ms = cost["pcg"]["kernel_ms"]["update"]
-    upd_gbs = update_bytes_per_point(N, shared_frac, jacobi=True) * n / (upd_ms * 1e-3) / 1e9
+    table_free = bool(info["gs_table_free"])
+    upd_gbs = update_bytes_per_point(N, shared_frac, jacobi=True, table_free=table_free) * n \
+        / (upd_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": upd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": upd_gbs / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "update_gather_kernel<float, PC> (gather + mask + r update + z = M^-1 r "
-                      "+ <r,z,c>, <r,r,c> partials) and the one-block rho finalize, timed "
-                      "together between HIP events", "avg_ms": upd_ms}
+            "kernel": "%s<float, PC> (gather + mask + r update + z = M^-1 r + <r,z,c>, "
+                      "<r,r,c> partials) and the one-block rho finalize, timed together "
+                      "between HIP events" % ("update_struct_kernel" if table_free
+                                              else "update_gather_kernel"),
+            "avg_ms": upd_ms}
     out["iteration_cost"] = cost
     # (c) oracle PCG on a bounded sample of the same mesh
     cpu = None

@@ -59,6 +59,10 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  * The on-the-fly form needs none of them (it reads the vertices). */
 #define SEM_MESH_G_FP32 0x1u   /* G as float [E][6][P3]  (24 B per point)  */
 #define SEM_MESH_G_FP64 0x2u   /* G as double [E][6][P3] (48 B per point)  */
+/* Keep the per-point table form of the gather-scatter inside CG even where
+ * the table-free form applies (odd N, conforming meshes); the two give
+ * bitwise identical results.  For comparison and testing. */
+#define SEM_MESH_GATHER_TABLE 0x4u
 
 /*
  * Build a mesh on the current HIP device (Sec. 3: decomposition into E
@@ -73,7 +77,8 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  *              gather-scatter.  Every id in [0, max id] need not be used.
  *   dirichlet  HOST uint8 [E][P3]: 1 on the Dirichlet boundary; must be equal
  *              on all copies of a global point.  May be NULL (no boundary).
- *   flags      bit set of SEM_MESH_G_FP32 / SEM_MESH_G_FP64.
+ *   flags      bit set of SEM_MESH_G_FP32 / SEM_MESH_G_FP64 /
+ *              SEM_MESH_GATHER_TABLE.
  *   out        receives the handle.
  * Copies what it needs; the host arrays may be freed on return.  Blocks until
  * the device-side setup (geometric factors, Jacobian check) has finished.
@@ -100,6 +105,10 @@ typedef struct {
     int32_t gs_in_update;  /* 1: every shared point lies on an element face, and sem_cg_solve
                               gathers the shared sums inside its vector update instead of a
                               separate gather-scatter pass (same results, bitwise) */
+    int32_t gs_table_free; /* 1: that gather derives each point's copies from its position in
+                              the element and per-element face and edge records (odd N,
+                              conforming mesh, no SEM_MESH_GATHER_TABLE) instead of a
+                              per-point table (same results, bitwise) */
 } sem_mesh_info_t;
 
 sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);

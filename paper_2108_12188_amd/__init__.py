@@ -21,7 +21,7 @@ __all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_se
 FP64, FP32, MIXED = 0, 1, 2
 PRECOMPUTED, ON_THE_FLY = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
-G_FP32, G_FP64 = 0x1, 0x2
+G_FP32, G_FP64, GATHER_TABLE = 0x1, 0x2, 0x4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsem.so")
@@ -55,7 +55,7 @@ class MeshInfo(C.Structure):
     _fields_ = [("n_elem", C.c_int64), ("order_N", C.c_int32), ("n_local", C.c_int64),
                 ("n_glob", C.c_int64), ("n_shared", C.c_int64), ("n_groups", C.c_int64),
                 ("n_dirichlet", C.c_int64), ("device_bytes", C.c_size_t),
-                ("gs_in_update", C.c_int32)]
+                ("gs_in_update", C.c_int32), ("gs_table_free", C.c_int32)]
 
 
 _lib = None
@@ -162,7 +162,7 @@ class Mesh:
     """A mesh on the current HIP device (owns all device-side mesh data)."""
 
     def __init__(self, vert, glob_id, dirichlet, N: int, g_fp32: bool = True,
-                 g_fp64: bool = False, stream=None):
+                 g_fp64: bool = False, stream=None, gather_table: bool = False):
         _torch()
         vert = np.ascontiguousarray(vert, dtype=np.float64)
         gid = np.ascontiguousarray(glob_id, dtype=np.int64)
@@ -170,7 +170,8 @@ class Mesh:
         E = vert.shape[0]
         if vert.shape != (E, 8, 3) or gid.size != E * (N + 1) ** 3:
             raise ValueError("vert must be [E][8][3] and glob_id [E][(N+1)^3]")
-        flags = (G_FP32 if g_fp32 else 0) | (G_FP64 if g_fp64 else 0)
+        flags = ((G_FP32 if g_fp32 else 0) | (G_FP64 if g_fp64 else 0) |
+                 (GATHER_TABLE if gather_table else 0))
         h = C.c_void_p()
         _check(lib().sem_mesh_create(E, N, vert.ctypes.data, gid.ctypes.data,
                                      None if dr is None else dr.ctypes.data, flags,

@@ -73,10 +73,13 @@ Workspace *ws_create(const Mesh &m, bool fp64) {
         ws->x = ws_alloc<char>(*ws, nv);
         ws->r = ws_alloc<char>(*ws, nv);
         ws->p = ws_alloc<char>(*ws, nv);
-        ws->w = ws_alloc<char>(*ws, nv);
+        // table-free gather: the edge-group sums sit right after w
+        ws->w = ws_alloc<char>(*ws, nv + (m.gs_struct ? (size_t)m.n_egroups * tsz : 0));
         ws->b = ws_alloc<char>(*ws, nv);
-        if (m.gs_in_update) ws->gsum = ws_alloc<char>(*ws, (size_t)m.n_groups_multi * tsz);
-        if (m.gsum_wedge) ws->wedge = ws_alloc<char>(*ws, (size_t)m.E * edge_slots(m.N) * tsz);
+        if (m.gs_in_update)
+            ws->gsum = ws_alloc<char>(*ws, (size_t)m.n_groups_multi * tsz);
+        if (m.gsum_wedge || m.gs_struct)
+            ws->wedge = ws_alloc<char>(*ws, (size_t)m.E * edge_slots(m.N) * tsz);
         // the smallest shape (1 element per block) bounds the Ax partial count
         ws->cap_ax = m.E;
         ws->cap_vec = vec_blocks(m.n);
@@ -183,16 +186,19 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, bool pc, hipStrea
     a.w = w;
     a.st = ws.st;
     a.partial = ws.part_ax;
-    a.wedge = m.gsum_wedge ? wedge : nullptr;
+    a.wedge = (m.gsum_wedge || m.gs_struct) ? wedge : nullptr;
     a.x = x;
     if (ev) SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     if (ev) SEM_HIP(hipEventRecord(ev[1], s));
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
-    if (m.gs_in_update) launch_group_sums_cg<T>(m, w, wedge, gsum, ws.st, ws.part_ax, (int)nax, s);
+    if (m.gs_struct) launch_edge_sums_cg<T>(m, wedge, w + m.n, ws.st, ws.part_ax, (int)nax, s);
+    else if (m.gs_in_update)
+        launch_group_sums_cg<T>(m, w, wedge, gsum, ws.st, ws.part_ax, (int)nax, s);
     else launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     if (ev) SEM_HIP(hipEventRecord(ev[2], s));
-    if (m.gs_in_update) launch_update_gather<T>(m, r, w, gsum, ws.st, ws.part_vec, s, pa);
+    if (m.gs_struct) launch_update_struct<T>(m, r, w, ws.st, ws.part_vec, s, pa);
+    else if (m.gs_in_update) launch_update_gather<T>(m, r, w, gsum, ws.st, ws.part_vec, s, pa);
     else launch_update<T>(m, r, w, ws.st, ws.part_vec, s, pa);
     if (ev) SEM_HIP(hipEventRecord(ev[3], s));
 }

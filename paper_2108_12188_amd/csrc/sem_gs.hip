@@ -45,21 +45,22 @@ gs_kernel(const GsClasses cls, int64_t lb0, int64_t nb_logical, const int32_t *_
     if (b < nb_logical) gs_logical_block<T>(cls, lb0 + b, idx, w);
 }
 
-// Group sums of the classes with M > 2: logical blocks lb0 .. lb0 +
-// nb_logical - 1 of the gather-scatter numbering; the last block forms
+// Group sums of the classes with M >= mmin: logical blocks lb0 .. lb0 +
+// nb_logical - 1 of the class list's block numbering; the last block forms
 // alpha from the operator's partials.
 template <typename T>
 __global__ void __launch_bounds__(kGsThreads)
 group_sums_kernel(const GsClasses cls, int64_t lb0, int64_t nb_logical,
                   const int32_t *__restrict__ idx, int64_t io0, const T *__restrict__ src,
-                  T *__restrict__ out, CgState *st, const double *part_ax, int64_t n_ax) {
+                  T *__restrict__ out, CgState *st, const double *part_ax, int64_t n_ax,
+                  int mmin) {
     if (st->stop) return;
     if (blockIdx.x == gridDim.x - 1) {
         vecb::finalize_alpha_body(st, part_ax, n_ax);
         return;
     }
     const int64_t b = logical_block(blockIdx.x, gridDim.x - 1);
-    if (b < nb_logical) gs_sums_logical_block<T>(cls, lb0 + b, idx, io0, src, out);
+    if (b < nb_logical) gs_sums_logical_block<T>(cls, lb0 + b, idx, io0, src, out, mmin);
 }
 
 template <typename T>
@@ -120,8 +121,22 @@ void launch_group_sums_cg(const Mesh &m, const T *w, const T *wedge, T *gsum, Cg
         hipLaunchKernelGGL((group_sums_kernel<T>), dim3(gs_phys_blocks(nlb) + 1),
                            dim3(kGsThreads), 0, s, m.gs, m.gs_blk_multi, nlb,
                            compact ? m.wedge_idx : m.gs_idx, compact ? m.wedge_io0 : (int64_t)0,
-                           compact ? wedge : w, gsum, st, ax_partial, (int64_t)n_ax_partial);
+                           compact ? wedge : w, gsum, st, ax_partial, (int64_t)n_ax_partial, 3);
         check_hip(hipGetLastError(), "group sums kernel launch");
+    } else {
+        launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
+    }
+}
+
+template <typename T>
+void launch_edge_sums_cg(const Mesh &m, const T *wedge, T *gsum, CgState *st,
+                         const double *ax_partial, int n_ax_partial, hipStream_t s) {
+    const int64_t nlb = gs_total_blocks(m.ecls);
+    if (nlb > 0) {
+        hipLaunchKernelGGL((group_sums_kernel<T>), dim3(gs_phys_blocks(nlb) + 1),
+                           dim3(kGsThreads), 0, s, m.ecls, (int64_t)0, nlb, m.ewedge_idx,
+                           (int64_t)0, wedge, gsum, st, ax_partial, (int64_t)n_ax_partial, 2);
+        check_hip(hipGetLastError(), "edge sums kernel launch");
     } else {
         launch_finalize_alpha(st, ax_partial, n_ax_partial, s);
     }
@@ -135,6 +150,10 @@ template void launch_gs_cg<float>(const Mesh &, float *, CgState *, const double
                                   hipStream_t);
 template void launch_gs_cg<double>(const Mesh &, double *, CgState *, const double *, int,
                                    hipStream_t);
+template void launch_edge_sums_cg<float>(const Mesh &, const float *, float *, CgState *,
+                                         const double *, int, hipStream_t);
+template void launch_edge_sums_cg<double>(const Mesh &, const double *, double *, CgState *,
+                                          const double *, int, hipStream_t);
 template void launch_group_sums_cg<float>(const Mesh &, const float *, const float *, float *,
                                           CgState *, const double *, int, hipStream_t);
 template void launch_group_sums_cg<double>(const Mesh &, const double *, const double *,

@@ -126,26 +126,29 @@ __device__ __forceinline__ void gs_sums_any(const int32_t *__restrict__ ib, int 
     }
 }
 
-// One logical block lb of a mesh's group sums over the classes with M > 2.
-// The copies of class c's groups are read from w at the indices
+// One logical block lb of a mesh's group sums over the classes with
+// M >= mmin (3: the groups of more than two copies of the full class list;
+// 2: every class of the edge-node list of the table-free gather).  The
+// copies of class c's groups are read from w at the indices
 // idx[cls.io[c] - io0 ...] (gs_idx and the local w, or the compact edge
 // array and its positions); the sums go to out + (groups of the classes
-// with M > 2 before c).
+// with M >= mmin before c).
 template <typename T>
 __device__ __forceinline__ void gs_sums_logical_block(const GsClasses &cls, int64_t lb,
                                                       const int32_t *__restrict__ idx,
                                                       int64_t io0, const T *__restrict__ w,
-                                                      T *__restrict__ out) {
+                                                      T *__restrict__ out, int mmin = 3) {
     int c = 0;
     while (c + 1 < cls.ncls && lb >= cls.blk0[c + 1]) ++c;
     int64_t goff = 0;
     for (int q = 0; q < c; ++q)
-        if (cls.M[q] > 2) goff += cls.ng[q];
+        if (cls.M[q] >= mmin) goff += cls.ng[q];
     const int M = cls.M[c];
     const int64_t g0 = (lb - cls.blk0[c]) * gs_per_block(M) + threadIdx.x;
     const int32_t *ib = idx + (cls.io[c] - io0);
     const int64_t ng = cls.ng[c];
     switch (M) {
+        case 2: gs_sums_fixed<T, 2>(ib, g0, ng, w, out + goff); break;
         case 4: gs_sums_fixed<T, 4>(ib, g0, ng, w, out + goff); break;
         case 8: gs_sums_fixed<T, 8>(ib, g0, ng, w, out + goff); break;
         default: gs_sums_any<T>(ib, M, g0, ng, w, out + goff); break;

@@ -106,6 +106,27 @@ struct GsClasses {
 void gs_classes_finish(GsClasses &c);
 int64_t gs_total_blocks(const GsClasses &c);   // logical blocks of a whole gather-scatter
 
+// Table-free gather inside the CG update (see Mesh::gs_struct): one record
+// per face and per edge slot of an element, [E][6 + edge_slots(N)], faces
+// first.  Face f = 2 d + (the face lies at coordinate N along d, its normal
+// direction): the copies of its face-interior points, with face coordinates
+// (a, b) (the two coordinates other than d, in i, j, k order), are
+// lo + sa a + sb b, where hi = code | sa << 8 | sb << 20 with sa, sb 12-bit
+// two's-complement strides (0, +-1, +-P or +-P^2; every partial sum fits
+// in 32 bits); a face without a partner (or a Dirichlet face) has
+// sa = sb = 0 and lo inside its own element.  Edge slot s (record 6 + s): lo = the rank of its group among the
+// edge groups (0 when unshared or Dirichlet), hi = code.  code: the points'
+// multiplicity | Dirichlet byte.
+struct alignas(8) ElemRec {
+    int32_t lo, hi;
+};
+// Per local position of the element (P^3 entries): bits 0-1 kind (0
+// interior, 1 face interior, 2 edge or corner node), bits 2-6 and 7-11 the
+// face coordinates a, b, bits 12-20 the record (face f, or 6 + edge slot).
+__host__ __device__ inline uint32_t pos_entry(int kind, int a, int b, int rec) {
+    return (uint32_t)kind | ((uint32_t)a << 2) | ((uint32_t)b << 7) | ((uint32_t)rec << 12);
+}
+
 struct Mesh {
     int device = 0;
     int64_t E = 0;
@@ -143,6 +164,22 @@ struct Mesh {
     bool gsum_wedge = false;
     int64_t wedge_io0 = 0;
     int32_t *wedge_idx = nullptr;
+    // Table-free form of the same gather (odd N, conforming meshes, unless
+    // SEM_MESH_GATHER_TABLE): the update derives every point's copies from
+    // its position in the element (pos_tab) and the element's face and edge
+    // records (ElemRec) instead of loading gsrc and mcode.  The sums of the
+    // n_egroups edge and corner groups of two or more copies (ecls /
+    // ewedge_idx: positions in the compact edge array) follow w in class
+    // order.  Division of a local index by P^3: (l * p3_magic) >> p3_shift
+    // (checked on the host for every l < n).
+    bool gs_struct = false;
+    ElemRec *erec = nullptr;       // [E][6 + edge_slots(N)]
+    uint32_t *pos_tab = nullptr;   // [P3]
+    GsClasses ecls{};
+    int64_t n_egroups = 0;
+    int32_t *ewedge_idx = nullptr;
+    uint32_t p3_magic = 0;
+    int p3_shift = 0;
     // Jacobi preconditioner (built on first use): 1 / diag(A) on the free
     // points, 0 on the Dirichlet points, local form
     double *minv64 = nullptr;
@@ -187,6 +224,14 @@ struct HostTables {
     int64_t wedge_io0 = 0;          // gs_idx offset of the first such group
     std::vector<int32_t> wedge_idx; // copies' positions in the compact edge array
     std::vector<int32_t> gsrc;      // [n] (only when gs_in_update), see Mesh::gsrc
+    bool gs_struct = false;         // the table-free form applies, see Mesh::gs_struct
+    std::vector<ElemRec> erec;
+    std::vector<uint32_t> pos_tab;
+    GsClasses ecls{};
+    int64_t n_egroups = 0;
+    std::vector<int32_t> ewedge_idx;
+    uint32_t p3_magic = 0;
+    int p3_shift = 0;
 };
 // Validates glob_id / dirichlet (fail() on error) and fills t.
 void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, HostTables &t);
@@ -284,6 +329,13 @@ void launch_gs_cg(const Mesh &m, T *w, CgState *st, const double *ax_partial, in
 template <typename T>
 void launch_group_sums_cg(const Mesh &m, const T *w, const T *wedge, T *gsum, CgState *st,
                           const double *ax_partial, int n_ax_partial, hipStream_t s);
+// The same for the table-free gather (needs m.gs_struct): gsum[k] = sum of
+// the copies of the k-th edge or corner group of two or more copies
+// (ascending local index, read from wedge, the operator's compact edge
+// array), then alpha.
+template <typename T>
+void launch_edge_sums_cg(const Mesh &m, const T *wedge, T *gsum, CgState *st,
+                         const double *ax_partial, int n_ax_partial, hipStream_t s);
 int gs_cg_blocks(const Mesh &m);
 int64_t gs_logical_blocks(const Mesh &m);
 
@@ -305,6 +357,12 @@ void launch_x_flush(const Mesh &m, T *x, const T *p, const CgState *st, hipStrea
 template <typename T>
 void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgState *st,
                           double *partial, hipStream_t s, PcArgs<T> pc = PcArgs<T>{});
+// The same with the table-free gather (needs m.gs_struct): wg holds w
+// (n values) followed by the edge-group sums of launch_edge_sums_cg;
+// bitwise the results of launch_update_gather.
+template <typename T>
+void launch_update_struct(const Mesh &m, T *r, const T *wg, CgState *st, double *partial,
+                          hipStream_t s, PcArgs<T> pc = PcArgs<T>{});
 // r = b - w (w may be null: r = b); p = 0; rho_0 = <r, r, c>; initial state.
 // With pc.minv: z = minv r, rho = <r, z, c>, and the threshold and the
 // reported residual use <r, r, c>.

@@ -34,7 +34,7 @@ void free_mesh_arrays(Mesh *m) {
     void *ptrs[] = {m->vert64,     m->vert32,  m->G32,     m->G64,       m->B64,
                     m->mcode,      m->gs_idx,  m->dir_idx, m->gsrc,
                     m->wedge_idx,  m->basis_blob, m->scratch, m->state,   m->minv64,
-                    m->minv32};
+                    m->minv32,     m->erec,    m->pos_tab, m->ewedge_idx};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -66,6 +66,10 @@ size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec) {
     b += n * 4 * 2;                                // group index list and Dirichlet list (bounds)
     b += n * 4;                                        // table of the gather in the update
     b += n / 3 * 4;                                    // edge-array positions (bound)
+    {   // table-free gather: element records and edge-group positions (bounds)
+        const size_t ms = (size_t)edge_slots(N);
+        b += (size_t)E * (6 + ms) * 8 + ((size_t)E * ms + 8 * kMaxGsClasses) * 4 + P3 * 4;
+    }
     if (flags & SEM_MESH_G_FP32) b += n * 24;
     if (flags & SEM_MESH_G_FP64) b += n * 48;
     b += ((size_t)vec_blocks((int64_t)n) + 16) * 8 + sizeof(CgState) + 4096;
@@ -86,7 +90,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     if (N < 1 || N > kMaxOrder)
         fail(SEM_EUNSUPPORTED, "order N=" + std::to_string(N) + " is not built (1..11)");
     if (!vert || !gid) fail(SEM_EINVAL, "vert_xyz and glob_id must not be NULL");
-    if (flags & ~(uint32_t)(SEM_MESH_G_FP32 | SEM_MESH_G_FP64))
+    if (flags & ~(uint32_t)(SEM_MESH_G_FP32 | SEM_MESH_G_FP64 | SEM_MESH_GATHER_TABLE))
         fail(SEM_EINVAL, "unknown mesh flags");
     const int P = N + 1, P3 = P * P * P;
     const int64_t n = E * P3;
@@ -113,6 +117,13 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     m->gs_blk_multi = t.gs_blk_multi;
     m->gsum_wedge = t.gsum_wedge;
     m->wedge_io0 = t.wedge_io0;
+    m->gs_struct = t.gs_struct && !(flags & SEM_MESH_GATHER_TABLE);
+    if (m->gs_struct) {
+        m->ecls = t.ecls;
+        m->n_egroups = t.n_egroups;
+        m->p3_magic = t.p3_magic;
+        m->p3_shift = t.p3_shift;
+    }
 
     // ---- basis ---------------------------------------------------------------
     gll_points(N, m->h_xi, m->h_w);
@@ -130,6 +141,11 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         m->dir_idx = dev_alloc<int32_t>(*m, t.dir_idx.size());
         if (t.gs_in_update) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
         if (t.gsum_wedge) m->wedge_idx = dev_alloc<int32_t>(*m, t.wedge_idx.size());
+        if (m->gs_struct) {
+            m->erec = dev_alloc<ElemRec>(*m, t.erec.size());
+            m->pos_tab = dev_alloc<uint32_t>(*m, t.pos_tab.size());
+            m->ewedge_idx = dev_alloc<int32_t>(*m, t.ewedge_idx.size());
+        }
         // basis blob: FP64 D, Dt, xi, w then FP32 D, Dt, xi, w
         const size_t PP = (size_t)P * P;
         const size_t nd = 2 * PP + 2 * P;
@@ -166,6 +182,11 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
             upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
         }
         if (t.gsum_wedge) upload(m->wedge_idx, t.wedge_idx.data(), t.wedge_idx.size(), s);
+        if (m->gs_struct) {
+            upload(m->erec, t.erec.data(), t.erec.size(), s);
+            upload(m->pos_tab, t.pos_tab.data(), t.pos_tab.size(), s);
+            upload(m->ewedge_idx, t.ewedge_idx.data(), t.ewedge_idx.size(), s);
+        }
         upload(b64, h64.data(), nd, s);
         upload(b32, h32.data(), nd, s);
         SEM_HIP(hipMemsetAsync(m->state, 0, sizeof(CgState), s));

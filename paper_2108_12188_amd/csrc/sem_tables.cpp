@@ -7,6 +7,7 @@
 // indices ascending, and groups inside a bucket in ascending order of their
 // first local index.  No device call is made in this file.
 #include <algorithm>
+#include <climits>
 #include <numeric>
 
 #include "sem_gs_body.h"
@@ -33,6 +34,164 @@ int64_t gs_total_blocks(const GsClasses &c) {
     return q >= 0 ? c.blk0[q] + (c.ng[q] + gsb::gs_per_block(c.M[q]) - 1) / gsb::gs_per_block(c.M[q])
                   : 0;
 }
+
+namespace {
+
+// Local position of face point (a, b) of face f = 2 d + s (d: normal
+// direction, s: coordinate N on that side) in an element of order N.
+int face_position(int N, int f, int a, int b) {
+    const int P = N + 1, d = f >> 1, c = (f & 1) ? N : 0;
+    const int i = d == 0 ? c : a;
+    const int j = d == 0 ? a : (d == 1 ? c : b);
+    const int k = d == 2 ? c : b;
+    return i + P * (j + P * k);
+}
+
+// Tables of the table-free gather inside the CG update (Mesh::gs_struct).
+// Applies to odd N (P^3 a multiple of 4: a pack of 4 points never straddles
+// two elements) on meshes where every face-interior point is shared with
+// exactly one face point of one neighbour by an affine map of the face
+// coordinates, interior points are unshared and free, and every group of
+// two or more copies at an edge or corner node consists of edge or corner
+// nodes only.  Each condition is checked point by point; any failure keeps
+// the per-point table form.
+bool build_struct_tables(int64_t E, int N, const std::vector<uint8_t> &mcode,
+                         const std::vector<int32_t> &plink, const std::vector<int32_t> &cnt,
+                         const std::vector<int64_t> &start, const std::vector<int32_t> &byid,
+                         HostTables &t) {
+    const int P = N + 1, P3 = P * P * P, MS = edge_slots(N), NR = 6 + MS;
+    const int64_t n = E * P3;
+    if (N % 2 == 0 || P > 32 || NR > 511) return false;
+    // position table
+    t.pos_tab.assign(P3, 0);
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j)
+            for (int i = 0; i < P; ++i) {
+                const int loc = i + P * (j + P * k);
+                const bool ei = i == 0 || i == N, ej = j == 0 || j == N, ek = k == 0 || k == N;
+                const int on = (int)ei + (int)ej + (int)ek;
+                if (on == 0) {
+                    t.pos_tab[loc] = pos_entry(0, 0, 0, 0);
+                } else if (on == 1) {
+                    const int d = ei ? 0 : (ej ? 1 : 2);
+                    const int f = 2 * d + ((d == 0 ? i : (d == 1 ? j : k)) == N);
+                    const int a = d == 0 ? j : i, b = d == 2 ? j : k;
+                    t.pos_tab[loc] = pos_entry(1, a, b, f);
+                } else {
+                    const int es = edge_slot(N, i, j, k);
+                    if (es < 0 || es >= MS) return false;
+                    t.pos_tab[loc] = pos_entry(2, 0, 0, 6 + es);
+                }
+            }
+    // division by P^3 as a multiply-shift, exact for every l < 2^31
+    int lg = 0;
+    while ((1 << lg) < P3) ++lg;
+    t.p3_shift = 31 + lg;
+    t.p3_magic = (uint32_t)(((uint64_t)1 << t.p3_shift) / (uint64_t)P3 + 1);
+    // interior points: unshared and free
+    for (int64_t l = 0; l < n; ++l) {
+        const uint32_t pe = t.pos_tab[l % P3];
+        if ((pe & 3) == 0 && mcode[l] != 1) return false;
+    }
+    const auto fits32 = [](int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; };
+    t.erec.assign((size_t)E * NR, ElemRec{0, 0});
+    // faces
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            ElemRec rc{(int32_t)(e * P3), 0};
+            if (N >= 3) {
+                const int64_t l11 = e * P3 + face_position(N, f, 1, 1);
+                const uint8_t code = mcode[l11];
+                const int m = code & kMultMask;
+                if (m > 2) return false;
+                int64_t sa = 0, sb = 0;
+                if (m == 2 && !(code & kDirichletBit)) {
+                    const int64_t q11 = plink[l11];
+                    sa = plink[e * P3 + face_position(N, f, 2, 1)] - q11;
+                    sb = plink[e * P3 + face_position(N, f, 1, 2)] - q11;
+                    rc.lo = (int32_t)(q11 - sa - sb);
+                }
+                if (sa < -2048 || sa > 2047 || sb < -2048 || sb > 2047) return false;
+                rc.hi = (int32_t)((uint32_t)code | ((uint32_t)(sa & 0xFFF) << 8) |
+                                  ((uint32_t)(sb & 0xFFF) << 20));
+                for (int b = 1; b < N; ++b)
+                    for (int a = 1; a < N; ++a) {
+                        const int64_t l = e * P3 + face_position(N, f, a, b);
+                        if (mcode[l] != code) return false;
+                        // the device forms lo + sa a, then + sb b, in 32 bits
+                        if (!fits32((int64_t)rc.lo + sa * a)) return false;
+                        const int64_t q = (int64_t)rc.lo + sa * a + sb * b;
+                        if (q < 0 || q >= n) return false;
+                        if (m == 2 && !(code & kDirichletBit) && q != plink[l]) return false;
+                    }
+            }
+            t.erec[(size_t)e * NR + f] = rc;
+        }
+    // edge and corner nodes: codes, and their groups of two or more copies
+    for (int64_t l = 0; l < n; ++l) {
+        const uint32_t pe = t.pos_tab[l % P3];
+        if ((pe & 3) == 2) t.erec[(size_t)(l / P3) * NR + (pe >> 12)] = ElemRec{0, mcode[l]};
+    }
+    const int64_t G = (int64_t)cnt.size();
+    auto edge_pos = [&](int64_t l) -> int64_t {
+        const uint32_t pe = t.pos_tab[l % P3];
+        return (pe & 3) == 2 ? (l / P3) * MS + ((pe >> 12) - 6) : -1;
+    };
+    GsClasses ec{};
+    std::vector<int32_t> &ew = t.ewedge_idx;
+    ew.clear();
+    t.n_egroups = 0;
+    int sizes_seen[256] = {0};
+    for (int64_t g = 0; g < G; ++g) {
+        if (cnt[g] < 2) continue;
+        const int32_t l0 = byid[start[g]];
+        if (mcode[l0] & kDirichletBit) continue;      // masked: the update never reads the sum
+        const bool first_edge = edge_pos(l0) >= 0;
+        for (int64_t o = start[g]; o < start[g + 1]; ++o)
+            if ((edge_pos(byid[o]) >= 0) != first_edge) return false;
+        if (first_edge) sizes_seen[cnt[g]] = 1;
+    }
+    for (int msz = 2; msz <= kMaxMultiplicity; ++msz) {
+        if (!sizes_seen[msz]) continue;
+        if (ec.ncls == kMaxGsClasses) return false;
+        const int c = ec.ncls++;
+        ec.M[c] = msz;
+        while (ew.size() % 8) ew.push_back(0);
+        ec.io[c] = (int64_t)ew.size();
+        int64_t ng = 0;
+        // compact ids are numbered by first appearance: ascending first local
+        // index; a group's rank is its position in class order
+        for (int64_t g = 0; g < G; ++g) {
+            if (cnt[g] != msz) continue;
+            const int32_t l0 = byid[start[g]];
+            if ((mcode[l0] & kDirichletBit) || edge_pos(l0) < 0) continue;
+            const int64_t rank = t.n_egroups + ng;
+            if (rank >= (int64_t(1) << 31) - n) return false;
+            for (int64_t o = start[g]; o < start[g + 1]; ++o) {
+                const int32_t lm = byid[o];
+                ew.push_back((int32_t)edge_pos(lm));
+                t.erec[(size_t)(lm / P3) * NR + (t.pos_tab[lm % P3] >> 12)].lo = (int32_t)rank;
+            }
+            ++ng;
+        }
+        ec.ng[c] = ng;
+        t.n_egroups += ng;
+    }
+    while (ew.size() % 8) ew.push_back(0);
+    gs_classes_finish(ec);
+    t.ecls = ec;
+    // every local index: the division, and the decoded code against mcode
+    for (int64_t l = 0; l < n; ++l) {
+        const int64_t e = (int64_t)(((uint64_t)l * t.p3_magic) >> t.p3_shift);
+        if (e != l / P3) return false;
+        const uint32_t pe = t.pos_tab[l - e * P3];
+        const int code = (pe & 3) == 0 ? 1 : (t.erec[(size_t)e * NR + (pe >> 12)].hi & 255);
+        if (code != mcode[l]) return false;
+    }
+    return true;
+}
+
+}  // namespace
 
 void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, HostTables &t) {
     const int P = N + 1, P3 = P * P * P;
@@ -192,7 +351,6 @@ void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, Host
         for (int64_t l = 0; l < n; ++l)
             t.gsrc[l] = (mcode[l] & kMultMask) > 1 ? plink[l] : (int32_t)l;
     }
-    std::vector<int32_t>().swap(plink);
     t.gs_in_update = ok;
 
     // compact edge-array positions of the copies of the groups with m > 2
@@ -226,6 +384,7 @@ void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, Host
         if (!all_edge) t.wedge_idx.clear();
     }
 
+    t.gs_struct = ok && build_struct_tables(E, N, mcode, plink, cnt, start, byid, t);
 }
 
 }  // namespace sem

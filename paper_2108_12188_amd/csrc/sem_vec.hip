@@ -39,6 +39,13 @@ update_gather_kernel(int64_t n, T *__restrict__ r, const T *__restrict__ w,
     update_gather_body<T, PC>(n, r, w, gsum, mcode, gm, st, partial, blockIdx.x, gridDim.x, pc);
 }
 
+template <typename T, bool PC>
+__global__ void __launch_bounds__(kVecThreads)
+update_struct_kernel(int64_t n, T *__restrict__ r, const T *__restrict__ wg,
+                     const StructMap sm, CgState *st, double *partial, PcArgs<T> pc) {
+    update_struct_body<T, PC>(n, r, wg, sm, st, partial, blockIdx.x, gridDim.x, pc);
+}
+
 __global__ void __launch_bounds__(kFinalizeThreads)
 finalize_rho_kernel(CgState *st, const double *partial, int cnt, const double *partial2) {
     finalize_rho_body(st, partial, cnt, partial2);
@@ -250,6 +257,24 @@ void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgStat
 }
 
 template <typename T>
+void launch_update_struct(const Mesh &m, T *r, const T *wg, CgState *st, double *partial,
+                          hipStream_t s, PcArgs<T> pc) {
+    if (!m.gs_struct) fail(SEM_EUNSUPPORTED, "mesh has no table-free gather");
+    if (m.P3 > kMaxPosTab || m.n % 4) fail(SEM_EUNSUPPORTED, "table-free gather: bad order");
+    const StructMap sm{m.erec, m.pos_tab, m.P3, 6 + edge_slots(m.N), m.p3_magic, m.p3_shift};
+    const int nb = vec_blocks(m.n);
+    if (pc.minv)
+        hipLaunchKernelGGL((update_struct_kernel<T, true>), dim3(nb), dim3(kVecThreads), 0, s,
+                           m.n, r, wg, sm, st, partial, pc);
+    else
+        hipLaunchKernelGGL((update_struct_kernel<T, false>), dim3(nb), dim3(kVecThreads), 0, s,
+                           m.n, r, wg, sm, st, partial, pc);
+    hipLaunchKernelGGL(finalize_rho_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, st,
+                       (const double *)partial, nb, (const double *)pc.partial2);
+    check_hip(hipGetLastError(), "update kernel launch");
+}
+
+template <typename T>
 void launch_cg_init(const Mesh &m, const T *b, const T *w, T *r, T *p, CgState *st,
                     double *partial, hipStream_t s, PcArgs<T> pc) {
     const int nb = vec_blocks(m.n);
@@ -320,6 +345,10 @@ template void launch_update_gather<float>(const Mesh &, float *, const float *, 
 template void launch_update_gather<double>(const Mesh &, double *, const double *,
                                            const double *, CgState *, double *, hipStream_t,
                                            PcArgs<double>);
+template void launch_update_struct<float>(const Mesh &, float *, const float *, CgState *,
+                                          double *, hipStream_t, PcArgs<float>);
+template void launch_update_struct<double>(const Mesh &, double *, const double *, CgState *,
+                                           double *, hipStream_t, PcArgs<double>);
 template void launch_cg_init<float>(const Mesh &, const float *, const float *, float *, float *,
                                     CgState *, double *, hipStream_t, PcArgs<float>);
 template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,

@@ -245,6 +245,169 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
     }
 }
 
+// Table-free form of the same gather (Mesh::gs_struct): a point's copies
+// follow from its position in the element and the element's records.
+struct StructMap {
+    const ElemRec *rec;         // [E][nrec]
+    const uint32_t *pos_tab;    // [p3] (pos_entry)
+    int p3, nrec;               // P^3, 6 + edge_slots(N)
+    uint32_t magic;             // element of local index l: (l * magic) >> shift
+    int shift;
+};
+constexpr int kMaxPosTab = kMaxP * kMaxP * kMaxP;
+
+__host__ __device__ __forceinline__ int64_t struct_elem(const StructMap &sm, int64_t l) {
+    return (int64_t)(((uint64_t)l * sm.magic) >> sm.shift);
+}
+
+// The record point l (element e, position entry pe) needs: its face's or
+// its edge slot's (face 0's for an interior point, which uses none).
+// Loaded first: the address of the value the point gathers depends on it.
+__host__ __device__ __forceinline__ ElemRec struct_record(const StructMap &sm, int64_t e,
+                                                          uint32_t pe) {
+    return sm.rec[e * sm.nrec + (pe >> 12)];
+}
+
+// Where point l finds the value it loads besides its own w, as an index
+// into wg = [w | the edge-group sums] (the sums sit right after the n local
+// values): a face point the copy on the neighbour's face (its own index
+// when it has none), a shared edge or corner node n + its group's rank, any
+// other point its own index; and its code byte.  Every path gives an index
+// inside wg.
+struct StructSrc {
+    int64_t idx;
+    uint8_t code;
+    bool edge;
+};
+__host__ __device__ __forceinline__ StructSrc struct_source(const StructMap &sm, int64_t n,
+                                                            int64_t l, uint32_t pe,
+                                                            const ElemRec &rc) {
+    const int kind = (int)(pe & 3);
+    const int a = (int)((pe >> 2) & 31), b = (int)((pe >> 7) & 31);
+    const uint8_t code = (uint8_t)(rc.hi & 255);
+    const int32_t sa = (int32_t)((uint32_t)rc.hi << 12) >> 20;   // bits 8-19, signed
+    const int32_t sb = rc.hi >> 20;                               // bits 20-31, signed
+    const int64_t q = (int64_t)(rc.lo + sa * a + sb * b);
+    const bool eshared = (code & kMultMask) >= 2 && !(code & kDirichletBit);
+    StructSrc s;
+    const int64_t own_or_face = kind == 1 ? q : l;
+    s.idx = (kind == 2 && eshared) ? n + (int64_t)rc.lo : own_or_face;
+    s.code = kind == 0 ? (uint8_t)1 : code;
+    s.edge = kind == 2;
+    return s;
+}
+// mask(QQ^T w)_l from the loaded value: a face pair adds its partner (the
+// sum a + b == b + a of the gather-scatter), a shared edge or corner node
+// takes its group's sum (the gather-scatter's ascending order), points with
+// m = 1 keep their own value, Dirichlet points get 0.
+template <typename T>
+__host__ __device__ __forceinline__ T struct_sum(T own, uint8_t code, bool edge, T src) {
+    const bool shared = (code & kMultMask) >= 2;
+    const T pair_sum = own + src;
+    T v = edge ? (shared ? src : own) : (code == kPairCode ? pair_sum : own);
+    return (code & kDirichletBit) ? T(0) : v;
+}
+
+// update_gather_body with the table-free gather: the same per-thread packs,
+// the same values and the same sums, so bitwise the same results.  n is a
+// multiple of 4 (P^3 is), and the 4 points of a pack lie in one element.
+// wg: w followed by the edge-group sums.  Load order: the element records
+// first (pinned there by a compiler fence, so none is moved into a branch),
+// then r and w, then the gathered values, whose addresses need only
+// the records (loads complete in issue order, so the gathers wait for the
+// records, not for r and w).
+template <typename T, bool PC = false>
+__device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
+                                                   const T *__restrict__ wg,
+                                                   const StructMap &sm, CgState *st,
+                                                   double *partial, int64_t vb, int64_t vgrid,
+                                                   PcArgs<T> pc = PcArgs<T>{}) {
+    if (st->stop) return;
+    __shared__ double cw[kVecThreads];
+    __shared__ double red[16];
+    __shared__ __align__(16) uint32_t pos[kMaxPosTab];
+    for (int q = threadIdx.x; q < sm.p3; q += blockDim.x) pos[q] = sm.pos_tab[q];
+    weights_lds(cw);
+    const T a = (T)st->alpha;
+    double acc = 0.0, acc2 = 0.0;
+    const int64_t n4 = n >> 2;
+    const int64_t stride = vgrid * blockDim.x;
+    const int64_t tid = vb * blockDim.x + threadIdx.x;
+    constexpr int K = kUpdPacks;
+    for (int64_t q = tid; q < n4; q += K * stride) {
+        int64_t qq[K];
+        bool live[K];
+#pragma unroll
+        for (int h = 0; h < K; ++h) {
+            live[h] = q + h * stride < n4;
+            qq[h] = live[h] ? q + h * stride : q;
+        }
+        uint32_t pv[K][4];
+        ElemRec rc[K][4];
+#pragma unroll
+        for (int h = 0; h < K; ++h) {
+            const int64_t l0 = 4 * qq[h];
+            const int64_t e = struct_elem(sm, l0);
+            const uint4 pe = *reinterpret_cast<const uint4 *>(pos + (l0 - e * sm.p3));
+            pv[h][0] = pe.x, pv[h][1] = pe.y, pv[h][2] = pe.z, pv[h][3] = pe.w;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) rc[h][t] = struct_record(sm, e, pv[h][t]);
+        }
+        __asm__ volatile("" ::: "memory");
+        Pack4<T> rv[K], wv[K];
+#pragma unroll
+        for (int h = 0; h < K; ++h) {
+            rv[h] = reinterpret_cast<const Pack4<T> *>(r)[qq[h]];
+            wv[h] = reinterpret_cast<const Pack4<T> *>(wg)[qq[h]];
+        }
+        int64_t ix[K][4];
+        uint8_t cd[K][4];
+        bool ed[K][4];
+#pragma unroll
+        for (int h = 0; h < K; ++h)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const StructSrc ss = struct_source(sm, n, 4 * qq[h] + t, pv[h][t], rc[h][t]);
+                ix[h][t] = ss.idx;
+                cd[h][t] = ss.code;
+                ed[h][t] = ss.edge;
+            }
+        T src[K][4];
+#pragma unroll
+        for (int h = 0; h < K; ++h)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) src[h][t] = wg[ix[h][t]];
+        // a pack past the end (!live) repeats the first: it stores the same
+        // values and adds exactly 0 to the sums
+#pragma unroll
+        for (int h = 0; h < K; ++h) {
+            Pack4<T> mi{}, zv{};
+            if constexpr (PC) mi = reinterpret_cast<const Pack4<T> *>(pc.minv)[qq[h]];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T wg = struct_sum<T>(wv[h].v[t], cd[h][t], ed[h][t], src[h][t]);
+                rv[h].v[t] -= a * wg;
+                const double rd = (double)rv[h].v[t];
+                if constexpr (PC) {
+                    zv.v[t] = mi.v[t] * rv[h].v[t];
+                    acc += live[h] ? rd * (double)zv.v[t] * cw[cd[h][t]] : 0.0;
+                    acc2 += live[h] ? rd * rd * cw[cd[h][t]] : 0.0;
+                } else {
+                    acc += live[h] ? rd * rd * cw[cd[h][t]] : 0.0;
+                }
+            }
+            reinterpret_cast<Pack4<T> *>(r)[qq[h]] = rv[h];
+            if constexpr (PC) reinterpret_cast<Pack4<T> *>(pc.z)[qq[h]] = zv;
+        }
+    }
+    const double s = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) partial[vb] = s;
+    if constexpr (PC) {
+        const double s2 = block_sum_f64(acc2, red);
+        if (threadIdx.x == 0) pc.partial2[vb] = s2;
+    }
+}
+
 // rho_i = sum of the update partials; beta_i = rho_i / rho_{i-1}; the
 // iteration count, the history and the stopping test (Algorithm 1, last
 // two steps).  One block.

@@ -7,8 +7,10 @@
 // usage: gather_tables_check E N glob_id.bin dirichlet.bin seed
 //   glob_id.bin: int64 [E][(N+1)^3], dirichlet.bin: uint8 [E][(N+1)^3]
 // Prints "gs_in_update=<0|1> checked=<points> odd_m=<points with m other
-// than 1, 2, 4, 8> gsum_wedge=<0|1>" and exits 0, or names the first
-// failing point and exits 1.
+// than 1, 2, 4, 8> gsum_wedge=<0|1> table_free=<0|1> checked_tf=<points>"
+// and exits 0, or names the first failing point and exits 1.  The
+// table-free form (odd N) is checked the same way: every point's decoded
+// code and value against its copies' ascending-order sum, bitwise.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -187,8 +189,84 @@ int main(int argc, char **argv) {
             ++checked;
         }
     }
-    std::printf("gs_in_update=%d checked=%lld odd_m=%lld gsum_wedge=%d\n",
+    // the table-free form: the operator's compact edge copy, the sums of the
+    // edge-node groups in class order (the group-sum kernel's order: members
+    // as listed), then the update's decode of every point, bitwise against
+    // the same ascending-order sums
+    int64_t checked_tf = 0;
+    if (t.gs_struct) {
+        const int MS = sem::edge_slots(N);
+        CHECK(N % 2 == 1 && (int)t.pos_tab.size() == P3, "table-free form at N = %d", N);
+        std::vector<float> we32((size_t)E * MS, 0.f);
+        std::vector<double> we64((size_t)E * MS, 0.0);
+        for (l = 0; l < n; ++l) {
+            const int loc = (int)(l % P3);
+            const int es = sem::edge_slot(N, loc % P, (loc / P) % P, loc / (P * P));
+            if (es >= 0) {
+                we32[(size_t)(l / P3) * MS + es] = w32[l];
+                we64[(size_t)(l / P3) * MS + es] = w64[l];
+            }
+        }
+        std::vector<float> es32;
+        std::vector<double> es64;
+        for (int c = 0; c < t.ecls.ncls; ++c) {
+            const int M = t.ecls.M[c];
+            CHECK(M >= 2, "edge class of %d copies", M);
+            for (int64_t g = 0; g < t.ecls.ng[c]; ++g) {
+                const int32_t *ix = t.ewedge_idx.data() + t.ecls.io[c] + g * M;
+                float s32 = we32[ix[0]];
+                double s64 = we64[ix[0]];
+                for (int q = 1; q < M; ++q) {
+                    CHECK(ix[q] >= 0 && ix[q] < E * MS, "edge position %d", ix[q]);
+                    s32 += we32[ix[q]];
+                    s64 += we64[ix[q]];
+                }
+                es32.push_back(s32);
+                es64.push_back(s64);
+            }
+        }
+        CHECK((int64_t)es32.size() == t.n_egroups, "%zu edge groups, tables say %lld",
+              es32.size(), (long long)t.n_egroups);
+        const sem::vecb::StructMap sm{t.erec.data(), t.pos_tab.data(), P3, 6 + MS, t.p3_magic,
+                                      t.p3_shift};
+        // the update's wg: w followed by the edge-group sums
+        std::vector<float> wg32(w32);
+        std::vector<double> wg64(w64);
+        wg32.insert(wg32.end(), es32.begin(), es32.end());
+        wg64.insert(wg64.end(), es64.begin(), es64.end());
+        for (l = 0; l < n; ++l) {
+            const int64_t l0 = l & ~(int64_t)3;
+            const int64_t e = sem::vecb::struct_elem(sm, l0);
+            CHECK(e == l / P3, "element %lld of a pack", (long long)e);
+            const uint32_t pe = t.pos_tab[l - e * P3];
+            const sem::ElemRec rc = sem::vecb::struct_record(sm, e, pe);
+            const sem::vecb::StructSrc ss = sem::vecb::struct_source(sm, n, l, pe, rc);
+            CHECK(ss.code == t.mcode[l], "decoded code %d, expected %d", ss.code, t.mcode[l]);
+            CHECK(ss.idx >= 0 && ss.idx < (int64_t)wg32.size(), "source index %lld out of bounds",
+                  (long long)ss.idx);
+            const std::vector<int64_t> &cp = copies[gid[l]];
+            float s32 = w32[cp[0]];
+            double s64 = w64[cp[0]];
+            for (size_t q = 1; q < cp.size(); ++q) {
+                s32 += w32[cp[q]];
+                s64 += w64[cp[q]];
+            }
+            if (t.mcode[l] & sem::kDirichletBit) {
+                s32 = 0.f;
+                s64 = 0.0;
+            }
+            const float g32 = sem::vecb::struct_sum<float>(w32[l], ss.code, ss.edge, wg32[ss.idx]);
+            const double g64 = sem::vecb::struct_sum<double>(w64[l], ss.code, ss.edge, wg64[ss.idx]);
+            CHECK(std::memcmp(&g32, &s32, 4) == 0, "table-free fp32 gather %a, expected %a", g32,
+                  s32);
+            CHECK(std::memcmp(&g64, &s64, 8) == 0, "table-free fp64 gather %a, expected %a", g64,
+                  s64);
+            ++checked_tf;
+        }
+    }
+    std::printf("gs_in_update=%d checked=%lld odd_m=%lld gsum_wedge=%d table_free=%d "
+                "checked_tf=%lld\n",
                 t.gs_in_update ? 1 : 0, (long long)checked, (long long)odd_m,
-                t.gsum_wedge ? 1 : 0);
+                t.gsum_wedge ? 1 : 0, t.gs_struct ? 1 : 0, (long long)checked_tf);
     return 0;
 }

@@ -194,3 +194,54 @@ def test_cg_gather_in_update_modes(prec):
                                    rtol=1e-11 if fp64 else 1e-4)
         assert rel_norm(to_host(x), xo) < (1e-11 if fp64 else 1e-4)
         gm.close()
+
+
+@pytest.mark.parametrize("N", [5, 7, 9])
+def test_cg_table_free_gather_bitwise_equals_table(N):
+    """Odd orders gather the shared sums in the update from each point's
+    position and per-element face and edge records instead of a per-point
+    table: FP32 (both G forms, with and without Jacobi), FP64 and mixed
+    solves give bitwise the results of the table form (SEM_MESH_GATHER_TABLE)
+    on a permuted, reoriented mesh, and on one whose only Dirichlet face is
+    x = 0 (free boundary faces, edges and corners)."""
+    import dataclasses
+
+    import torch
+    import paper_2108_12188_amd as sem
+    base = box_mesh(4, 3, 3, N, perturb=0.1, seed=90 + N, permute=True, reorient=True)
+    GX = 4 * N + 1
+    one_face = dataclasses.replace(base, dirichlet=(base.glob_id % GX == 0).astype(np.uint8))
+    for mesh, tag in ((base, "box"), (one_face, "x0")):
+        b = random_global_rhs(mesh, seed=91)
+        meshes = [sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True),
+                  sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True, gather_table=True)]
+        assert meshes[0].info()["gs_table_free"] == 1
+        assert meshes[1].info()["gs_table_free"] == 0
+        runs = [("fp32-otf", sem.FP32, sem.ON_THE_FLY, 0), ("fp32-otf-jacobi", sem.FP32,
+                                                          sem.ON_THE_FLY, 1),
+                ("fp32-pre", sem.FP32, sem.PRECOMPUTED, 0), ("fp64-pre", sem.FP64,
+                                                              sem.PRECOMPUTED, 0)]
+        for name, prec, geom, pc in runs:
+            say(f"table-free gather N={N} {tag} {name}")
+            out = []
+            for gm in meshes:
+                dt = torch.float64 if prec == sem.FP64 else torch.float32
+                x, r = gm.cg_solve(to_dev(b, dt), prec=prec, geom=geom, fixed_iters=30,
+                                   history=31, precond=pc)
+                out.append((to_host(x), r))
+            (x0, r0), (x1, r1) = out
+            assert np.array_equal(x0, x1), name
+            assert np.array_equal(r0["hist_rho"], r1["hist_rho"]), name
+            # alpha_i from i = 1 (entry 0 is not written)
+            assert np.array_equal(r0["hist_alpha"][1:], r1["hist_alpha"][1:]), name
+        say(f"table-free gather N={N} {tag} mixed")
+        out = [gm.cg_solve(to_dev(b, torch.float64), prec=sem.MIXED, geom=sem.ON_THE_FLY,
+                           tol=1e-10) for gm in meshes]
+        assert out[0][1]["iters"] == out[1][1]["iters"]
+        assert np.array_equal(to_host(out[0][0]), to_host(out[1][0]))
+        for gm in meshes:
+            gm.close()
+    # an even order keeps the table
+    even = sem.Mesh.from_box(box_mesh(2, 2, 2, 6, perturb=0.1, seed=92))
+    assert even.info()["gs_table_free"] == 0 and even.info()["gs_in_update"] == 1
+    even.close()

@@ -49,6 +49,10 @@ def test_conforming_meshes_gather_in_update(checker, tmp_path, shape, N):
     assert int(out["checked"]) == mesh.E * (N + 1) ** 3
     if min(shape) > 1:   # interior edges exist: groups with m > 2 on element edges
         assert out["gsum_wedge"] == "1"
+    # odd orders also take the table-free form (P^3 a multiple of 4), checked
+    # point by point the same way
+    assert out["table_free"] == ("1" if N % 2 else "0")
+    assert int(out["checked_tf"]) == (mesh.E * (N + 1) ** 3 if N % 2 else 0)
 
 
 def test_odd_multiplicities_take_the_generic_loop(checker, tmp_path):
@@ -66,6 +70,22 @@ def test_odd_multiplicities_take_the_generic_loop(checker, tmp_path):
     assert out["gs_in_update"] == "1"
     assert int(out["odd_m"]) == 3
     assert out["gsum_wedge"] == "0"   # a group of face-interior nodes
+
+
+def test_face_group_of_three_keeps_the_table(checker, tmp_path):
+    """At odd N a face-interior node shared by three copies has no single
+    partner: the table-free form declines and the per-point table (still
+    checked bitwise) is used."""
+    mesh = box_mesh(3, 2, 2, 5, perturb=0.1, seed=8)
+    P = mesh.N + 1
+    gid = mesh.glob_id.copy()
+    face = mesh.N + P * (2 + P * 2)
+    other = 0 + P * (2 + P * 2)
+    gid[5, other] = gid[0, face]
+    out = _run(checker, tmp_path, mesh, gid)
+    assert out["gs_in_update"] == "1"
+    assert out["table_free"] == "0"
+    assert int(out["checked"]) == mesh.E * P ** 3
 
 
 def test_interior_tie_disables_gather_in_update(checker, tmp_path):
