@@ -59,10 +59,14 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  * The on-the-fly form needs none of them (it reads the vertices). */
 #define SEM_MESH_G_FP32 0x1u   /* G as float [E][6][P3]  (24 B per point)  */
 #define SEM_MESH_G_FP64 0x2u   /* G as double [E][6][P3] (48 B per point)  */
-/* Keep the per-point table form of the gather-scatter inside CG even where
- * the table-free form applies (odd N, conforming meshes); the two give
- * bitwise identical results.  For comparison and testing. */
+/* Form of the gather-scatter inside CG (the two give bitwise identical
+ * results).  The table-free form applies to odd N on conforming meshes and
+ * is used by default from 6 * 2^20 local points on (smaller meshes run
+ * faster with the per-point table).  SEM_MESH_GATHER_TABLE keeps the table
+ * form; SEM_MESH_GATHER_TABLE_FREE takes the table-free form wherever it
+ * applies, whatever the size.  Not both. */
 #define SEM_MESH_GATHER_TABLE 0x4u
+#define SEM_MESH_GATHER_TABLE_FREE 0x8u
 
 /*
  * Build a mesh on the current HIP device (Sec. 3: decomposition into E
@@ -78,7 +82,7 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  *   dirichlet  HOST uint8 [E][P3]: 1 on the Dirichlet boundary; must be equal
  *              on all copies of a global point.  May be NULL (no boundary).
  *   flags      bit set of SEM_MESH_G_FP32 / SEM_MESH_G_FP64 /
- *              SEM_MESH_GATHER_TABLE.
+ *              SEM_MESH_GATHER_TABLE or SEM_MESH_GATHER_TABLE_FREE.
  *   out        receives the handle.
  * Copies what it needs; the host arrays may be freed on return.  Blocks until
  * the device-side setup (geometric factors, Jacobian check) has finished.
@@ -106,9 +110,9 @@ typedef struct {
                               gathers the shared sums inside its vector update instead of a
                               separate gather-scatter pass (same results, bitwise) */
     int32_t gs_table_free; /* 1: that gather derives each point's copies from its position in
-                              the element and per-element face and edge records (odd N,
-                              conforming mesh, no SEM_MESH_GATHER_TABLE) instead of a
-                              per-point table (same results, bitwise) */
+                              the element and per-element face and edge records (see
+                              SEM_MESH_GATHER_TABLE_FREE) instead of a per-point table (same
+                              results, bitwise) */
 } sem_mesh_info_t;
 
 sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);

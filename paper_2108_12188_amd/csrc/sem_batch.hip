@@ -43,7 +43,7 @@ struct UpdBatchDesc {
     int64_t vgrid;
 };
 
-// group sums of one problem (see launch_group_sums_cg)
+// group sums of one problem (see launch_group_sums_cg / launch_edge_sums_cg)
 struct GsumBatchDesc {
     const GsClasses *cls;
     const int32_t *idx;
@@ -51,6 +51,7 @@ struct GsumBatchDesc {
     const float *src;
     float *out;
     const CgState *st;
+    int mmin;
 };
 
 // update with gather of one problem (see launch_update_gather)
@@ -61,6 +62,17 @@ struct UpdGBatchDesc {
     const float *gsum;
     const uint8_t *mcode;
     vecb::GatherMap gm;
+    CgState *st;
+    double *partial;
+    int64_t vgrid;
+};
+
+// update with the table-free gather of one problem (see launch_update_struct)
+struct UpdSBatchDesc {
+    int64_t n;
+    float *r;
+    const float *wg;
+    vecb::StructMap sm;
     CgState *st;
     double *partial;
     int64_t vgrid;
@@ -93,7 +105,7 @@ group_sums_batch_kernel(const GsumBatchDesc *__restrict__ d, const int2 *__restr
     const int2 pv = blk[blockIdx.x];
     const GsumBatchDesc g = d[pv.x];
     if (g.st->stop) return;
-    gsb::gs_sums_logical_block<float>(*g.cls, pv.y, g.idx, g.io0, g.src, g.out);
+    gsb::gs_sums_logical_block<float>(*g.cls, pv.y, g.idx, g.io0, g.src, g.out, g.mmin);
 }
 
 __global__ void __launch_bounds__(vecb::kVecThreads)
@@ -110,6 +122,13 @@ update_gather_batch_kernel(const UpdGBatchDesc *__restrict__ d, const int2 *__re
     const UpdGBatchDesc u = d[pv.x];
     vecb::update_gather_body<float>(u.n, u.r, u.w, u.gsum, u.mcode, u.gm, u.st, u.partial, pv.y,
                                     u.vgrid);
+}
+
+__global__ void __launch_bounds__(vecb::kVecThreads)
+update_struct_batch_kernel(const UpdSBatchDesc *__restrict__ d, const int2 *__restrict__ blk) {
+    const int2 pv = blk[blockIdx.x];
+    const UpdSBatchDesc u = d[pv.x];
+    vecb::update_struct_body<float>(u.n, u.r, u.wg, u.sm, u.st, u.partial, pv.y, u.vgrid);
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads)
@@ -169,12 +188,15 @@ struct BatchImpl {
     UpdGBatchDesc *d_updg = nullptr;
     int2 *d_updg_blk = nullptr;
     int64_t n_updg_blk = 0;
+    UpdSBatchDesc *d_upds = nullptr;
+    int2 *d_upds_blk = nullptr;
+    int64_t n_upds_blk = 0;
     FinBatchDesc *d_fin[2] = {nullptr, nullptr};   // [precomputed, on the fly]
     int2 *d_states = nullptr;
     int2 *h_states = nullptr;                        // pinned
     size_t cap_ax[2] = {0, 0}, cap_fin[2] = {0, 0}, cap_cls = 0, cap_gs = 0, cap_gs_blk = 0,
            cap_upd = 0, cap_upd_blk = 0, cap_gsum = 0, cap_gsum_blk = 0, cap_updg = 0,
-           cap_updg_blk = 0, cap_states = 0, cap_h_states = 0;
+           cap_updg_blk = 0, cap_upds = 0, cap_upds_blk = 0, cap_states = 0, cap_h_states = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -188,7 +210,8 @@ struct BatchImpl {
             for (auto &g : groups[f])
                 if (g.blk) (void)hipFree(g.blk);
         void *ptrs[] = {d_ax[0],   d_ax[1], d_cls,      d_gs,   d_gs_blk,   d_upd,
-                        d_upd_blk, d_gsum,  d_gsum_blk, d_updg, d_updg_blk, d_fin[0],
+                        d_upd_blk, d_gsum,  d_gsum_blk, d_updg, d_updg_blk, d_upds, d_upds_blk,
+                        d_fin[0],
                         d_fin[1],  d_states};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
@@ -223,6 +246,9 @@ struct BatchImpl {
         if (n_updg_blk > 0)
             hipLaunchKernelGGL(update_gather_batch_kernel, dim3((unsigned)n_updg_blk),
                                dim3(vecb::kVecThreads), 0, s, d_updg, d_updg_blk);
+        if (n_upds_blk > 0)
+            hipLaunchKernelGGL(update_struct_batch_kernel, dim3((unsigned)n_upds_blk),
+                               dim3(vecb::kVecThreads), 0, s, d_upds, d_upds_blk);
         hipLaunchKernelGGL(finalize_rho_batch_kernel, dim3(count()), dim3(kFinalizeThreads), 0, s,
                            d_fin[f]);
         check_hip(hipGetLastError(), "batched iteration launch");
@@ -320,8 +346,9 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     std::vector<UpdBatchDesc> upd;
     std::vector<GsumBatchDesc> gsumd;
     std::vector<UpdGBatchDesc> updg;
+    std::vector<UpdSBatchDesc> upds;
     std::vector<FinBatchDesc> fin[2];
-    std::vector<int2> gs_blk, upd_blk, gsum_blk, updg_blk;
+    std::vector<int2> gs_blk, upd_blk, gsum_blk, updg_blk, upds_blk;
     std::map<int, std::vector<int2>> order_blk[2];
     std::map<int, int> order_epb[2];
     std::map<int, bool> order_mfma[2];
@@ -338,7 +365,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             a.st = ws.st;
             a.partial = ws.part_ax;
             a.x = static_cast<float *>(ws.x);
-            a.wedge = m.gsum_wedge ? static_cast<float *>(ws.wedge) : nullptr;
+            a.wedge = (m.gsum_wedge || m.gs_struct) ? static_cast<float *>(ws.wedge) : nullptr;
             ax[otf].push_back(a);
         }
         for (int f = 0; f < 2; ++f) {
@@ -353,10 +380,24 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
             order_xi[m.N] = m.h_xi;
             order_w[m.N] = m.h_w;
         }
-        cls.push_back(m.gs);
+        cls.push_back(m.gs_struct ? m.ecls : m.gs);
         const int64_t nlb = m.n_groups > 0 ? gs_logical_blocks(m) : 0;
         const int nv = vec_blocks(m.n);
-        if (m.gs_in_update) {
+        if (m.gs_struct) {
+            // the single-mesh schedule with the table-free gather: sums of
+            // every edge-node group after w, then the update
+            float *wg = static_cast<float *>(ws.w);
+            gsumd.push_back({d_cls + q, m.ewedge_idx, (int64_t)0,
+                             static_cast<const float *>(ws.wedge), wg + m.n, ws.st, 2});
+            const int64_t nelb = gs_total_blocks(m.ecls);
+            for (int64_t lb = 0; lb < nelb; ++lb)
+                gsum_blk.push_back(make_int2((int)gsumd.size() - 1, (int)lb));
+            const vecb::StructMap sm{m.erec, m.pos_tab, m.P3, 6 + edge_slots(m.N), m.p3_magic,
+                                     m.p3_shift};
+            upds.push_back({m.n, static_cast<float *>(ws.r), wg, sm, ws.st, ws.part_vec, nv});
+            for (int vb = 0; vb < nv; ++vb)
+                upds_blk.push_back(make_int2((int)upds.size() - 1, vb));
+        } else if (m.gs_in_update) {
             // the single-mesh schedule: group sums of the edge and vertex
             // groups, update with gather (the same logical and virtual blocks)
             const bool compact = m.gsum_wedge;
@@ -364,7 +405,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
                              compact ? m.wedge_io0 : (int64_t)0,
                              compact ? static_cast<const float *>(ws.wedge)
                                      : static_cast<const float *>(ws.w),
-                             static_cast<float *>(ws.gsum), ws.st});
+                             static_cast<float *>(ws.gsum), ws.st, 3});
             for (int64_t lb = m.gs_blk_multi; lb < nlb; ++lb)
                 gsum_blk.push_back(make_int2((int)gsumd.size() - 1, (int)lb));
             const vecb::GatherMap gm{m.gsrc};
@@ -398,6 +439,8 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     upload_sync(d_gsum, gsumd);
     ensure_cap(d_updg, cap_updg, count, bytes);
     upload_sync(d_updg, updg);
+    ensure_cap(d_upds, cap_upds, count, bytes);
+    upload_sync(d_upds, upds);
     for (int f = 0; f < 2; ++f) {
         ensure_cap(d_fin[f], cap_fin[f], count, bytes);
         upload_sync(d_fin[f], fin[f]);
@@ -421,6 +464,9 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     n_updg_blk = (int64_t)updg_blk.size();
     ensure_cap(d_updg_blk, cap_updg_blk, updg_blk.size(), bytes);
     upload_sync(d_updg_blk, updg_blk);
+    n_upds_blk = (int64_t)upds_blk.size();
+    ensure_cap(d_upds_blk, cap_upds_blk, upds_blk.size(), bytes);
+    upload_sync(d_upds_blk, upds_blk);
     for (int f = 0; f < 2; ++f) {
         for (auto &g : groups[f])
             if (g.blk) (void)hipFree(g.blk);

@@ -18,6 +18,8 @@ constexpr int kMaxMultiplicity = 127;
 constexpr uint8_t kDirichletBit = 0x80;
 constexpr uint8_t kMultMask = 0x7F;
 constexpr int kMaxP = kMaxOrder + 1;
+// local points from which a mesh takes the table-free gather by default
+constexpr int64_t kTableFreeMinPoints = int64_t(6) << 20;
 
 // Edge and corner nodes of an element's P^3 block (on two or three of its
 // faces): 12 N - 4 of them, numbered column by column (i, j on the border

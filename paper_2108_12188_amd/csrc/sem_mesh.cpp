@@ -90,8 +90,11 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     if (N < 1 || N > kMaxOrder)
         fail(SEM_EUNSUPPORTED, "order N=" + std::to_string(N) + " is not built (1..11)");
     if (!vert || !gid) fail(SEM_EINVAL, "vert_xyz and glob_id must not be NULL");
-    if (flags & ~(uint32_t)(SEM_MESH_G_FP32 | SEM_MESH_G_FP64 | SEM_MESH_GATHER_TABLE))
+    if (flags & ~(uint32_t)(SEM_MESH_G_FP32 | SEM_MESH_G_FP64 | SEM_MESH_GATHER_TABLE |
+                            SEM_MESH_GATHER_TABLE_FREE))
         fail(SEM_EINVAL, "unknown mesh flags");
+    if ((flags & SEM_MESH_GATHER_TABLE) && (flags & SEM_MESH_GATHER_TABLE_FREE))
+        fail(SEM_EINVAL, "SEM_MESH_GATHER_TABLE and SEM_MESH_GATHER_TABLE_FREE exclude each other");
     const int P = N + 1, P3 = P * P * P;
     const int64_t n = E * P3;
     if (E > (int64_t(1) << 31) / P3 || n >= (int64_t(1) << 31))
@@ -117,7 +120,10 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     m->gs_blk_multi = t.gs_blk_multi;
     m->gsum_wedge = t.gsum_wedge;
     m->wedge_io0 = t.wedge_io0;
-    m->gs_struct = t.gs_struct && !(flags & SEM_MESH_GATHER_TABLE);
+    // the table-free gather where it applies: forced, or by size (below about
+    // 6 M points its fixed per-block set-up costs more than the table's bytes)
+    m->gs_struct = t.gs_struct && !(flags & SEM_MESH_GATHER_TABLE) &&
+                   ((flags & SEM_MESH_GATHER_TABLE_FREE) || n >= kTableFreeMinPoints);
     if (m->gs_struct) {
         m->ecls = t.ecls;
         m->n_egroups = t.n_egroups;
@@ -139,7 +145,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         m->mcode = dev_alloc<uint8_t>(*m, (size_t)n);
         m->gs_idx = dev_alloc<int32_t>(*m, t.gs_idx.size());
         m->dir_idx = dev_alloc<int32_t>(*m, t.dir_idx.size());
-        if (t.gs_in_update) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
+        if (t.gs_in_update && !m->gs_struct) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
         if (t.gsum_wedge) m->wedge_idx = dev_alloc<int32_t>(*m, t.wedge_idx.size());
         if (m->gs_struct) {
             m->erec = dev_alloc<ElemRec>(*m, t.erec.size());
@@ -178,9 +184,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         upload(m->mcode, t.mcode.data(), t.mcode.size(), s);
         upload(m->gs_idx, t.gs_idx.data(), t.gs_idx.size(), s);
         upload(m->dir_idx, t.dir_idx.data(), t.dir_idx.size(), s);
-        if (t.gs_in_update) {
-            upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
-        }
+        if (t.gs_in_update && !m->gs_struct) upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
         if (t.gsum_wedge) upload(m->wedge_idx, t.wedge_idx.data(), t.wedge_idx.size(), s);
         if (m->gs_struct) {
             upload(m->erec, t.erec.data(), t.erec.size(), s);

@@ -243,6 +243,7 @@ void launch_update_gather(const Mesh &m, T *r, const T *w, const T *gsum, CgStat
                           double *partial, hipStream_t s, PcArgs<T> pc) {
     if (!m.gs_in_update)
         fail(SEM_EUNSUPPORTED, "mesh shares points inside elements: no gather in the update");
+    if (!m.gsrc) fail(SEM_EUNSUPPORTED, "mesh holds no per-point gather table");
     const GatherMap gm{m.gsrc};
     const int nb = vec_blocks(m.n);
     if (pc.minv)

@@ -45,6 +45,36 @@ def test_batch_fp32_fixed_equals_solo(geom):
     batch.close()
 
 
+@pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
+def test_batch_mixed_gather_forms_equal_solo(geom):
+    """One batch holding meshes with the table-free gather (odd N, forced), with
+    the per-point table (SEM_MESH_GATHER_TABLE, and an even order): every
+    problem ends bitwise equal to its own solve, and the two forms of the
+    same mesh to each other."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"batch mixed gather forms geom={geom}")
+    b7 = box_mesh(3, 3, 2, 7, perturb=0.1, seed=60, reorient=True, permute=True)
+    b4 = box_mesh(3, 2, 2, 4, perturb=0.1, seed=61, reorient=True, permute=True)
+    b9 = box_mesh(2, 2, 3, 9, perturb=0.1, seed=62)
+    gms = [sem.Mesh.from_box(b7, table_free=True), sem.Mesh.from_box(b7, gather_table=True),
+           sem.Mesh.from_box(b4, table_free=True), sem.Mesh.from_box(b9, table_free=True)]
+    assert [g.info()["gs_table_free"] for g in gms] == [1, 0, 0, 1]
+    boxes = [b7, b7, b4, b9]
+    bs = [to_dev(random_global_rhs(b, seed=70 + (q != 1) * q), torch.float32)
+          for q, b in enumerate(boxes)]
+    batch = sem.Batch(gms)
+    xs, res = batch.solve(bs, prec=sem.FP32, geom=geom, fixed_iters=19)
+    for q, gm in enumerate(gms):
+        xq, rq = gm.cg_solve(bs[q], prec=sem.FP32, geom=geom, fixed_iters=19)
+        assert res[q]["iters"] == 19 == rq["iters"]
+        assert torch.equal(xs[q], xq), q
+    assert torch.equal(xs[0], xs[1])
+    batch.close()
+    for g in gms:
+        g.close()
+
+
 def test_batch_fp32_tolerance_equals_solo_and_oracle():
     import torch
     import paper_2108_12188_amd as sem

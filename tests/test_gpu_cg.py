@@ -198,12 +198,14 @@ def test_cg_gather_in_update_modes(prec):
 
 @pytest.mark.parametrize("N", [5, 7, 9])
 def test_cg_table_free_gather_bitwise_equals_table(N):
-    """Odd orders gather the shared sums in the update from each point's
+    """Odd orders can gather the shared sums in the update from each point's
     position and per-element face and edge records instead of a per-point
-    table: FP32 (both G forms, with and without Jacobi), FP64 and mixed
-    solves give bitwise the results of the table form (SEM_MESH_GATHER_TABLE)
-    on a permuted, reoriented mesh, and on one whose only Dirichlet face is
-    x = 0 (free boundary faces, edges and corners)."""
+    table (forced here with SEM_MESH_GATHER_TABLE_FREE: these meshes are
+    below the size from which it is the default): FP32 (both G forms, with
+    and without Jacobi), FP64 and mixed solves give bitwise the results of
+    the table form (SEM_MESH_GATHER_TABLE) on a permuted, reoriented mesh,
+    and on one whose only Dirichlet face is x = 0 (free boundary faces,
+    edges and corners)."""
     import dataclasses
 
     import torch
@@ -213,7 +215,7 @@ def test_cg_table_free_gather_bitwise_equals_table(N):
     one_face = dataclasses.replace(base, dirichlet=(base.glob_id % GX == 0).astype(np.uint8))
     for mesh, tag in ((base, "box"), (one_face, "x0")):
         b = random_global_rhs(mesh, seed=91)
-        meshes = [sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True),
+        meshes = [sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True, table_free=True),
                   sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True, gather_table=True)]
         assert meshes[0].info()["gs_table_free"] == 1
         assert meshes[1].info()["gs_table_free"] == 0
@@ -241,7 +243,25 @@ def test_cg_table_free_gather_bitwise_equals_table(N):
         assert np.array_equal(to_host(out[0][0]), to_host(out[1][0]))
         for gm in meshes:
             gm.close()
-    # an even order keeps the table
-    even = sem.Mesh.from_box(box_mesh(2, 2, 2, 6, perturb=0.1, seed=92))
+    # an even order keeps the table, even when asked
+    even = sem.Mesh.from_box(box_mesh(2, 2, 2, 6, perturb=0.1, seed=92), table_free=True)
     assert even.info()["gs_table_free"] == 0 and even.info()["gs_in_update"] == 1
     even.close()
+
+
+def test_gather_form_default_by_size_and_flags():
+    """The table-free gather is the default from 6 * 2^20 local points on
+    (24^3 N = 7: 7.1 M points), the table below (small meshes run faster
+    with it); asking for both forms is an error."""
+    import paper_2108_12188_amd as sem
+    small = box_mesh(3, 3, 3, 7, perturb=0.1, seed=93)
+    gm = sem.Mesh.from_box(small)
+    assert gm.info()["gs_table_free"] == 0
+    gm.close()
+    with pytest.raises(sem.SemError) as ei:
+        sem.Mesh.from_box(small, gather_table=True, table_free=True)
+    assert ei.value.code == -1
+    say("gather form default on 24^3 N=7")
+    big = sem.Mesh.from_box(box_mesh(24, 24, 24, 7, perturb=0.1, seed=94), g_fp32=False)
+    assert big.info()["gs_table_free"] == 1
+    big.close()
