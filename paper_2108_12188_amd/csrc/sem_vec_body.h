@@ -275,7 +275,7 @@ __host__ __device__ __forceinline__ ElemRec struct_record(const StructMap &sm, i
 // other point its own index; and its code byte.  Every path gives an index
 // inside wg.
 struct StructSrc {
-    int64_t idx;
+    int32_t idx;      // n + the number of edge groups stays below 2^31 (host check)
     uint8_t code;
     bool edge;
 };
@@ -287,11 +287,11 @@ __host__ __device__ __forceinline__ StructSrc struct_source(const StructMap &sm,
     const uint8_t code = (uint8_t)(rc.hi & 255);
     const int32_t sa = (int32_t)((uint32_t)rc.hi << 12) >> 20;   // bits 8-19, signed
     const int32_t sb = rc.hi >> 20;                               // bits 20-31, signed
-    const int64_t q = (int64_t)(rc.lo + sa * a + sb * b);
+    const int32_t q = rc.lo + sa * a + sb * b;
     const bool eshared = (code & kMultMask) >= 2 && !(code & kDirichletBit);
     StructSrc s;
-    const int64_t own_or_face = kind == 1 ? q : l;
-    s.idx = (kind == 2 && eshared) ? n + (int64_t)rc.lo : own_or_face;
+    const int32_t own_or_face = kind == 1 ? q : (int32_t)l;
+    s.idx = (kind == 2 && eshared) ? (int32_t)n + rc.lo : own_or_face;
     s.code = kind == 0 ? (uint8_t)1 : code;
     s.edge = kind == 2;
     return s;
@@ -360,7 +360,7 @@ __device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
             rv[h] = reinterpret_cast<const Pack4<T> *>(r)[qq[h]];
             wv[h] = reinterpret_cast<const Pack4<T> *>(wg)[qq[h]];
         }
-        int64_t ix[K][4];
+        int32_t ix[K][4];
         uint8_t cd[K][4];
         bool ed[K][4];
 #pragma unroll
