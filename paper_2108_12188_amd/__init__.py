@@ -159,7 +159,12 @@ def _dev_vec(t, n, name):
 
 
 class Mesh:
-    """A mesh on the current HIP device (owns all device-side mesh data)."""
+    """A mesh on the current HIP device (owns all device-side mesh data).
+
+    sem_mesh_create: g_fp32 / g_fp64 keep precomputed geometric factors in
+    that precision; gather_table / table_free choose the form of the
+    gather-scatter inside CG (per-point table, or position-derived at odd
+    N) instead of the size rule (same results either way)."""
 
     def __init__(self, vert, glob_id, dirichlet, N: int, g_fp32: bool = True,
                  g_fp64: bool = False, stream=None, gather_table: bool = False,
