@@ -348,7 +348,8 @@ __device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
         for (int h = 0; h < K; ++h) {
             const int64_t l0 = 4 * qq[h];
             const int64_t e = struct_elem(sm, l0);
-            const uint4 pe = *reinterpret_cast<const uint4 *>(pos + (l0 - e * sm.p3));
+            // 16-byte entries (P^3 and l0 are multiples of 4): one ds_read_b128
+            const uint4 pe = reinterpret_cast<const uint4 *>(pos)[(l0 - e * sm.p3) >> 2];
             pv[h][0] = pe.x, pv[h][1] = pe.y, pv[h][2] = pe.z, pv[h][3] = pe.w;
 #pragma unroll
             for (int t = 0; t < 4; ++t) rc[h][t] = struct_record(sm, e, pv[h][t]);
