@@ -294,7 +294,10 @@ def main(argv=None):
     roof["avg_ms"] = ax_ms
     roof["traffic"] = read_traffic(f"cg_fused_{args.geom}_N{N}", n)
 
-    extra = {"kernel_ms": km, "iteration_ms": sum(km.values()),
+    info = gm.info()
+    extra = {"gather_form": "table-free" if info["gs_table_free"] else
+             ("per-point table" if info["gs_in_update"] else "gather-scatter pass"),
+             "kernel_ms": km, "iteration_ms": sum(km.values()),
              "rel_res_recursive": res["rel_res_recursive"] if res else None}
     if not args.no_extras:
         u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n).astype(np.float32),
