@@ -237,7 +237,6 @@ struct HostTables {
 };
 // Validates glob_id / dirichlet (fail() on error) and fills t.
 void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, HostTables &t);
-int surface_nodes(int N);
 
 // ---------------------------------------------------------------------------
 // Host basis construction (sem_basis.cpp)

@@ -15,12 +15,6 @@
 
 namespace sem {
 
-// Nodes on the surface of one element's P^3 block: P^3 - (P-2)^3 (all 8 for N = 1).
-int surface_nodes(int N) {
-    const int P = N + 1, Pi = P - 2;
-    return P * P * P - (Pi > 0 ? Pi * Pi * Pi : 0);
-}
-
 void gs_classes_finish(GsClasses &c) {
     int64_t blk = 0;
     for (int q = 0; q < c.ncls; ++q) {
