@@ -262,6 +262,17 @@ def test_gather_form_default_by_size_and_flags():
         sem.Mesh.from_box(small, gather_table=True, table_free=True)
     assert ei.value.code == -1
     say("gather form default on 24^3 N=7")
-    big = sem.Mesh.from_box(box_mesh(24, 24, 24, 7, perturb=0.1, seed=94), g_fp32=False)
+    import torch
+    box = box_mesh(24, 24, 24, 7, perturb=0.1, seed=94)
+    big = sem.Mesh.from_box(box, g_fp32=False)
     assert big.info()["gs_table_free"] == 1
+    # at this size too the two forms agree bitwise (10 FP32 iterations)
+    b = to_dev(random_global_rhs(box, seed=95), torch.float32)
+    x0, r0 = big.cg_solve(b, prec=sem.FP32, geom=sem.ON_THE_FLY, fixed_iters=10, history=11)
     big.close()
+    tab = sem.Mesh.from_box(box, g_fp32=False, gather_table=True)
+    assert tab.info()["gs_table_free"] == 0
+    x1, r1 = tab.cg_solve(b, prec=sem.FP32, geom=sem.ON_THE_FLY, fixed_iters=10, history=11)
+    tab.close()
+    assert torch.equal(x0, x1)
+    assert np.array_equal(r0["hist_rho"], r1["hist_rho"])
