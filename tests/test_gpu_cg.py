@@ -276,3 +276,29 @@ def test_gather_form_default_by_size_and_flags():
     tab.close()
     assert torch.equal(x0, x1)
     assert np.array_equal(r0["hist_rho"], r1["hist_rho"])
+
+
+def test_cg_fp32_full_size_matches_oracle():
+    """The headline workload in the launch configuration the benchmark times
+    (32^3 hexahedra, N = 7, +-10% deformed, its mesh and RHS seeds, FP32,
+    on-the-fly G, the built-in engine and gather form: matrix cores,
+    table-free gather): the first 10 iterations against the FP64 oracle,
+    rho to 1e-4 and x to 1e-4 normwise."""
+    import torch
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, RHS_SEED
+    say("cg fp32 full size 32^3 N=7 vs oracle")
+    mesh = box_mesh(32, 32, 32, 7, perturb=0.1, seed=MESH_SEED_BASE + 2)
+    b = random_global_rhs(mesh, seed=RHS_SEED)
+    gm = sem.Mesh.from_box(mesh)
+    assert gm.info()["gs_table_free"] == 1
+    assert sem.ax_engine_get(7, sem.FP32, sem.ON_THE_FLY) == sem.ENGINE_MFMA
+    x, res = gm.cg_solve(to_dev(b, torch.float32), prec=sem.FP32, geom=sem.ON_THE_FLY,
+                         fixed_iters=10, history=11)
+    xh = to_host(x)
+    gm.close()
+    del x
+    pr = oracle.Problem(mesh)
+    xo, _, hist = pr.cg(b, fixed=10)
+    np.testing.assert_allclose(res["hist_rho"][:11], hist["rho"][:11], rtol=1e-4)
+    assert rel_norm(xh, xo) < 1e-4
