@@ -18,6 +18,13 @@ constexpr int kVecMaxBlocks = SEM_VEC_MAX_BLOCKS;
 #define SEM_UPD_PACKS 2
 #endif
 constexpr int kUpdPacks = SEM_UPD_PACKS;
+// the same for the table-free gather, whose records already keep loads in
+// flight (one pack per step measured faster there); the per-thread packs
+// and their order are those of every K, so both forms agree bitwise
+#ifndef SEM_UPD_STRUCT_PACKS
+#define SEM_UPD_STRUCT_PACKS 1
+#endif
+constexpr int kUpdStructPacks = SEM_UPD_STRUCT_PACKS;
 
 template <typename T>
 struct alignas(4 * sizeof(T)) Pack4 {
@@ -333,7 +340,7 @@ __device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
     const int64_t tid = vb * blockDim.x + threadIdx.x;
-    constexpr int K = kUpdPacks;
+    constexpr int K = kUpdStructPacks;
     for (int64_t q = tid; q < n4; q += K * stride) {
         int64_t qq[K];
         bool live[K];
