@@ -10,7 +10,7 @@ namespace vecb {
 
 constexpr int kVecThreads = 256;
 #ifndef SEM_VEC_MAX_BLOCKS
-#define SEM_VEC_MAX_BLOCKS 2048
+#define SEM_VEC_MAX_BLOCKS 4096
 #endif
 constexpr int kVecMaxBlocks = SEM_VEC_MAX_BLOCKS;
 // packs of 4 points a thread of the gather update keeps in flight per step
