@@ -58,15 +58,20 @@ using Fn64 = void (*)(bool, AxMode, const AxArgs<double> &, const double *, cons
 #define SEM_AX_FUSED_MAX_BLOCKS 2048
 #endif
 constexpr int64_t kAxFusedMaxBlocks = SEM_AX_FUSED_MAX_BLOCKS;
-// the matrix-core form's blocks are single waves: 4 times as many
+// the matrix-core form: blocks of one wave (N = 7; measured best of 8192,
+// 16384 and 32768) and of two waves (N = 9: 4096, ahead of 8192)
 #ifndef SEM_AX_MFMA_MAX_BLOCKS
-#define SEM_AX_MFMA_MAX_BLOCKS 8192
+#define SEM_AX_MFMA_MAX_BLOCKS 16384
+#endif
+#ifndef SEM_AX_MFMA2_MAX_BLOCKS
+#define SEM_AX_MFMA2_MAX_BLOCKS 4096
 #endif
 constexpr int64_t kAxMfmaMaxBlocks = SEM_AX_MFMA_MAX_BLOCKS;
+constexpr int64_t kAxMfma2MaxBlocks = SEM_AX_MFMA2_MAX_BLOCKS;
 
 static int64_t ax_grid(int64_t ntiles, AxMode mode, bool mfma, int threads = 64) {
-    // matrix-core blocks: the same number of waves whatever their size
-    const int64_t cap = mfma ? kAxMfmaMaxBlocks * 64 / threads : kAxFusedMaxBlocks;
+    const int64_t cap =
+        mfma ? (threads == 64 ? kAxMfmaMaxBlocks : kAxMfma2MaxBlocks) : kAxFusedMaxBlocks;
     if (mode == AxMode::CgFused && ntiles > cap) return cap;
     return ntiles;
 }
