@@ -14,7 +14,7 @@
  *   - Order N, P = N + 1, P3 = P^3 local points per element; N in [1, 11].
  *   - Local (replicated) vectors have n_local = E * P3 entries, element-major,
  *     local point l = i + P*(j + P*k) inside an element (i fastest).  This is
- *     the "local representation u_L = Q u" of Sec. 3.1.
+ *     the local form u_L = Q u of a global vector u (Sec. 3.1).
  *   - Vectors passed as `void*` are caller-owned DEVICE buffers of n_local
  *     entries of the precision named by the call (double for SEM_FP64 and
  *     SEM_MIXED, float for SEM_FP32), at least 16-byte aligned.  The mesh
@@ -75,7 +75,7 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  *   order_N    N in [1, 11].
  *   vert_xyz   HOST double [E][8][3]: element vertices; vertex a + 2b + 4c sits
  *              at reference corner (xi, eta, gamma) = (2a-1, 2b-1, 2c-1).
- *              Elements are trilinear ("linearly deformed", Sec. 5.1).
+ *              Elements are trilinear: linearly deformed hexahedra (Sec. 5.1).
  *   glob_id    HOST int64 [E][P3]: global point of every local point (this is
  *              Q).  Ids are >= 0; points with equal id are summed by the
  *              gather-scatter.  Every id in [0, max id] need not be used.
@@ -122,8 +122,8 @@ sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);
  * for every element e).  prec: SEM_FP32 or SEM_FP64 (buffers of that type).
  * geom: SEM_G_PRECOMPUTED reads the G array of that precision (it must have
  * been requested at mesh creation, else SEM_EUNSUPPORTED); SEM_G_ON_THE_FLY
- * recomputes G at every point from the 8 vertices ("rematerialization",
- * Sec. 5.1).  u and w must not overlap.
+ * recomputes G at every point from the 8 vertices (the paper's
+ * rematerialization, Sec. 5.1).  u and w must not overlap.
  */
 sem_status sem_ax(sem_mesh_t mesh, sem_precision prec, sem_geom geom,
                   const void *u_dev, void *w_dev, void *hip_stream);

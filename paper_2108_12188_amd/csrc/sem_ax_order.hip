@@ -4,7 +4,7 @@
 // paper (w_e = D^T G^e D u_e, per element, no gather-scatter) in two forms:
 //   * precomputed G: the six symmetric factors are streamed from HBM
 //     (Sec. 4.2: 6 words per point, the HBM-bound form);
-//   * on-the-fly G ("rematerialization", Sec. 5.1, Eq. 13-14): G is rebuilt
+//   * on-the-fly G (rematerialization, Sec. 5.1, Eq. 13-14): G is rebuilt
 //     at every point from the element's 8 vertices, so only u and w move.
 // and two modes:
 //   * Plain: w = A_L u;
