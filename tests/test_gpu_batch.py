@@ -119,8 +119,13 @@ def test_batch_errors():
     boxes, gms = _meshes(sem)
     with pytest.raises(sem.SemError):
         sem.Batch([gms[0], gms[0]])
+    with pytest.raises(sem.SemError) as ei:
+        sem.Batch([])
+    assert ei.value.code == -1
     batch = sem.Batch(gms[:2])
     bs = [torch.zeros(g.n, dtype=torch.float64, device="cuda") for g in gms[:2]]
+    with pytest.raises(ValueError):
+        batch.solve(bs[:1], prec=sem.FP32, tol=1e-8)
     with pytest.raises(sem.SemError) as ei:
         batch.solve(bs, prec=sem.FP64, tol=1e-8)
     assert ei.value.code == -6

@@ -115,6 +115,33 @@ def test_cg_zero_rhs_and_nonzero_guess():
     gm.close()
 
 
+@pytest.mark.parametrize("table_free", [False, True], ids=["table", "table_free"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,shape,copies", [(2, (1, 1, 1), 1), (1, (2, 2, 2), 8)],
+                         ids=["centre", "corner8"])
+def test_cg_single_unknown(N, shape, copies, prec, table_free):
+    """Meshes with one unknown: the centre of one N = 2 element (no shared
+    point), and at N = 1 the middle vertex of a 2x2x2 box, shared by all
+    eight elements.  CG (Algorithm 1) reaches the solution in one step."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say(f"cg single unknown N={N} {shape} {prec} table_free={table_free}")
+    mesh = box_mesh(*shape, N, perturb=0.1, seed=4)
+    pr = oracle.Problem(mesh)
+    gm = sem.Mesh.from_box(mesh, g_fp64=(prec == "fp64"), table_free=table_free)
+    bh = random_global_rhs(mesh, seed=5)
+    assert np.count_nonzero(bh) == copies
+    fp64 = prec == "fp64"
+    dt = torch.float64 if fp64 else torch.float32
+    x, res = gm.cg_solve(to_dev(bh, dt), prec=sem.FP64 if fp64 else sem.FP32,
+                         tol=1e-12 if fp64 else 1e-5, max_iter=50)
+    assert res["converged"] == 1 and res["iters"] == 1
+    xo, _, _ = pr.cg(bh, tol=1e-14, max_iter=50)
+    assert np.count_nonzero(xo) == copies
+    assert rel_norm(to_host(x), xo) < (1e-13 if fp64 else 1e-6)
+    gm.close()
+
+
 def test_cg_max_iter_cap():
     import torch
     import paper_2108_12188_amd as sem

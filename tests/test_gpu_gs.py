@@ -131,6 +131,10 @@ def test_mesh_errors():
     assert ei.value.code == -1
     with pytest.raises(ValueError):
         sem.Mesh(mesh.vert, mesh.glob_id, mesh.dirichlet, 4)
+    # an empty mesh passes the shape check and is refused by the library
+    with pytest.raises(sem.SemError) as ei:
+        sem.Mesh(np.zeros((0, 8, 3)), np.zeros((0, 64), np.int64), None, 3)
+    assert ei.value.code == -1 and "n_elem" in str(ei.value)
     big = box_mesh(1, 1, 1, 12)
     with pytest.raises(sem.SemError) as ei:
         sem.Mesh.from_box(big)
