@@ -154,6 +154,95 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
+def bench_references() -> dict:
+    """FP64 oracle values for the large workloads, written by
+    tests/golden/make_bench_references.py (empty if absent)."""
+    p = os.path.join(ROOT, "tests", "golden", "bench_references.json")
+    try:
+        with open(p) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def fp64_latency(geom, solves=50):
+    """Plain FP64 CG on 4^3 affine hexahedra, N = 7, manufactured forcing,
+    tol 1e-8: p50/p99 over `solves` solves and time per iteration."""
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import box_mesh
+    gm = sem.Mesh.from_box(box_mesh(4, 4, 4, 7), g_fp32=False, g_fp64=True)
+    xyz = gm.coords()
+    b = gm.rhs(_forcing(xyz), prec=sem.FP64)
+    for _ in range(5):
+        gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8)
+    torch.cuda.synchronize()
+    times, res = [], None
+    for _ in range(solves):
+        t0 = time.perf_counter()
+        _, res = gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8)
+        times.append(time.perf_counter() - t0)
+    x, rt = gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8, true_residual=True)
+    err = float((x - _exact(xyz)).abs().max())
+    gm.close()
+    p50 = _pct(times, 50)
+    return {"p50_ms": p50 * 1e3, "p99_ms": _pct(times, 99) * 1e3, "solves": solves,
+            "iters": res["iters"], "us_per_iter": p50 / res["iters"] * 1e6,
+            "rel_res_true": rt["rel_res_true"], "max_err_vs_exact_u": err}
+
+
+def mixed_vs_fp64(ref=None):
+    """24^3 deformed hexahedra, N = 9, manufactured forcing: mixed precision
+    (FP32 inner CG with G on the fly, FP64 outer residual) against plain FP64
+    CG (precomputed FP64 G), both to a true relative residual of 1e-10.  With
+    `ref` (the oracle's FP64 solution to 1e-12 at sampled points) the
+    sampled error of both solutions against it."""
+    import numpy as np
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, box_mesh
+    mesh = box_mesh(24, 24, 24, 9, perturb=0.1, seed=MESH_SEED_BASE + 3)
+    gm = sem.Mesh.from_box(mesh, g_fp32=False, g_fp64=True)
+    n = mesh.n_local
+    xyz = gm.coords()
+    b = gm.rhs(_forcing(xyz), prec=sem.FP64)
+    u = _exact(xyz)
+    del xyz
+    idx = None
+    if ref:
+        idx = torch.as_tensor(np.asarray(ref["sample_index"], dtype=np.int64), device="cuda")
+        xs = np.asarray(ref["sample_x"])
+    out = {}
+    for label, prec, geom in (("mixed", sem.MIXED, sem.ON_THE_FLY),
+                              ("fp64", sem.FP64, sem.PRECOMPUTED)):
+        gm.cg_solve(b, prec=prec, geom=geom, tol=1e-3, max_iter=50)      # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, r = gm.cg_solve(b, prec=prec, geom=geom, tol=1e-10, max_iter=100000,
+                           true_residual=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        row = {"seconds": dt, "iters": r["iters"], "outer": r["outer"],
+               "rel_res_true": r["rel_res_true"], "converged": r["converged"],
+               "gdof_iter_per_s": n * r["iters"] / dt / 1e9,
+               "max_err_vs_exact_u": float((x - u).abs().max())}
+        if idx is not None:
+            got = x[idx].cpu().numpy()
+            row["sampled_max_rel_err_vs_oracle_xstar"] = float(
+                np.max(np.abs(got - xs)) / np.max(np.abs(xs)))
+        out[label] = row
+        del x
+    gm.close()
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    if ref:
+        out["oracle_xstar"] = {"tol": ref["tol"], "iterations": ref["iterations"],
+                               "samples": len(ref["sample_index"]),
+                               "source": "tests/golden/bench_references.json"}
+    return out
+
+
 def time_ax(gm, u, geom, reps=50):
     """Median duration (ms) of one sem_ax launch on torch's current stream."""
     import torch
@@ -186,7 +275,7 @@ def main(argv=None):
                          "workloads (FP64 latency, mixed vs FP64, batched, serving); "
                          "6: Jacobi-preconditioned CG against plain CG; 7: FP32 CG "
                          "throughput against the element count")
-    ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
     ap.add_argument("--no-tune", action="store_true", help="ignore the tuned tile shapes")
@@ -255,11 +344,17 @@ def main(argv=None):
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
     t0 = time.perf_counter()
-    res = None
+    res, timed = None, []
     for _ in range(args.steps):
         _, res = step()
+        timed.append(res)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # every timed solve must have run all its iterations (status 2: the
+    # fixed count was reached; a breakdown, status 3, would stop early)
+    for r in timed:
+        if r["iters"] != iters or r["status"] != 2:
+            raise RuntimeError(f"a timed solve stopped early: {r}")
     ms_per_step = 1000.0 * dt / args.steps
     value = n * iters / (dt / args.steps) / 1e9
     log(f"bench: {ms_per_step:.2f} ms/step, {value:.2f} GDOF*iter/s")
@@ -293,12 +388,31 @@ def main(argv=None):
         roof["mfma_frac"] = roof["mfma_tflops"] / FP32_PEAK_TFLOPS
     roof["avg_ms"] = ax_ms
     roof["traffic"] = read_traffic(f"cg_fused_{args.geom}_N{N}", n)
+    roof["traffic_source"] = (
+        "profiles/ax_counters.json: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, of this "
+        "workload on the same kernel source (hash-checked), calibrated against a 256 MiB "
+        "copy; not measured in this run" if roof["traffic"] is not None else
+        "none recorded for the current kernel source")
 
     info = gm.info()
     extra = {"gather_form": "table-free" if info["gs_table_free"] else
              ("per-point table" if info["gs_in_update"] else "gather-scatter pass"),
              "kernel_ms": km, "iteration_ms": sum(km.values()),
+             "timed_solves": {"count": len(timed), "iterations_each": iters,
+                              "status_each": sorted({r["status"] for r in timed})},
              "rel_res_recursive": res["rel_res_recursive"] if res else None}
+    # the FP64 true residual of the FP32 iterate after the 500 iterations,
+    # beside the FP64 oracle's after the same iterations (committed
+    # reference values written by tests/golden/make_bench_references.py)
+    x.zero_()
+    _, rt = gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=iters, true_residual=True)
+    extra["rel_res_true_fp64"] = rt["rel_res_true"]
+    refs = bench_references()
+    hl = refs.get("headline") if (nel, N, iters) == (32, 7, 500) else None
+    if hl:
+        extra["oracle_fp64_after_same_iterations"] = {
+            "rel_res_true": hl["rel_res_true"], "rel_res_recursive": hl["rel_res_recursive"],
+            "source": "tests/golden/bench_references.json (FP64 oracle, 500 iterations)"}
     if not args.no_extras:
         u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n).astype(np.float32),
                             device="cuda")
@@ -341,6 +455,10 @@ def main(argv=None):
         torch.cuda.synchronize()
         extra["cg_fp64_pre_gdof"] = n * it64 / (time.perf_counter() - t1) / 1e9
         gm64.close()
+        del b64, x64
+        log("bench: FP64 latency (4^3 N=7) and mixed vs FP64 to 1e-10 (24^3 N=9)")
+        extra["fp64_latency_4cube_N7"] = fp64_latency(geom)
+        extra["mixed_vs_fp64_24cube_N9"] = mixed_vs_fp64(refs.get("mixed_24_N9"))
     extra["mesh"] = gm.info()
 
     cpu = None
@@ -426,9 +544,9 @@ def run_config1(args):
     x, res_t = gm.cg_solve(b, prec=sem.FP64, geom=geom, tol=1e-8, true_residual=True)
     err = float((x - _exact(xyz)).abs().max())
     pr = oracle.Problem(mesh)
-    bh = b.cpu().numpy()
+    bo, _ = pr.rhs_manufactured()       # the oracle's own right-hand side
     t0 = time.perf_counter()
-    xo, it_o, _ = pr.cg(bh, tol=1e-8, max_iter=5000, history=False)
+    xo, it_o, _ = pr.cg(bo, tol=1e-8, max_iter=5000, history=False)
     t_cpu = time.perf_counter() - t0
     xd = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
     p50 = _pct(times, 50)
@@ -545,11 +663,77 @@ def run_config4(args):
                   "config": {"workload": "64 problems 8^3..20^3, N in {5,7,9}, mixed to 1e-8"}})
 
 
+class _Fp64Engine:
+    """Plain FP64 CG serving for comparison: the admitted requests are solved
+    one at a time, in admission order, each with sem_cg_solve(FP64) to the
+    same tolerance (no batching, no mixed precision).  Same interface as
+    serve.GpuEngine."""
+
+    def __init__(self, make_problem, tol, geom, prep_workers=4):
+        import concurrent.futures as cf
+
+        import torch
+
+        import paper_2108_12188_amd as sem
+        self.sem, self.torch = sem, torch
+        self.make_problem, self.tol, self.geom = make_problem, tol, geom
+        self.pool = cf.ThreadPoolExecutor(max_workers=prep_workers)
+        self.preparing, self.order = {}, []
+        self.t0 = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(dt)
+
+    def footprint(self, r):
+        n = r.n_elem * (r.order + 1) ** 3
+        return self.sem.mesh_footprint(r.n_elem, r.order, g_fp32=False, g_fp64=True,
+                                       prec=self.sem.FP64) + 64 * n
+
+    def _prepare(self, r):
+        sem = self.sem
+        vert, gid, dirichlet, N, forcing = self.make_problem(r)
+        mesh = sem.Mesh(vert, gid, dirichlet, N, g_fp32=False,
+                        g_fp64=self.geom == sem.PRECOMPUTED)
+        b = mesh.rhs(forcing(mesh.coords()).contiguous(), prec=sem.FP64)
+        self.torch.cuda.current_stream().synchronize()
+        return mesh, b
+
+    def admit(self, r):
+        self.preparing[r.tag] = self.pool.submit(self._prepare, r)
+        self.order.append(r.tag)
+
+    def step(self):
+        if not self.order:
+            return []
+        tag = self.order.pop(0)
+        mesh, b = self.preparing.pop(tag).result()
+        _, res = mesh.cg_solve(b, prec=self.sem.FP64, geom=self.geom, tol=self.tol,
+                               max_iter=100000, true_residual=True)
+        mesh.close()
+        return [(tag, res)]
+
+    def release(self, tag):
+        pass
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+
 def run_config5(args):
     """Serving: seeded Poisson arrivals of solve requests (4^3..24^3 deformed
     hexahedra, N in {5, 7, 9}, mixed precision to 1e-8); continuous batching
-    with admission by device-memory footprint; latency p50/p99 and solves/s."""
-    import numpy as np
+    with admission by device-memory footprint; latency p50/p99 and solves/s.
+
+    The arrival rate defaults to 0.8 x the measured batched capacity: the
+    first 64 requests of the stream, prepared in advance and solved as one
+    batch (mixed, to 1e-8), give solves/s.  The same stream is then served
+    at that rate and at 0.5 x the capacity, and once more at 0.8 x by plain
+    FP64 CG (one solve at a time, same tolerance) for comparison."""
     import torch
 
     import paper_2108_12188_amd as sem
@@ -557,32 +741,80 @@ def run_config5(args):
     from seminputs import MESH_SEED_BASE, arrival_times, batch_problems, box_mesh
     geom = sem.PRECOMPUTED if args.geom == "pre" else sem.ON_THE_FLY
     specs = batch_problems(args.requests, seed=MESH_SEED_BASE + 5, e_lo=4 ** 3, e_hi=24 ** 3)
-    rate = args.rate if args.rate > 0 else 20.0
-    arr = arrival_times(len(specs), rate, seed=MESH_SEED_BASE + 50)
-    reqs = [Request(tag=q, arrival=float(arr[q]), n_elem=sp["nx"] * sp["ny"] * sp["nz"],
-                    order=sp["N"], payload=sp) for q, sp in enumerate(specs)]
 
     def make_problem(r):
         sp = r.payload
         bx = box_mesh(sp["nx"], sp["ny"], sp["nz"], sp["N"], perturb=0.1, seed=sp["seed"])
         return bx.vert, bx.glob_id, bx.dirichlet, sp["N"], _forcing
 
-    free, total = torch.cuda.mem_get_info()
-    eng = GpuEngine(make_problem, tol=1e-8, geom=geom, round_iters=16, prep_workers=4)
-    sch = Scheduler(eng, budget_bytes=int(0.8 * free), max_slots=64)
-    out = sch.run(reqs)
-    eng.close()
-    st = summarize(out)
+    # batched capacity on a sample of the stream
+    k = min(64, len(specs))
+    log(f"bench5: capacity from a batch of the first {k} requests")
+    meshes = []
+    for sp in specs[:k]:
+        bx = box_mesh(sp["nx"], sp["ny"], sp["nz"], sp["N"], perturb=0.1, seed=sp["seed"])
+        meshes.append(sem.Mesh.from_box(bx, g_fp32=geom == sem.PRECOMPUTED))
+    bs = [m.rhs(_forcing(m.coords()), prec=sem.FP64) for m in meshes]
+    batch = sem.Batch(meshes)
+    batch.solve(bs, prec=sem.MIXED, geom=geom, tol=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, bres = batch.solve(bs, prec=sem.MIXED, geom=geom, tol=1e-8)
+    torch.cuda.synchronize()
+    capacity = k / (time.perf_counter() - t0)
+    batch.close()
+    for m in meshes:
+        m.close()
+    del bs, meshes
+    log(f"bench5: batched capacity {capacity:.1f} solves/s")
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    rate_main = args.rate if args.rate > 0 else 0.8 * capacity
+    runs = {}
+
+    def serve(label, rate, fp64=False):
+        arr = arrival_times(len(specs), rate, seed=MESH_SEED_BASE + 50)
+        reqs = [Request(tag=q, arrival=float(arr[q]), n_elem=sp["nx"] * sp["ny"] * sp["nz"],
+                        order=sp["N"], payload=sp) for q, sp in enumerate(specs)]
+        log(f"bench5: {label}: {len(reqs)} requests at {rate:.1f}/s")
+        if fp64:
+            eng = _Fp64Engine(make_problem, 1e-8, geom, prep_workers=8)
+        else:
+            eng = GpuEngine(make_problem, tol=1e-8, geom=geom, round_iters=16, prep_workers=8)
+        sch = Scheduler(eng, budget_bytes=budget, max_slots=64)
+        out = sch.run(reqs)
+        eng.close()
+        st = summarize(out)
+        st.update({"arrival_rate_per_s": rate, "peak_admitted_bytes": sch.peak_used,
+                   "max_rel_res_true": max((r.result or {}).get("rel_res_true", 0.0)
+                                           for r in out),
+                   "not_converged": [r.tag for r in out if r.status != "done"]})
+        if not fp64:
+            st["peak_measured_bytes"] = eng.peak_measured_bytes
+        log(f"bench5: {label}: p50 {st['p50_s']:.3f} s, p99 {st['p99_s']:.3f} s, "
+            f"{st['solves_per_s']:.1f} solves/s")
+        runs[label] = st
+        return st
+
+    main_run = serve("mixed_0.8x", rate_main)
+    if args.rate <= 0:
+        serve("mixed_0.5x", 0.5 * capacity)
+    serve("fp64_0.8x", rate_main, fp64=True)
     return _emit({"metric": "serving: solve latency p50 (arrival to result)",
-                  "value": st["p50_s"], "unit": "s", "higher_is_better": False,
-                  "p50_s": st["p50_s"], "p99_s": st["p99_s"], "solves_per_s": st["solves_per_s"],
-                  "summary": st, "arrival_rate_per_s": rate, "peak_admitted_bytes": sch.peak_used,
-                  "not_converged": [(r.tag, r.status, r.result) for r in out
-                                    if r.status != "done"],
-                  "budget_bytes": sch.budget, "geom": args.geom, "dtype": "f32+f64",
+                  "value": main_run["p50_s"], "unit": "s", "higher_is_better": False,
+                  "p50_s": main_run["p50_s"], "p99_s": main_run["p99_s"],
+                  "solves_per_s": main_run["solves_per_s"],
+                  "batched_capacity_solves_per_s": capacity,
+                  "capacity_sample": f"first {k} requests solved as one batch (mixed, 1e-8), "
+                                     f"all converged: {all(r['converged'] for r in bres)}",
+                  "arrival_rate_per_s": rate_main, "runs": runs,
+                  "budget_bytes": budget, "geom": args.geom, "dtype": "f32+f64",
                   "data": "synthetic",
-                  "config": {"workload": f"{len(reqs)} requests, 4^3..24^3, N in {{5,7,9}}, "
-                                         f"mixed to 1e-8, Poisson arrivals {rate}/s"}})
+                  "config": {"workload": f"{len(specs)} requests, 4^3..24^3, N in {{5,7,9}}, "
+                                         f"mixed to 1e-8, Poisson arrivals at "
+                                         f"{rate_main:.1f}/s (plain FP64 CG serving of the same "
+                                         f"stream for comparison)"}})
 
 
 def run_config6(args):

@@ -261,7 +261,9 @@ sem_status sem_batch_solve(sem_batch_t batch, const sem_cg_opts *opts,
  * round).  A request's result is bitwise that of its own sem_cg_solve.
  * sem_server_add: b_dev / x_dev are DEVICE double [n_local] of the mesh and
  * must stay valid until the request is reported done; x holds the initial
- * guess.  One request per mesh at a time.
+ * guess.  hip_stream is the stream that produced b and x: the server's own
+ * stream waits for the work enqueued on it so far before reading them (the
+ * call itself does not block).  One request per mesh at a time.
  * sem_server_step: runs one round on the server's own stream, blocks until
  * it is done, writes up to cap finished requests (their tags and results;
  * their x is final), and the number of requests still held.
@@ -270,7 +272,7 @@ typedef struct sem_server_s *sem_server_t;
 sem_status sem_server_create(const sem_cg_opts *opts, int round_iters, sem_server_t *out);
 void sem_server_destroy(sem_server_t server);
 sem_status sem_server_add(sem_server_t server, sem_mesh_t mesh, const void *b_dev, void *x_dev,
-                          int64_t tag);
+                          int64_t tag, void *hip_stream);
 sem_status sem_server_step(sem_server_t server, int64_t *done_tags, sem_cg_result *done_results,
                            int cap, int *n_done, int *n_active);
 

@@ -99,7 +99,7 @@ def lib():
     L.sem_server_create.argtypes = [C.POINTER(CgOpts), i32, C.POINTER(vp)]
     L.sem_server_destroy.argtypes = [vp]
     L.sem_server_destroy.restype = None
-    L.sem_server_add.argtypes = [vp, vp, vp, vp, i64]
+    L.sem_server_add.argtypes = [vp, vp, vp, vp, i64, vp]
     L.sem_server_step.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.sem_mesh_footprint.argtypes = [i64, i32, u32, i32, C.POINTER(C.c_size_t)]
     L.sem_ax_shape_set.argtypes = [i32, i32, i32, i32]
@@ -406,11 +406,13 @@ class Server:
         self._h = h
         self._held = {}
 
-    def add(self, mesh: "Mesh", b, x, tag: int):
+    def add(self, mesh: "Mesh", b, x, tag: int, stream=None):
+        """Queue a request; the server reads b and x after the work already
+        enqueued on `stream` (default: the current stream) has finished."""
         _dev_vec(b, mesh.n, "b")
         _dev_vec(x, mesh.n, "x")
         _check(lib().sem_server_add(self._h, mesh.handle, C.c_void_p(b.data_ptr()),
-                                    C.c_void_p(x.data_ptr()), tag))
+                                    C.c_void_p(x.data_ptr()), tag, _stream(stream)))
         self._held[tag] = (mesh, b, x)
 
     def step(self, cap: int = 256):

@@ -48,7 +48,8 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
 struct ServerImpl;
 ServerImpl *server_new(const sem_cg_opts &o, int round_iters);
 void server_delete(ServerImpl *sv);
-void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag);
+void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag,
+                hipStream_t user_s);
 int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, int *n_done);
 size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec);
 size_t workspace_bytes(const Mesh &m);
@@ -337,13 +338,13 @@ void sem_server_destroy(sem_server_t server) {
 }
 
 sem_status sem_server_add(sem_server_t server, sem_mesh_t mesh, const void *b_dev, void *x_dev,
-                          int64_t tag) {
+                          int64_t tag, void *hip_stream) {
     return guarded([&]() -> sem_status {
         need(server, "server");
         Mesh *m = as_mesh(mesh);
         DeviceGuard dg(m->device);
         server_add(*reinterpret_cast<ServerImpl *>(server), m, static_cast<const double *>(b_dev),
-                   static_cast<double *>(x_dev), tag);
+                   static_cast<double *>(x_dev), tag, static_cast<hipStream_t>(hip_stream));
         return SEM_OK;
     });
 }

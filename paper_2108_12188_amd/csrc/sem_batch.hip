@@ -750,7 +750,8 @@ ServerImpl *server_new(const sem_cg_opts &o, int round_iters) {
 
 void server_delete(ServerImpl *sv) { delete sv; }
 
-void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag) {
+void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag,
+                hipStream_t user_s) {
     if (!b || !x) fail(SEM_EINVAL, "b and x must not be NULL");
     for (const ServerReq &r : sv.reqs)
         if (r.m == m) fail(SEM_EINVAL, "the mesh already has a request in the server");
@@ -758,6 +759,10 @@ void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag
     if (sv.o.geom == SEM_G_PRECOMPUTED && !m->G32)
         fail(SEM_EUNSUPPORTED, "precomputed FP32 G was not built for the mesh");
     hipStream_t s = sv.batch.stream;
+    // b and x may still be in flight on the caller's stream: the server's
+    // stream waits for everything enqueued there so far.
+    SEM_HIP(hipEventRecord(sv.batch.ev, user_s));
+    SEM_HIP(hipStreamWaitEvent(s, sv.batch.ev, 0));
     Workspace &w64 = cg_workspace(*m, true);
     (void)cg_workspace(*m, false);
     double *x64 = static_cast<double *>(w64.x);

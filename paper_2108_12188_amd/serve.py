@@ -152,6 +152,9 @@ class GpuEngine:
         self.held: dict[int, tuple] = {}
         self.keep_results = keep_results
         self.results: dict[int, object] = {}
+        self.peak_measured_bytes = 0
+        self._kept_bytes = 0        # results of released requests kept for the caller
+        self._alloc0 = torch.cuda.memory_allocated()
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -162,8 +165,25 @@ class GpuEngine:
         if dt > 0:
             time.sleep(dt)
 
+    # Device bytes per local point a request holds beyond its mesh handle
+    # and solver work vectors: its FP64 right-hand side and solution (16),
+    # and while it is prepared the point coordinates [3][n] (24), the
+    # forcing (8) and at most two temporaries of the forcing expression (16).
+    CALLER_BYTES_PER_POINT = 16 + 24 + 8 + 16
+
     def footprint(self, r: Request) -> int:
-        return self._fp(r.n_elem, r.order, g_fp32=self.g_fp32, prec=self._mixed)
+        n = r.n_elem * (r.order + 1) ** 3
+        return self._fp(r.n_elem, r.order, g_fp32=self.g_fp32, prec=self._mixed) \
+            + self.CALLER_BYTES_PER_POINT * n
+
+    def _measure(self):
+        """Device bytes held right now by the admitted requests: their mesh
+        handles (as the library reports them) plus the tensors this engine
+        allocated since it was created."""
+        torch = self._torch
+        held = sum(m.info()["device_bytes"] for m, _, _ in self.held.values())
+        tensors = max(0, torch.cuda.memory_allocated() - self._alloc0 - self._kept_bytes)
+        self.peak_measured_bytes = max(self.peak_measured_bytes, held + tensors)
 
     def _prepare(self, r: Request):
         torch = self._torch
@@ -193,6 +213,7 @@ class GpuEngine:
         self._add_ready(block=not self.held)
         if not self.held:
             return []
+        self._measure()
         done, _ = self.server.step()
         return done
 
@@ -200,6 +221,7 @@ class GpuEngine:
         mesh, b, x = self.held.pop(tag)
         if self.keep_results:
             self.results[tag] = x
+            self._kept_bytes += x.numel() * x.element_size()
         mesh.close()
 
     def close(self):

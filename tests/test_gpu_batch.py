@@ -79,7 +79,9 @@ def test_batch_fp32_tolerance_equals_solo_and_oracle():
     import torch
     import paper_2108_12188_amd as sem
     boxes, gms = _meshes(sem)
-    bs = [to_dev(random_global_rhs(b, seed=3 + q), torch.float32) for q, b in enumerate(boxes)]
+    bh = [random_global_rhs(b, seed=3 + q).astype(np.float32).astype(np.float64)
+          for q, b in enumerate(boxes)]
+    bs = [to_dev(v, torch.float32) for v in bh]
     batch = sem.Batch(gms)
     xs, res = batch.solve(bs, prec=sem.FP32, tol=1e-5, max_iter=5000)
     for q, gm in enumerate(gms):
@@ -88,7 +90,7 @@ def test_batch_fp32_tolerance_equals_solo_and_oracle():
         assert torch.equal(xs[q], xq)
     # one problem against the oracle's converged solution
     pr = oracle.Problem(boxes[1])
-    xo, _, _ = pr.cg(to_host(bs[1]), tol=1e-12, max_iter=20000)
+    xo, _, _ = pr.cg(bh[1], tol=1e-12, max_iter=20000)
     assert rel_norm(to_host(xs[1]), xo) < 1e-4
     batch.close()
 

@@ -34,24 +34,28 @@ def test_cg_fp64_small_box_matches_oracle(graph):
     bh = to_host(b)
     bref, u_exact = pr.rhs_manufactured()
     assert rel_norm(bh, bref) < 1e-14
-    xo, it_o, hist = pr.cg(bh, tol=1e-8, max_iter=2000)
+    xo, it_o, hist = pr.cg(bref, tol=1e-8, max_iter=2000)
     x, res = gm.cg_solve(b, prec=sem.FP64, tol=1e-8, max_iter=2000, use_graph=graph,
                          true_residual=True, history=60)
     assert res["converged"] == 1
     assert abs(res["iters"] - it_o) <= 2
-    # CG amplifies rounding differences as it converges: the oracle itself,
-    # with D perturbed by 1e-16, keeps rho_i to ~1e-15 for i <= 25 and then
-    # drifts by up to 5% (of a rho_i that is 1e-7 rho_0 by then).  So the
-    # first 20 iterations must agree tightly, the rest in absolute terms.
+    # CG amplifies rounding differences as it converges.  On this problem
+    # the oracle against itself, with every entry of D moved by one ulp,
+    # keeps rho_i to ~1e-14 relative up to i = 25, then drifts by up to ~20%
+    # of rho_i near i = 38 (where rho_i ~ 1e-7 rho_0), i.e. by up to
+    # ~1.3e-8 rho_0, while its solution moves by ~2.5e-12
+    # (tests/test_oracle_cg.py::test_cg_history_drift_under_one_ulp_of_D).
+    # So the first 20 iterations must agree tightly, the rest within twice
+    # that drift in absolute terms, and the solution tightly.
     rg, ro = res["hist_rho"], hist["rho"]
     np.testing.assert_allclose(rg[:21], ro[:21], rtol=1e-10)
     np.testing.assert_allclose(res["hist_alpha"][1:21], hist["alpha"][1:21], rtol=1e-10)
     k = min(len(rg), len(ro))
-    assert np.max(np.abs(rg[:k] - ro[:k])) <= 1e-8 * ro[0]
+    assert np.max(np.abs(rg[:k] - ro[:k])) <= 2e-8 * ro[0]
     xg = to_host(x)
-    assert rel_norm(xg, xo) < 1e-6
+    assert rel_norm(xg, xo) < 1e-10
     assert res["rel_res_true"] < 1.1e-8
-    assert pr.true_rel_residual(bh, xg) < 1.1e-8
+    assert pr.true_rel_residual(bref, xg) < 1.1e-8
     assert np.max(np.abs(xg - u_exact)) < 1e-5
     gm.close()
 
@@ -176,12 +180,12 @@ def test_mixed_precision_reaches_1e10(geom):
     pr = oracle.Problem(mesh)
     gm = sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=False)
     b = _manufactured(gm, pr, sem.FP64)
-    bh = to_host(b)
+    bref, _ = pr.rhs_manufactured()         # the oracle's own right-hand side
     x, res = gm.cg_solve(b, prec=sem.MIXED, geom=geom, tol=1e-10, inner_tol=1e-5)
     assert res["converged"] == 1 and res["outer"] >= 2
     xh = to_host(x)
-    assert pr.true_rel_residual(bh, xh) < 1.2e-10
-    xs, _, _ = pr.cg(bh, tol=1e-12, max_iter=20000)
+    assert pr.true_rel_residual(bref, xh) < 1.2e-10
+    xs, _, _ = pr.cg(bref, tol=1e-12, max_iter=20000)
     assert rel_norm(xh, xs) < 1e-8
     gm.close()
 
