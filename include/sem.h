@@ -147,6 +147,20 @@ sem_status sem_dot(sem_mesh_t mesh, sem_precision prec, const void *a_dev,
                    const void *b_dev, double *out_dev, void *hip_stream);
 
 /*
+ * sem_dot without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and result as
+ * sem_dot (bitwise).  Its block partials live in a static device array of
+ * the library, 4096 doubles (32 KiB) per GPU, held until the process ends;
+ * the partial count is min(ceil(n_local / 1024), 4096), so every mesh fits,
+ * and a larger count would return SEM_EINVAL.  The call makes no hipMalloc
+ * or hipFree (its first call on a device looks the array's address up).
+ * Calls that overlap on one GPU share the array and race: serialise them.
+ */
+sem_status sem_dot_noalloc(sem_mesh_t mesh, sem_precision prec, const void *a_dev,
+                           const void *b_dev, double *out_dev, void *hip_stream);
+
+/*
  * Diagonal of the assembled operator A = Q^T A_L Q (Eq. 4) in local form
  * (unmasked): the element diagonals (A_L)_qq = sum_{a,b} sum_q' (D_a)_{q'q}
  * G_ab(q') (D_b)_{q'q}, formed in FP64 from the vertices whatever G form the

@@ -60,7 +60,7 @@ class MeshInfo(C.Structure):
 
 _lib = None
 EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "sem_gs",
-           "sem_dot", "sem_diag", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
+           "sem_dot", "sem_dot_noalloc", "sem_diag", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
            "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
            "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_ax_shape_set",
            "sem_ax_shape_get", "sem_ax_engine_set", "sem_ax_engine_get", "sem_last_error",
@@ -88,6 +88,7 @@ def lib():
     L.sem_ax.argtypes = [vp, i32, i32, vp, vp, vp]
     L.sem_gs.argtypes = [vp, i32, vp, i32, vp]
     L.sem_dot.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.sem_dot_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
     L.sem_coords.argtypes = [vp, vp, vp]
     L.sem_diag.argtypes = [vp, vp, vp]
     L.sem_rhs.argtypes = [vp, i32, vp, vp, vp]
@@ -111,7 +112,7 @@ def lib():
     L.sem_last_error.argtypes = []
     L.sem_version.restype = C.c_char_p
     L.sem_version.argtypes = []
-    for name in ("sem_mesh_create", "sem_mesh_info", "sem_ax", "sem_gs", "sem_dot",
+    for name in ("sem_mesh_create", "sem_mesh_info", "sem_ax", "sem_gs", "sem_dot", "sem_dot_noalloc",
                  "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve",
                  "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint",
                  "sem_ax_shape_set", "sem_ax_shape_get", "sem_ax_engine_set",
@@ -234,6 +235,14 @@ class Mesh:
                              _dev_vec(b, self.n, "b"), C.c_void_p(o.data_ptr()),
                              _stream(stream)))
         return o if out is not None else float(o.item())
+
+    def dot_noalloc(self, a, b, out, stream=None):
+        """<a, b, c> into the one-element float64 device tensor `out`
+        without any device allocation by the library (sem_dot_noalloc)."""
+        _check(lib().sem_dot_noalloc(self.handle, _prec_of(a), _dev_vec(a, self.n, "a"),
+                                     _dev_vec(b, self.n, "b"), _dev_vec(out, 1, "out"),
+                                     _stream(stream)))
+        return out
 
     def diag(self, stream=None):
         """Diagonal of the assembled operator in local form (float64 device

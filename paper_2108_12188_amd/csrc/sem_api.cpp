@@ -205,6 +205,26 @@ sem_status sem_dot(sem_mesh_t mesh, sem_precision prec, const void *a_dev, const
     });
 }
 
+sem_status sem_dot_noalloc(sem_mesh_t mesh, sem_precision prec, const void *a_dev,
+                           const void *b_dev, double *out_dev, void *hip_stream) {
+    return guarded([&]() -> sem_status {
+        Mesh *m = as_mesh(mesh);
+        need(a_dev, "a_dev");
+        need(b_dev, "b_dev");
+        need(out_dev, "out_dev");
+        check_prec(prec);
+        DeviceGuard dg(m->device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (prec == SEM_FP32)
+            launch_dot_noalloc<float>(*m, static_cast<const float *>(a_dev),
+                                      static_cast<const float *>(b_dev), out_dev, s);
+        else
+            launch_dot_noalloc<double>(*m, static_cast<const double *>(a_dev),
+                                       static_cast<const double *>(b_dev), out_dev, s);
+        return SEM_OK;
+    });
+}
+
 sem_status sem_diag(sem_mesh_t mesh, double *diag_dev, void *hip_stream) {
     return guarded([&]() -> sem_status {
         Mesh *m = as_mesh(mesh);

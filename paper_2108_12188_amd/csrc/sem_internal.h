@@ -379,6 +379,10 @@ void launch_diag_local(const Mesh &m, double *d, hipStream_t s);
 template <typename T>
 void launch_dot(const Mesh &m, const T *a, const T *b, double *out, double *partial,
                 hipStream_t s);
+// The same weighted inner product with its block partials in a file-scope
+// device array of the library (no device allocation; sem_dot_noalloc).
+template <typename T>
+void launch_dot_noalloc(const Mesh &m, const T *a, const T *b, double *out, hipStream_t s);
 // r = b - w and *out = <r, r, c>  (FP64 outer residual of the refinement)
 void launch_residual64(const Mesh &m, const double *b, const double *w, double *r, double *out,
                        double *partial, hipStream_t s);

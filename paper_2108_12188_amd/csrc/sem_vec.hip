@@ -5,6 +5,8 @@
 // <a, b, c>; the per-point code holds m_l and the Dirichlet flag.  The grid
 // size depends only on n, and the block partials are summed in index order
 // by the last block, so every result is bitwise reproducible.
+#include <mutex>
+
 #include "sem_vec_body.h"
 
 namespace sem {
@@ -354,6 +356,61 @@ template void launch_cg_init<float>(const Mesh &, const float *, const float *, 
                                     CgState *, double *, hipStream_t, PcArgs<float>);
 template void launch_cg_init<double>(const Mesh &, const double *, const double *, double *,
                                      double *, CgState *, double *, hipStream_t, PcArgs<double>);
+// ---------------------------------------------------------------------------
+// sem_dot_noalloc: the weighted inner product with its block partials in
+// `scratch`, a file-scope device array (one copy per GPU, held until the
+// process ends), so the call allocates nothing.  Every block writes its own
+// partial before the finalize kernel reads exactly those, so nothing needs
+// clearing between calls.  Calls that overlap on one GPU share the array and
+// race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocPartials = 4096;          // 32 KiB of FP64 partials
+static_assert(kVecMaxBlocks <= kNoAllocPartials,
+              "the no-allocation dot needs one scratch slot per vector block");
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of this GPU's copy of `scratch` (the array's name is only a
+// host-side stand-in); looked up once per device with that device current.
+double *noalloc_scratch() {
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        fail(SEM_EUNSUPPORTED, "device ordinal beyond the no-allocation table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) fail(SEM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+}  // namespace
+
+template <typename T>
+void launch_dot_noalloc(const Mesh &m, const T *a, const T *b, double *out, hipStream_t s) {
+    const int nb = vec_blocks(m.n);
+    if (nb > kNoAllocPartials)
+        fail(SEM_EINVAL, "sem_dot_noalloc: " + std::to_string(nb) +
+                             " block partials exceed the static scratch of " +
+                             std::to_string(kNoAllocPartials));
+    double *part = noalloc_scratch();
+    hipLaunchKernelGGL((dot_kernel<T>), dim3(nb), dim3(kVecThreads), 0, s, m.n, a, b, m.mcode,
+                       part);
+    hipLaunchKernelGGL(finalize_sum_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, out,
+                       (const double *)part, nb);
+    check_hip(hipGetLastError(), "dot kernel launch");
+}
+template void launch_dot_noalloc<float>(const Mesh &, const float *, const float *, double *,
+                                        hipStream_t);
+template void launch_dot_noalloc<double>(const Mesh &, const double *, const double *, double *,
+                                         hipStream_t);
+
 template void launch_dot<float>(const Mesh &, const float *, const float *, double *, double *,
                                 hipStream_t);
 template void launch_dot<double>(const Mesh &, const double *, const double *, double *,
