@@ -40,18 +40,18 @@ def test_cg_fp64_small_box_matches_oracle(graph):
     assert res["converged"] == 1
     assert abs(res["iters"] - it_o) <= 2
     # CG amplifies rounding differences as it converges.  On this problem
-    # the oracle against itself, with every entry of D moved by one ulp,
-    # keeps rho_i to ~1e-14 relative up to i = 25, then drifts by up to ~20%
-    # of rho_i near i = 38 (where rho_i ~ 1e-7 rho_0), i.e. by up to
-    # ~1.3e-8 rho_0, while its solution moves by ~2.5e-12
-    # (tests/test_oracle_cg.py::test_cg_history_drift_under_one_ulp_of_D).
-    # So the first 20 iterations must agree tightly, the rest within twice
-    # that drift in absolute terms, and the solution tightly.
+    # the oracle against itself, with D, G or b moved by one ulp, keeps rho_i
+    # to ~1e-14 relative up to i = 20, then drifts by up to ~20% of rho_i
+    # near i = 38 (where rho_i ~ 1e-8 max rho), i.e. by up to ~1.2e-9 of
+    # max_j rho_j, while its solution moves by ~5e-12
+    # (tests/test_oracle_cg.py::test_cg_history_drift_under_one_ulp_perturbations).
+    # So the first 20 iterations must agree tightly, the rest within about
+    # four times that drift in absolute terms, and the solution tightly.
     rg, ro = res["hist_rho"], hist["rho"]
     np.testing.assert_allclose(rg[:21], ro[:21], rtol=1e-10)
     np.testing.assert_allclose(res["hist_alpha"][1:21], hist["alpha"][1:21], rtol=1e-10)
     k = min(len(rg), len(ro))
-    assert np.max(np.abs(rg[:k] - ro[:k])) <= 2e-8 * ro[0]
+    assert np.max(np.abs(rg[:k] - ro[:k])) <= 5e-9 * np.max(ro)
     xg = to_host(x)
     assert rel_norm(xg, xo) < 1e-10
     assert res["rel_res_true"] < 1.1e-8
