@@ -270,11 +270,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--geom", choices=["pre", "otf"], default="otf",
                     help="geometric-factor form of the timed solver")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6, 7],
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6, 7, 8],
                     help="2: the headline FP32 CG throughput line; 1, 3, 4, 5: the other "
                          "workloads (FP64 latency, mixed vs FP64, batched, serving); "
                          "6: Jacobi-preconditioned CG against plain CG; 7: FP32 CG "
-                         "throughput against the element count")
+                         "throughput against the element count; 8: the headline CG on "
+                         "unstructured element numberings, reordered or not")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
@@ -782,7 +783,13 @@ def run_config5(args):
             eng = _Fp64Engine(make_problem, 1e-8, geom, prep_workers=8)
         else:
             eng = GpuEngine(make_problem, tol=1e-8, geom=geom, round_iters=16, prep_workers=8)
-        sch = Scheduler(eng, budget_bytes=budget, max_slots=64)
+        t_run = time.perf_counter()
+
+        def progress(k):
+            if k % 100 == 0:
+                log(f"bench5: {label}: {k} done after {time.perf_counter() - t_run:.1f} s")
+
+        sch = Scheduler(eng, budget_bytes=budget, max_slots=64, on_done=progress)
         out = sch.run(reqs)
         eng.close()
         st = summarize(out)
@@ -990,8 +997,86 @@ def run_config7(args):
                                          "+-10% deformed, random continuous RHS"}})
 
 
+def unstructured_rows(args, orders=("structured", "shuffled", "hilbert", "morton"),
+                      steps: int = 3):
+    """FP32 CG throughput of the headline workload on the same 32^3 N = 7
+    deformed box stored as an unstructured mesh would hold it: elements in a
+    seeded random order with each local frame rotated by one of the 24 cube
+    rotations ("shuffled"), then that mesh renumbered along a Hilbert or
+    Morton curve through the element centroids (sem_element_order), beside
+    the lexicographic box ("structured").  Same geometry and right-hand side
+    in every case (only the numbering differs)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, RHS_SEED, box_mesh, random_global_rhs
+    nel, N, iters = args.nel, args.order, args.iters
+    geom = sem.PRECOMPUTED if args.geom == "pre" else sem.ON_THE_FLY
+    rows = {}
+    for label in orders:
+        shuffled = label != "structured"
+        mesh = box_mesh(nel, nel, nel, N, perturb=0.1, seed=MESH_SEED_BASE + 2,
+                        permute=shuffled, reorient=shuffled)
+        bh = random_global_rhs(mesh, seed=RHS_SEED)
+        if label in ("hilbert", "morton"):
+            kind = sem.ORDER_HILBERT if label == "hilbert" else sem.ORDER_MORTON
+            t0 = time.perf_counter()
+            perm = sem.element_order(mesh.vert, kind)
+            t_order = time.perf_counter() - t0
+            v, gid, d, bh = sem.permute_elements(perm, mesh.vert, mesh.glob_id, mesh.dirichlet,
+                                                 bh)
+            mesh = dataclasses.replace(mesh, vert=v, glob_id=gid, dirichlet=d)
+        gm = sem.Mesh.from_box(mesh, g_fp32=geom == sem.PRECOMPUTED)
+        b = torch.as_tensor(bh.astype(np.float32), device="cuda")
+        x = torch.zeros_like(b)
+        gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            _, r = gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=iters)
+            if r["iters"] != iters or r["status"] != 2:
+                raise RuntimeError(f"a timed solve stopped early: {r}")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        x.zero_()
+        _, prof = gm.cg_solve(b, x=x, prec=sem.FP32, geom=geom, fixed_iters=iters,
+                              kernel_times=True)
+        info = gm.info()
+        rows[label] = {"gdof_iter_per_s": mesh.n_local * iters / dt / 1e9,
+                       "ms_per_solve": dt * 1e3, "kernel_ms": prof["kernel_ms"],
+                       "rel_res_recursive": r["rel_res_recursive"],
+                       "gather_form": "table-free" if info["gs_table_free"] else "per-point table"}
+        if label in ("hilbert", "morton"):
+            rows[label]["order_seconds_host"] = t_order
+        log(f"bench: {label}: {rows[label]['gdof_iter_per_s']:.1f} GDOF*iter/s "
+            f"{prof['kernel_ms']}")
+        gm.close()
+        del b, x
+    base = rows.get("structured", {}).get("gdof_iter_per_s")
+    if base:
+        for label, row in rows.items():
+            row["vs_structured"] = row["gdof_iter_per_s"] / base
+    return rows
+
+
+def run_config8(args):
+    """The headline FP32 CG on unstructured element numberings, with and
+    without reordering along a space-filling curve (see unstructured_rows)."""
+    rows = unstructured_rows(args)
+    return _emit({"metric": "FP32 CG GDOF·iter/s, 32^3 N=7: shuffled and rotated elements, "
+                            "Hilbert / Morton reordered, structured",
+                  "value": rows["hilbert"]["gdof_iter_per_s"], "unit": "GDOF·iter/s",
+                  "higher_is_better": True, "rows": rows, "dtype": "f32", "data": "synthetic",
+                  "config": {"workload": "32^3 N=7 +-10% deformed, 500 FP32 CG iterations, "
+                                         "element numbering varied"}})
+
+
 SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5, 6: run_config6,
-          7: run_config7}
+          7: run_config7, 8: run_config8}
 
 
 if __name__ == "__main__":

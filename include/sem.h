@@ -94,6 +94,28 @@ sem_status sem_mesh_create(int64_t n_elem, int order_N, const double *vert_xyz,
                            const int64_t *glob_id, const uint8_t *dirichlet,
                            uint32_t flags, void *hip_stream, sem_mesh_t *out);
 
+/*
+ * Element order for locality on unstructured meshes.  Sec. 4.3 notes that an
+ * unstructured mesh guarantees no ordering or spatial locality of the
+ * elements in the local vectors, which makes the gather-scatter's accesses
+ * unaligned; Sec. 8.2 proposes partitioning or sorting the elements to
+ * recover it.  This sorts the elements along a space-filling curve through
+ * their centroids.  Host only (no device work).
+ *   n_elem, vert_xyz  as in sem_mesh_create.
+ *   kind      SEM_ORDER_HILBERT or SEM_ORDER_MORTON (Z-order); elements whose
+ *             centroids fall in one cell of the curve's 2^21-per-axis grid
+ *             keep their input order.
+ *   perm      HOST int64 [n_elem], written: perm[k] is the input element
+ *             placed at position k.
+ * Applying perm to vert_xyz, glob_id and dirichlet (and to the element blocks
+ * of every local vector) before sem_mesh_create gives the same operator with
+ * the elements renumbered: every result equals that of the input order with
+ * its element blocks permuted.
+ * Errors: SEM_EINVAL (NULL, n_elem <= 0, non-finite coordinate, unknown kind).
+ */
+typedef enum { SEM_ORDER_HILBERT = 0, SEM_ORDER_MORTON = 1 } sem_element_order_kind;
+sem_status sem_element_order(int64_t n_elem, const double *vert_xyz, int kind, int64_t *perm);
+
 /* Free every device array of the mesh (synchronises the device). NULL is a no-op. */
 void sem_mesh_destroy(sem_mesh_t mesh);
 

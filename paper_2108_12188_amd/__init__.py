@@ -15,12 +15,13 @@ import numpy as np
 __all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_set",
            "ax_shape_get", "ax_engine_set", "ax_engine_get", "ENGINE_DEFAULT", "ENGINE_VALU",
            "ENGINE_MFMA", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
-           "PRECOND_NONE", "PRECOND_JACOBI",
-           "lib", "library_path", "version"]
+           "PRECOND_NONE", "PRECOND_JACOBI", "ORDER_HILBERT", "ORDER_MORTON", "element_order",
+           "permute_elements", "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
 PRECOMPUTED, ON_THE_FLY = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+ORDER_HILBERT, ORDER_MORTON = 0, 1
 G_FP32, G_FP64, GATHER_TABLE, GATHER_TABLE_FREE = 0x1, 0x2, 0x4, 0x8
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,7 +61,7 @@ class MeshInfo(C.Structure):
 
 _lib = None
 EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "sem_gs",
-           "sem_dot", "sem_dot_noalloc", "sem_diag", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
+           "sem_dot", "sem_dot_noalloc", "sem_diag", "sem_element_order", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
            "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
            "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_ax_shape_set",
            "sem_ax_shape_get", "sem_ax_engine_set", "sem_ax_engine_get", "sem_last_error",
@@ -84,6 +85,7 @@ def lib():
     L.sem_mesh_create.argtypes = [i64, i32, vp, vp, vp, u32, vp, C.POINTER(vp)]
     L.sem_mesh_destroy.argtypes = [vp]
     L.sem_mesh_destroy.restype = None
+    L.sem_element_order.argtypes = [i64, vp, i32, vp]
     L.sem_mesh_info.argtypes = [vp, C.POINTER(MeshInfo)]
     L.sem_ax.argtypes = [vp, i32, i32, vp, vp, vp]
     L.sem_gs.argtypes = [vp, i32, vp, i32, vp]
@@ -116,7 +118,7 @@ def lib():
                  "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve",
                  "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint",
                  "sem_ax_shape_set", "sem_ax_shape_get", "sem_ax_engine_set",
-                 "sem_ax_engine_get", "sem_diag"):
+                 "sem_ax_engine_get", "sem_diag", "sem_element_order"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -390,6 +392,35 @@ def ax_engine_get(N: int, prec: int, geom: int) -> int:
     e = C.c_int()
     _check(lib().sem_ax_engine_get(N, prec, geom, C.byref(e)))
     return e.value
+
+
+def element_order(vert, kind: int = ORDER_HILBERT) -> np.ndarray:
+    """Element permutation along a space-filling curve through the element
+    centroids (sem_element_order; host only): perm[k] is the input element
+    placed at position k."""
+    v = np.ascontiguousarray(vert, dtype=np.float64)
+    if v.ndim != 3 or v.shape[1:] != (8, 3):
+        raise ValueError("vert must be [E][8][3]")
+    perm = np.empty(v.shape[0], dtype=np.int64)
+    _check(lib().sem_element_order(v.shape[0], C.c_void_p(v.ctypes.data), kind,
+                                   C.c_void_p(perm.ctypes.data)))
+    return perm
+
+
+def permute_elements(perm, *arrays):
+    """The element-major arrays in the order perm: arrays whose first axis is
+    the element (vertices [E][8][3], scatter map and Dirichlet flags
+    [E][P^3]) are indexed along it; flat local vectors [E * P^3] by element
+    blocks."""
+    E = len(perm)
+    out = []
+    for a in arrays:
+        a = np.asarray(a)
+        if a.ndim >= 2 and a.shape[0] == E:
+            out.append(np.ascontiguousarray(a[perm]))
+        else:
+            out.append(np.ascontiguousarray(a.reshape(E, -1)[perm].ravel()))
+    return out
 
 
 def mesh_footprint(n_elem: int, N: int, g_fp32: bool = True, g_fp64: bool = False,

@@ -26,7 +26,7 @@ CFLAGS = [
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 SOURCES = ["sem_ax_dispatch.cpp", "sem_basis.cpp", "sem_mesh.cpp", "sem_tables.cpp", "sem_cg.cpp",
-           "sem_api.cpp", "sem_gs.hip", "sem_vec.hip", "sem_geom.hip", "sem_batch.hip"]
+           "sem_api.cpp", "sem_order.cpp", "sem_gs.hip", "sem_vec.hip", "sem_geom.hip", "sem_batch.hip"]
 
 
 def _compile(src: str, obj: str, extra=()):

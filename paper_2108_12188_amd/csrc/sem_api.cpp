@@ -36,6 +36,7 @@ Mesh *as_mesh(sem_mesh_t m) {
 
 Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, const uint8_t *dir,
                   uint32_t flags, hipStream_t s);
+void element_order(int64_t E, const double *vert, int kind, int64_t *perm);
 void mesh_destroy(Mesh *m);
 sem_status cg_solve(Mesh &m, const sem_cg_opts &o, const void *b, void *x, sem_cg_result &res,
                     hipStream_t s);
@@ -96,6 +97,13 @@ struct DeviceGuard {
 using namespace sem;
 
 extern "C" {
+
+sem_status sem_element_order(int64_t n_elem, const double *vert_xyz, int kind, int64_t *perm) {
+    return guarded([&]() -> sem_status {
+        element_order(n_elem, vert_xyz, kind, perm);
+        return SEM_OK;
+    });
+}
 
 sem_status sem_mesh_create(int64_t n_elem, int order_N, const double *vert_xyz,
                            const int64_t *glob_id, const uint8_t *dirichlet, uint32_t flags,

@@ -42,8 +42,10 @@ class Scheduler:
     """Admission by slot and memory footprint, FIFO (optionally with
     backfilling of smaller requests behind a blocked head)."""
 
-    def __init__(self, engine, budget_bytes: int, max_slots: int = 64, backfill: bool = False):
+    def __init__(self, engine, budget_bytes: int, max_slots: int = 64, backfill: bool = False,
+                 on_done=None):
         self.engine = engine
+        self.on_done = on_done      # called with the number of finished requests
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.backfill = backfill
@@ -51,6 +53,7 @@ class Scheduler:
         self.peak_used = 0
         self.active: dict[int, int] = {}
         self.log: list[tuple] = []
+        self.finished = 0
 
     def _try_admit(self, waiting: collections.deque, now: float):
         while waiting and len(self.active) < self.max_slots:
@@ -108,6 +111,9 @@ class Scheduler:
                 self.used -= self.active.pop(tag)
                 self.engine.release(tag)
                 self.log.append(("done", tag, r.done))
+                self.finished += 1
+                if self.on_done is not None:
+                    self.on_done(self.finished)
         return pending
 
 

@@ -36,7 +36,11 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_error_string_without_gpu():
     import paper_2108_12188_amd as sem
     assert "gfx950" in sem.version()
-    assert sem.lib().sem_last_error() == b""
+    # a message only after a failing call on this thread
+    assert isinstance(sem.lib().sem_last_error(), bytes)
+    perm = (ctypes.c_int64 * 1)()
+    assert sem.lib().sem_element_order(0, None, 0, perm) == -1
+    assert b"n_elem" in sem.lib().sem_last_error()
 
 
 def test_binding_refuses_without_gpu():
