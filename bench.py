@@ -33,6 +33,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed)
 FP32_FMA_TFLOPS = 78.6         # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FMA)
 FP64_PEAK_TFLOPS = 78.6
+CLOCK_HZ = 2.4e9               # MI355X engine clock (256 CUs x 4 SIMDs)
 
 
 def log(*a):
@@ -97,6 +98,53 @@ def read_traffic(kernel_key: str, per_launch_points: int):
     if not k or k.get("n_local") != per_launch_points:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+def read_counters(key: str, per_launch_points: int):
+    """One kernel's entry of the committed rocprofv3 counter summary
+    (profiles/ax_counters.json), only if it was taken on the current kernel
+    source and at this size; else None."""
+    p = os.path.join(ROOT, "profiles", "ax_counters.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("src_hash") != src_hash():
+        return None
+    k = d.get("kernels", {}).get(key)
+    if not k or k.get("n_local") != per_launch_points:
+        return None
+    return k
+
+
+def otf_executed(ms: float, n: int, N: int):
+    """Executed work of the stand-alone on-the-fly operator against the
+    units that could bind it, from its committed instruction counters
+    (SQ_INSTS_VALU, SQ_INSTS_MFMA, SQ_VALU_MFMA_BUSY_CYCLES per launch) and
+    the duration `ms` measured in this run: the fraction of the VALU issue
+    rate (1024 SIMDs, one wave64 instruction per 4 cycles: 78.6 TFLOP/s of
+    non-packed FP32 FMAs), of the matrix cores' time, and of HBM."""
+    k = read_counters(f"ax_otf_plain_N{N}", n)
+    if not k:
+        return None
+    t = ms * 1e-3
+    simd_cycles = 1024 * CLOCK_HZ * t
+    E = n // (N + 1) ** 3
+    out = {"valu_insts_per_element": k["valu_insts_per_launch"] / E,
+           "mfma_insts_per_element": k["mfma_insts_per_launch"] / E,
+           "executed_flop_per_point": k.get("executed_flop_per_point"),
+           "paper_flop_per_point": ax_flops_per_point(N, "otf"),
+           "valu_issue_frac": 4 * k["valu_insts_per_launch"] / simd_cycles,
+           "mfma_busy_frac": k["mfma_busy_cycles_per_launch"] / simd_cycles,
+           "hbm_frac": k["hbm_bytes_per_launch"] / t / (HBM_PEAK_GBS * 1e9),
+           "source": "profiles/ax_counters.json (rocprofv3 --pmc of bench.py --ax-only, same "
+                     "kernel source, hash-checked); duration from this run"}
+    out["executed_tflops"] = (out["executed_flop_per_point"] or 0) * n / t / 1e12
+    units = {"VALU issue (non-packed FP32, 78.6 TFLOP/s of FMAs)": out["valu_issue_frac"],
+             "matrix cores": out["mfma_busy_frac"], "HBM": out["hbm_frac"]}
+    out["binding_unit"] = max(units, key=units.get)
+    out["frac_of_binding_unit"] = units[out["binding_unit"]]
+    return out
 
 
 def cpu_baseline(mesh, b, budget_s: float = 15.0):
@@ -270,12 +318,13 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--geom", choices=["pre", "otf"], default="otf",
                     help="geometric-factor form of the timed solver")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6, 7, 8],
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6, 7, 8, 9],
                     help="2: the headline FP32 CG throughput line; 1, 3, 4, 5: the other "
                          "workloads (FP64 latency, mixed vs FP64, batched, serving); "
                          "6: Jacobi-preconditioned CG against plain CG; 7: FP32 CG "
                          "throughput against the element count; 8: the headline CG on "
-                         "unstructured element numberings, reordered or not")
+                         "unstructured element numberings, reordered or not; 9: the paper's "
+                         "performance model (Eq. 15, Table 2) on this GPU")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
@@ -291,6 +340,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the operator-alone and FP64 comparison runs")
+    ap.add_argument("--ax-only", action="store_true",
+                    help="time only the local operator alone (precomputed and on-the-fly G, "
+                         "50 launches each) on the bench mesh and print their durations "
+                         "(for counter profiles)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -339,6 +392,14 @@ def main(argv=None):
             cb.copy_(ca)
         torch.cuda.synchronize()
         del ca, cb
+    if args.ax_only:
+        u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n).astype(np.float32),
+                            device="cuda")
+        ms = {g: time_ax(gm, u, g) for g in ("pre", "otf")}
+        return _emit({"metric": "local operator alone, median of 50 launches",
+                      "ax_pre_ms": ms["pre"], "ax_otf_ms": ms["otf"], "n_local": n,
+                      "config": {"workload": f"{nel}^3 N={N} +-10% deformed, FP32"}})
+
     log("bench: warmup")
     for _ in range(args.warmup):
         step()
@@ -423,7 +484,12 @@ def main(argv=None):
             extra[f"ax_{g}_gbs"] = ax_bytes_per_point(N, g, False) * n / (ms * 1e-3) / 1e9
             extra[f"ax_{g}_gflops_paper"] = ax_flops_per_point(N, g) * n / (ms * 1e-3) / 1e9
         extra["ax_pre_hbm_frac"] = extra["ax_pre_gbs"] / HBM_PEAK_GBS
-        extra["ax_otf_fp32_frac"] = extra["ax_otf_gflops_paper"] / 1e3 / FP32_PEAK_TFLOPS
+        # paper-convention flops (30P+96 per point) over the packed FP32
+        # peak: a convention, not what runs (the D contractions run on the
+        # matrix cores, the geometry on the non-packed VALU)
+        extra["ax_otf_fp32_frac_paper_convention"] = \
+            extra["ax_otf_gflops_paper"] / 1e3 / FP32_PEAK_TFLOPS
+        extra["ax_otf_executed"] = otf_executed(extra["ax_otf_ms"], n, N)
         # the other geometric-factor form through the whole solver
         other = sem.ON_THE_FLY if args.geom == "pre" else sem.PRECOMPUTED
         x.zero_()
@@ -1075,8 +1141,165 @@ def run_config8(args):
                                          "element numbering varied"}})
 
 
+def run_config9(args):
+    """The paper's performance model (Sec. 5.2, Eq. 15; Table 2) on MI355X.
+
+    For the three solver versions of Table 2 (FP32 with G rematerialized on
+    the fly, FP32 with precomputed G, FP64 with precomputed G) on the
+    headline 32^3 N = 7 mesh, two schedules of the same CG iteration:
+    * "pass": the paper's, the gather-scatter QQ^T a pass of its own over w
+      (mesh flag SEM_MESH_GATHER_PASS);
+    * "fused": this library's, the face sums gathered inside the update and
+      only the edge and vertex groups summed by a small kernel.
+    Per-kernel times come from HIP events around every launch of 200
+    iterations; the iteration time from solves replayed from graphs.
+    Observed beta_gs = the gather-scatter words / the gather-scatter
+    kernel's time (the paper's 2 n_gs for the pass schedule, n_gs the shared
+    local points, exact); observed beta_eff = the algorithmic words of every
+    other kernel / their time.  Model
+    parameters measured on kernels that do nothing else: beta_eff = a
+    1 GiB device copy, beta_gs = a random-permutation gather and scatter of
+    4-byte values over the same vector length (fully unaligned accesses,
+    the paper's reference case).  Eq. 15,
+    T_c = (Q - Q_gs) / beta_eff + Q_gs / beta_gs, then gives the iteration
+    time of each schedule from the model parameters, and the fused
+    schedule's from the bandwidths observed on the pass schedule; each is
+    compared with the measured time.  Words are 4 bytes (FP32 versions) or
+    8 bytes (FP64); cycles are 2.4 GHz engine cycles."""
+    import numpy as np
+    import torch
+
+    import paper_2108_12188_amd as sem
+    from seminputs import MESH_SEED_BASE, RHS_SEED, box_mesh, random_global_rhs
+    nel, N = args.nel, args.order
+    iters = min(args.iters, 200)
+    mesh = box_mesh(nel, nel, nel, N, perturb=0.1, seed=MESH_SEED_BASE + 2)
+    n = mesh.n_local
+    E = mesh.E
+    P3 = (N + 1) ** 3
+    bh = random_global_rhs(mesh, seed=RHS_SEED)
+
+    # model parameters from kernels that do nothing else
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return sorted(a.elapsed_time(b) for a, b in ev)[reps // 2] * 1e-3
+
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    t_copy = timed(lambda: dst.copy_(src))
+    copy_bps = 2 * src.numel() * 4 / t_copy
+    del src, dst
+    g = torch.Generator(device="cpu").manual_seed(RHS_SEED)
+    perm = torch.randperm(n, generator=g).to("cuda")
+    v = torch.rand(n, device="cuda")
+    out = torch.empty_like(v)
+    t_gather = timed(lambda: torch.index_select(v, 0, perm, out=out))
+    t_scatter = timed(lambda: out.index_copy_(0, perm, v))
+    # words moved at random per index: one load (gather) or one store
+    # (scatter); the index stream itself is sequential
+    rand_wps = 2 * n / (t_gather + t_scatter)
+    del perm, v, out
+
+    def wpc(bytes_per_s, word):
+        return bytes_per_s / word / CLOCK_HZ
+
+    versions = (("FP32-CG-Remat.", sem.FP32, sem.ON_THE_FLY, 4),
+                ("FP32-CG", sem.FP32, sem.PRECOMPUTED, 4),
+                ("FP64-CG", sem.FP64, sem.PRECOMPUTED, 8))
+    edge_slots = 12 * N - 4
+
+    def stream_bytes(sched, geom, word, n_gs):
+        """Algorithmic bytes per iteration of everything but the
+        gather-scatter: the CG-fused operator (r and p_old read, p written,
+        x read and written, w written; precomputed G 6 words per point, or
+        the 8 vertices, 24 words, per element), its compact copy of the edge nodes in
+        the fused schedule, and the update (r read and written, w read; the
+        pass schedule's plain update also reads a code byte per point, the
+        fused one the element records and the gathered face values)."""
+        op = 6 * word * n + (6 * word * n if geom == sem.PRECOMPUTED else 24 * word * E)
+        if sched == "pass":
+            return op + (3 * word + 1) * n
+        op += word * E * edge_slots
+        rec = 8 * (6 + edge_slots) * E
+        return op + 3 * word * n + rec + word * n_gs
+
+    rows = {}
+    for sched in ("pass", "fused"):
+        gm = sem.Mesh.from_box(mesh, g_fp32=True, g_fp64=True, gather_pass=(sched == "pass"))
+        info = gm.info()
+        n_gs = info["n_shared"]
+        for name, prec, geom, word in versions:
+            dt = torch.float32 if prec == sem.FP32 else torch.float64
+            b = torch.as_tensor(bh, dtype=dt, device="cuda")
+            x = torch.zeros_like(b)
+            gm.cg_solve(b, x=x, prec=prec, geom=geom, fixed_iters=20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                x.zero_()
+                gm.cg_solve(b, x=x, prec=prec, geom=geom, fixed_iters=iters)
+            torch.cuda.synchronize()
+            t_iter = (time.perf_counter() - t0) / (2 * iters)
+            x.zero_()
+            _, pr = gm.cg_solve(b, x=x, prec=prec, geom=geom, fixed_iters=iters,
+                                kernel_times=True)
+            km = pr["kernel_ms"]
+            sb = stream_bytes(sched, geom, word, n_gs)
+            # gather-scatter words: the paper's 2 n_gs for the pass; the
+            # fused schedule sums only the edge and vertex groups, from the
+            # compact copy (each copy read once, one sum per group written;
+            # counted as two words per edge slot, an upper bound)
+            gs_words = 2 * n_gs if sched == "pass" else 2 * E * edge_slots
+            t_gs = km["gs"] * 1e-3
+            t_rest = (km["ax"] + km["update"]) * 1e-3
+            row = {"n": n, "n_gs": n_gs, "stream_words": sb / word, "gs_words": gs_words,
+                   "iteration_us": t_iter * 1e6, "kernel_us": {k: v * 1e3 for k, v in km.items()},
+                   "beta_eff_obs": sb / word / t_rest / CLOCK_HZ,
+                   "beta_gs_obs": gs_words / t_gs / CLOCK_HZ,
+                   "beta_eff_model": wpc(copy_bps, word),
+                   "beta_gs_model": rand_wps / CLOCK_HZ,
+                   "gs_share_of_iteration": t_gs / t_iter,
+                   "gdof_iter_per_s": n / t_iter / 1e9}
+            # Eq. 15 with the model parameters
+            row["T_c_model_us"] = 1e6 * (sb / word / (row["beta_eff_model"] * CLOCK_HZ) +
+                                         gs_words / (row["beta_gs_model"] * CLOCK_HZ))
+            row["model_over_measured"] = row["T_c_model_us"] / row["iteration_us"]
+            if sched == "fused":
+                # Eq. 15 with the bandwidths observed on the pass schedule:
+                # a prediction of this schedule from the paper's one
+                ps = rows[name]["pass"]
+                tc = sb / word / (ps["beta_eff_obs"] * CLOCK_HZ) + \
+                    gs_words / (ps["beta_gs_obs"] * CLOCK_HZ)
+                row["T_c_from_pass_betas_us"] = tc * 1e6
+                row["from_pass_over_measured"] = tc * 1e6 / row["iteration_us"]
+            rows.setdefault(name, {})[sched] = row
+            log(f"bench9: {sched} {name}: {t_iter * 1e6:.1f} us/iter, beta_eff "
+                f"{row['beta_eff_obs']:.1f}, beta_gs {row['beta_gs_obs']:.1f} words/cycle")
+            del b, x
+        gm.close()
+    return _emit({"metric": "Eq. 15 performance model on MI355X (Table 2 analogue): observed "
+                            "and modelled beta_eff, beta_gs in words/cycle, 32^3 N=7",
+                  "value": rows["FP32-CG-Remat."]["pass"]["beta_gs_obs"],
+                  "unit": "words/cycle (beta_gs, FP32 remat, pass schedule)",
+                  "higher_is_better": True, "rows": rows,
+                  "machine": {"clock_hz": CLOCK_HZ, "copy_GBps": copy_bps / 1e9,
+                              "random_gather_scatter_Gwords_per_s": rand_wps / 1e9,
+                              "hbm_peak_words_per_cycle_fp32": HBM_PEAK_GBS * 1e9 / 4 / CLOCK_HZ},
+                  "dtype": "f32/f64", "data": "synthetic",
+                  "config": {"workload": f"{nel}^3 N={N} +-10% deformed, random RHS, {iters} "
+                                         f"CG iterations per version and schedule"}})
+
+
 SUITES = {1: run_config1, 3: run_config3, 4: run_config4, 5: run_config5, 6: run_config6,
-          7: run_config7, 8: run_config8}
+          7: run_config7, 8: run_config8, 9: run_config9}
 
 
 if __name__ == "__main__":

@@ -67,6 +67,12 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  * applies, whatever the size.  Not both. */
 #define SEM_MESH_GATHER_TABLE 0x4u
 #define SEM_MESH_GATHER_TABLE_FREE 0x8u
+/* The paper's schedule instead (Algorithm 1 with the gather-scatter QQ^T as a
+ * pass of its own over w between the operator and the update, Sec. 4.3):
+ * same results up to rounding order; for measuring the gather-scatter's own
+ * bandwidth as the performance model of Sec. 5.2 (Eq. 15) does.  Excludes
+ * the two flags above. */
+#define SEM_MESH_GATHER_PASS 0x10u
 
 /*
  * Build a mesh on the current HIP device (Sec. 3: decomposition into E
@@ -81,8 +87,9 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
  *              gather-scatter.  Every id in [0, max id] need not be used.
  *   dirichlet  HOST uint8 [E][P3]: 1 on the Dirichlet boundary; must be equal
  *              on all copies of a global point.  May be NULL (no boundary).
- *   flags      bit set of SEM_MESH_G_FP32 / SEM_MESH_G_FP64 /
- *              SEM_MESH_GATHER_TABLE or SEM_MESH_GATHER_TABLE_FREE.
+ *   flags      bit set of SEM_MESH_G_FP32 / SEM_MESH_G_FP64 / one of
+ *              SEM_MESH_GATHER_TABLE, SEM_MESH_GATHER_TABLE_FREE,
+ *              SEM_MESH_GATHER_PASS.
  *   out        receives the handle.
  * Copies what it needs; the host arrays may be freed on return.  Blocks until
  * the device-side setup (geometric factors, Jacobian check) has finished.

@@ -22,7 +22,7 @@ FP64, FP32, MIXED = 0, 1, 2
 PRECOMPUTED, ON_THE_FLY = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 ORDER_HILBERT, ORDER_MORTON = 0, 1
-G_FP32, G_FP64, GATHER_TABLE, GATHER_TABLE_FREE = 0x1, 0x2, 0x4, 0x8
+G_FP32, G_FP64, GATHER_TABLE, GATHER_TABLE_FREE, GATHER_PASS = 0x1, 0x2, 0x4, 0x8, 0x10
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsem.so")
@@ -167,11 +167,12 @@ class Mesh:
     sem_mesh_create: g_fp32 / g_fp64 keep precomputed geometric factors in
     that precision; gather_table / table_free choose the form of the
     gather-scatter inside CG (per-point table, or position-derived at odd
-    N) instead of the size rule (same results either way)."""
+    N) instead of the size rule (same results either way); gather_pass runs
+    it as a pass of its own, the paper's schedule."""
 
     def __init__(self, vert, glob_id, dirichlet, N: int, g_fp32: bool = True,
                  g_fp64: bool = False, stream=None, gather_table: bool = False,
-                 table_free: bool = False):
+                 table_free: bool = False, gather_pass: bool = False):
         _torch()
         vert = np.ascontiguousarray(vert, dtype=np.float64)
         gid = np.ascontiguousarray(glob_id, dtype=np.int64)
@@ -180,7 +181,8 @@ class Mesh:
         if vert.shape != (E, 8, 3) or gid.size != E * (N + 1) ** 3:
             raise ValueError("vert must be [E][8][3] and glob_id [E][(N+1)^3]")
         flags = ((G_FP32 if g_fp32 else 0) | (G_FP64 if g_fp64 else 0) |
-                 (GATHER_TABLE if gather_table else 0) | (GATHER_TABLE_FREE if table_free else 0))
+                 (GATHER_TABLE if gather_table else 0) | (GATHER_TABLE_FREE if table_free else 0) |
+                 (GATHER_PASS if gather_pass else 0))
         h = C.c_void_p()
         _check(lib().sem_mesh_create(E, N, vert.ctypes.data, gid.ctypes.data,
                                      None if dr is None else dr.ctypes.data, flags,

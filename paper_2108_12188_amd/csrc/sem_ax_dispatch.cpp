@@ -69,10 +69,18 @@ constexpr int64_t kAxFusedMaxBlocks = SEM_AX_FUSED_MAX_BLOCKS;
 constexpr int64_t kAxMfmaMaxBlocks = SEM_AX_MFMA_MAX_BLOCKS;
 constexpr int64_t kAxMfma2MaxBlocks = SEM_AX_MFMA2_MAX_BLOCKS;
 
+// the plain (stand-alone) operator: one tile per block unless capped
+#ifndef SEM_AX_PLAIN_MAX_BLOCKS
+#define SEM_AX_PLAIN_MAX_BLOCKS 0
+#endif
+constexpr int64_t kAxPlainMaxBlocks = SEM_AX_PLAIN_MAX_BLOCKS;
+
 static int64_t ax_grid(int64_t ntiles, AxMode mode, bool mfma, int threads = 64) {
     const int64_t cap =
         mfma ? (threads == 64 ? kAxMfmaMaxBlocks : kAxMfma2MaxBlocks) : kAxFusedMaxBlocks;
     if (mode == AxMode::CgFused && ntiles > cap) return cap;
+    if (mode != AxMode::CgFused && kAxPlainMaxBlocks > 0 && ntiles > kAxPlainMaxBlocks)
+        return kAxPlainMaxBlocks;
     return ntiles;
 }
 

@@ -174,6 +174,11 @@ struct BatchImpl {
         int64_t nblk = 0;
     };
     std::vector<OrderGroup> groups[2];              // [precomputed, on the fly]
+    struct BlkTable {
+        int2 *blk = nullptr;
+        size_t cap = 0;
+    };
+    std::map<int, BlkTable> blk_tab[2];              // per order; owns the group tables
     AxArgs<float> *d_ax[2] = {nullptr, nullptr};   // [precomputed, on the fly]
     GsClasses *d_cls = nullptr;
     GsBatchDesc *d_gs = nullptr;
@@ -207,8 +212,8 @@ struct BatchImpl {
         (void)hipDeviceSynchronize();
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
         for (int f = 0; f < 2; ++f)
-            for (auto &g : groups[f])
-                if (g.blk) (void)hipFree(g.blk);
+            for (auto &kv : blk_tab[f])
+                if (kv.second.blk) (void)hipFree(kv.second.blk);
         void *ptrs[] = {d_ax[0],   d_ax[1], d_cls,      d_gs,   d_gs_blk,   d_upd,
                         d_upd_blk, d_gsum,  d_gsum_blk, d_updg, d_updg_blk, d_upds, d_upds_blk,
                         d_fin[0],
@@ -468,17 +473,19 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     ensure_cap(d_upds_blk, cap_upds_blk, upds_blk.size(), bytes);
     upload_sync(d_upds_blk, upds_blk);
     for (int f = 0; f < 2; ++f) {
-        for (auto &g : groups[f])
-            if (g.blk) (void)hipFree(g.blk);
+        // each order's block table (and its capacity) persists across
+        // rebuilds: the serving loop rebuilds whenever its member set changes
         groups[f].clear();
         for (auto &kv : order_blk[f]) {
+            BlkTable &t = blk_tab[f][kv.first];
+            ensure_cap(t.blk, t.cap, kv.second.size(), bytes);
+            upload_sync(t.blk, kv.second);
             OrderGroup g;
             g.N = kv.first;
             g.epb = order_epb[f][kv.first];
             g.mfma = order_mfma[f][kv.first];
             g.nblk = (int64_t)kv.second.size();
-            g.blk = dalloc<int2>(kv.second.size(), bytes);
-            upload_sync(g.blk, kv.second);
+            g.blk = t.blk;
             groups[f].push_back(g);
         }
     }

@@ -91,10 +91,16 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         fail(SEM_EUNSUPPORTED, "order N=" + std::to_string(N) + " is not built (1..11)");
     if (!vert || !gid) fail(SEM_EINVAL, "vert_xyz and glob_id must not be NULL");
     if (flags & ~(uint32_t)(SEM_MESH_G_FP32 | SEM_MESH_G_FP64 | SEM_MESH_GATHER_TABLE |
-                            SEM_MESH_GATHER_TABLE_FREE))
+                            SEM_MESH_GATHER_TABLE_FREE | SEM_MESH_GATHER_PASS))
         fail(SEM_EINVAL, "unknown mesh flags");
-    if ((flags & SEM_MESH_GATHER_TABLE) && (flags & SEM_MESH_GATHER_TABLE_FREE))
-        fail(SEM_EINVAL, "SEM_MESH_GATHER_TABLE and SEM_MESH_GATHER_TABLE_FREE exclude each other");
+    {
+        const int forms = ((flags & SEM_MESH_GATHER_TABLE) ? 1 : 0) +
+                          ((flags & SEM_MESH_GATHER_TABLE_FREE) ? 1 : 0) +
+                          ((flags & SEM_MESH_GATHER_PASS) ? 1 : 0);
+        if (forms > 1)
+            fail(SEM_EINVAL, "SEM_MESH_GATHER_TABLE, SEM_MESH_GATHER_TABLE_FREE and "
+                             "SEM_MESH_GATHER_PASS exclude each other");
+    }
     const int P = N + 1, P3 = P * P * P;
     const int64_t n = E * P3;
     if (E > (int64_t(1) << 31) / P3 || n >= (int64_t(1) << 31))
@@ -110,6 +116,12 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
 
     HostTables t;
     build_tables(E, N, gid, dir, t);
+    if (flags & SEM_MESH_GATHER_PASS) {
+        // the paper's schedule: a gather-scatter pass of its own
+        t.gs_in_update = false;
+        t.gsum_wedge = false;
+        t.gs_struct = false;
+    }
     m->n_glob = t.n_glob;
     m->gs = t.gs;
     m->n_groups = t.n_groups;

@@ -194,8 +194,9 @@ def test_mixed_precision_reaches_1e10(geom):
 def test_cg_gather_in_update_modes(prec):
     """A conforming mesh gathers the shared sums inside the CG update (also
     with a group of 3 copies); a scatter map that ties two element-interior
-    nodes (valid, not conforming) takes the separate gather-scatter pass.
-    All follow the oracle."""
+    nodes (valid, not conforming) takes the separate gather-scatter pass, and
+    so does a conforming mesh created with SEM_MESH_GATHER_PASS (the paper's
+    schedule).  All follow the oracle."""
     import dataclasses
 
     import torch
@@ -211,10 +212,11 @@ def test_cg_gather_in_update_modes(prec):
     gid3 = mesh.glob_id.copy()
     gid3[5, P * (2 + P * 2)] = gid3[0, mesh.N + P * (2 + P * 2)]
     odd = dataclasses.replace(mesh, glob_id=gid3)
-    for m, expect in ((mesh, 1), (odd, 1), (tied, 0)):
-        say(f"cg {prec} gather-in-update={expect}")
+    for m, expect, kw in ((mesh, 1, {}), (odd, 1, {}), (tied, 0, {}),
+                          (mesh, 0, {"gather_pass": True})):
+        say(f"cg {prec} gather-in-update={expect} {kw}")
         pr = oracle.Problem(m)
-        gm = sem.Mesh.from_box(m, g_fp64=fp64, g_fp32=not fp64)
+        gm = sem.Mesh.from_box(m, g_fp64=fp64, g_fp32=not fp64, **kw)
         assert gm.info()["gs_in_update"] == expect
         b = random_global_rhs(m, seed=12188)
         xo, _, hist = pr.cg(b, fixed=12)
