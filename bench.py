@@ -865,6 +865,7 @@ def run_config5(args):
                    "not_converged": [r.tag for r in out if r.status != "done"]})
         if not fp64:
             st["peak_measured_bytes"] = eng.peak_measured_bytes
+            st["host_time_s"] = dict(eng.timing)
         log(f"bench5: {label}: p50 {st['p50_s']:.3f} s, p99 {st['p99_s']:.3f} s, "
             f"{st['solves_per_s']:.1f} solves/s")
         runs[label] = st

@@ -18,6 +18,7 @@ from __future__ import annotations
 import collections
 import concurrent.futures as cf
 import math
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -159,6 +160,10 @@ class GpuEngine:
         self.keep_results = keep_results
         self.results: dict[int, object] = {}
         self.peak_measured_bytes = 0
+        # host time split: preparation (summed over the worker threads) and
+        # the scheduling thread's waits and server rounds
+        self.timing = collections.Counter()
+        self._lock = threading.Lock()
         self._kept_bytes = 0        # results of released requests kept for the caller
         self._alloc0 = torch.cuda.memory_allocated()
         self.t0 = time.perf_counter()
@@ -193,12 +198,20 @@ class GpuEngine:
 
     def _prepare(self, r: Request):
         torch = self._torch
+        t0 = time.perf_counter()
         vert, gid, dirichlet, N, forcing = self.make_problem(r)
+        t1 = time.perf_counter()
         mesh = self._Mesh(vert, gid, dirichlet, N, g_fp32=self.g_fp32)
+        t2 = time.perf_counter()
         f = forcing(mesh.coords())
         b = mesh.rhs(f.contiguous(), prec=self._mixed)
         x = torch.zeros_like(b)
         torch.cuda.current_stream().synchronize()
+        t3 = time.perf_counter()
+        with self._lock:
+            self.timing["make_problem_s"] += t1 - t0
+            self.timing["mesh_create_s"] += t2 - t1
+            self.timing["rhs_s"] += t3 - t2
         return mesh, b, x
 
     def admit(self, r: Request):
@@ -216,11 +229,16 @@ class GpuEngine:
             self.held[t] = (mesh, b, x)
 
     def step(self):
+        t0 = time.perf_counter()
         self._add_ready(block=not self.held)
+        t1 = time.perf_counter()
+        self.timing["wait_prepared_s"] += t1 - t0
         if not self.held:
             return []
         self._measure()
         done, _ = self.server.step()
+        self.timing["server_step_s"] += time.perf_counter() - t1
+        self.timing["rounds"] += 1
         return done
 
     def release(self, tag: int):
