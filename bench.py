@@ -328,6 +328,10 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second "
                     "(0: 0.8 x the measured batched capacity)")
+    ap.add_argument("--round-iters", type=int, default=32,
+                    help="serving: CG iterations of the running requests per server round")
+    ap.add_argument("--slots", type=int, default=128,
+                    help="serving: requests admitted at once at most (and the device budget)")
     ap.add_argument("--no-tune", action="store_true", help="ignore the tuned tile shapes")
     ap.add_argument("--engine", choices=["default", "valu", "mfma"], default="default",
                     help="contraction engine of the FP32 local operator at the bench order")
@@ -848,14 +852,15 @@ def run_config5(args):
         if fp64:
             eng = _Fp64Engine(make_problem, 1e-8, geom, prep_workers=8)
         else:
-            eng = GpuEngine(make_problem, tol=1e-8, geom=geom, round_iters=16, prep_workers=8)
+            eng = GpuEngine(make_problem, tol=1e-8, geom=geom, round_iters=args.round_iters,
+                            prep_workers=8)
         t_run = time.perf_counter()
 
         def progress(k):
             if k % 100 == 0:
                 log(f"bench5: {label}: {k} done after {time.perf_counter() - t_run:.1f} s")
 
-        sch = Scheduler(eng, budget_bytes=budget, max_slots=64, on_done=progress)
+        sch = Scheduler(eng, budget_bytes=budget, max_slots=args.slots, on_done=progress)
         out = sch.run(reqs)
         eng.close()
         st = summarize(out)

@@ -137,10 +137,22 @@ finalize_rho_batch_kernel(const FinBatchDesc *__restrict__ d) {
     vecb::finalize_rho_body(f.st, f.part_vec, f.n_vec);
 }
 
-// (stop, iter) of every problem into one array for a single host read
-__global__ void gather_states_kernel(const FinBatchDesc *__restrict__ d, int count, int2 *out) {
+// What the host reads of every problem's CG state after a chunk of batched
+// iterations: one array, one copy.
+struct StateRow {
+    int stop;
+    int iter;
+    double rr;       // <r, r, c> of the current residual
+    double rho0;     // <r0, r0, c>
+};
+
+__global__ void gather_states_kernel(const FinBatchDesc *__restrict__ d, int count,
+                                     StateRow *out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < count) out[q] = make_int2(d[q].st->stop, d[q].st->iter);
+    if (q < count) {
+        const CgState *st = d[q].st;
+        out[q] = StateRow{st->stop, st->iter, st->rr, st->rho0};
+    }
 }
 
 template <typename T>
@@ -197,8 +209,8 @@ struct BatchImpl {
     int2 *d_upds_blk = nullptr;
     int64_t n_upds_blk = 0;
     FinBatchDesc *d_fin[2] = {nullptr, nullptr};   // [precomputed, on the fly]
-    int2 *d_states = nullptr;
-    int2 *h_states = nullptr;                        // pinned
+    StateRow *d_states = nullptr;
+    StateRow *h_states = nullptr;                    // pinned
     size_t cap_ax[2] = {0, 0}, cap_fin[2] = {0, 0}, cap_cls = 0, cap_gs = 0, cap_gs_blk = 0,
            cap_upd = 0, cap_upd_blk = 0, cap_gsum = 0, cap_gsum_blk = 0, cap_updg = 0,
            cap_updg_blk = 0, cap_upds = 0, cap_upds_blk = 0, cap_states = 0, cap_h_states = 0;
@@ -291,7 +303,7 @@ struct BatchImpl {
     void read_states() {
         hipLaunchKernelGGL(gather_states_kernel, dim3((count() + 255) / 256), dim3(256), 0, stream,
                            d_fin[0], count(), d_states);
-        SEM_HIP(hipMemcpyAsync(h_states, d_states, sizeof(int2) * count(), hipMemcpyDeviceToHost,
+        SEM_HIP(hipMemcpyAsync(h_states, d_states, sizeof(StateRow) * count(), hipMemcpyDeviceToHost,
                                stream));
         SEM_HIP(hipStreamSynchronize(stream));
     }
@@ -454,7 +466,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     if (cap_h_states < (size_t)count) {
         if (h_states) (void)hipHostFree(h_states);
         h_states = nullptr;
-        SEM_HIP(hipHostMalloc((void **)&h_states, sizeof(int2) * std::max(count, 1)));
+        SEM_HIP(hipHostMalloc((void **)&h_states, sizeof(StateRow) * std::max(count, 1)));
         cap_h_states = std::max(count, 1);
     }
     n_gs_blk = (int64_t)gs_blk.size();
@@ -499,14 +511,17 @@ double now_s() {
 }
 
 // Sets the FP32 CG state of problem q: fresh solve (todo) or stopped.
-void set_state(Mesh &m, bool active, double tol, int max_iter, int fixed, hipStream_t s) {
+// idle: the caller knows no copy from or to the workspace's pinned state is
+// still in flight (else the stream is synchronised first).
+void set_state(Mesh &m, bool active, double tol, int max_iter, int fixed, hipStream_t s,
+               bool idle = false) {
     Workspace &ws = cg_workspace(m, false);
     CgState h{};
     h.thresh = tol * tol;
     h.max_iter = fixed > 0 ? fixed : max_iter;
     h.fixed = fixed > 0 ? 1 : 0;
     h.stop = active ? 0 : 1;
-    SEM_HIP(hipStreamSynchronize(s));
+    if (!idle) SEM_HIP(hipStreamSynchronize(s));
     *ws.h_st = h;
     SEM_HIP(hipMemcpyAsync(ws.st, ws.h_st, sizeof(CgState), hipMemcpyHostToDevice, s));
 }
@@ -520,8 +535,8 @@ void iterate_all(BatchImpl &B, bool otf, int chunk, bool use_graph, int max_iter
         bool any = false;
         int64_t sum = 0;
         for (int q = 0; q < B.count(); ++q) {
-            any |= B.h_states[q].x == 0;
-            sum += B.h_states[q].y;
+            any |= B.h_states[q].stop == 0;
+            sum += B.h_states[q].iter;
         }
         if (!any) break;
         if (sum <= last_sum || round > guard)
@@ -837,8 +852,10 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
             Workspace &w32 = cg_workspace(*r.m, false);
             float *b32 = static_cast<float *>(w32.b);
             launch_scale_to_f32(r.m->n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
+            // the stream was synchronised after the outer residuals, and
+            // this request's pinned state is not in use: no further sync
             set_state(*r.m, true, refine_inner_tol(sv.inner_tol, sv.o.tol, r.rel), sv.inner_cap,
-                      0, s);
+                      0, s, true);
             SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * r.m->n, s));
             launch_cg_init<float>(*r.m, b32, nullptr, static_cast<float *>(w32.r),
                                   static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
@@ -865,13 +882,10 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
         int q = 0;
         for (ServerReq &r : sv.reqs) {
             if (r.phase != 1) continue;
-            const int stop = sv.batch.h_states[q++].x;
-            if (!stop) continue;
+            const StateRow h = sv.batch.h_states[q++];   // read for every member at once
+            if (!h.stop) continue;
             Workspace &w32 = cg_workspace(*r.m, false);
             Workspace &w64 = cg_workspace(*r.m, true);
-            SEM_HIP(hipMemcpyAsync(w32.h_st, w32.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-            SEM_HIP(hipStreamSynchronize(s));
-            const CgState &h = *w32.h_st;
             r.total += h.iter;
             r.last_stop = h.stop;
             r.inner_rel = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;

@@ -155,6 +155,7 @@ class GpuEngine:
         self.server = Server(tol=tol, geom=geom, inner_tol=inner_tol, round_iters=round_iters)
         self.make_problem = make_problem
         self.pool = cf.ThreadPoolExecutor(max_workers=prep_workers)
+        self.release_pool = cf.ThreadPoolExecutor(max_workers=1)
         self.preparing: dict[int, cf.Future] = {}
         self.held: dict[int, tuple] = {}
         self.keep_results = keep_results
@@ -232,13 +233,16 @@ class GpuEngine:
         t0 = time.perf_counter()
         self._add_ready(block=not self.held)
         t1 = time.perf_counter()
-        self.timing["wait_prepared_s"] += t1 - t0
         if not self.held:
+            with self._lock:
+                self.timing["wait_prepared_s"] += t1 - t0
             return []
         self._measure()
         done, _ = self.server.step()
-        self.timing["server_step_s"] += time.perf_counter() - t1
-        self.timing["rounds"] += 1
+        with self._lock:
+            self.timing["wait_prepared_s"] += t1 - t0
+            self.timing["server_step_s"] += time.perf_counter() - t1
+            self.timing["rounds"] += 1
         return done
 
     def release(self, tag: int):
@@ -246,10 +250,21 @@ class GpuEngine:
         if self.keep_results:
             self.results[tag] = x
             self._kept_bytes += x.numel() * x.element_size()
+        # destroying a mesh synchronises the device and frees its arrays:
+        # done on a thread of its own so the scheduling thread goes on
+        # feeding the server (the server no longer holds the request)
+        self.release_pool.submit(self._destroy, mesh, b)
+
+    def _destroy(self, mesh, b):
+        t0 = time.perf_counter()
         mesh.close()
+        del b
+        with self._lock:
+            self.timing["release_s"] += time.perf_counter() - t0
 
     def close(self):
         self.pool.shutdown(wait=True)
         for t in list(self.held):
             self.release(t)
+        self.release_pool.shutdown(wait=True)
         self.server.close()
