@@ -299,12 +299,16 @@ struct BatchImpl {
         SEM_HIP(hipGraphLaunch(it->second, stream));
     }
 
-    // reads (stop, iter) of every problem
-    void read_states() {
+    // the state of every member into the pinned h_states (stream-ordered)
+    void enqueue_read_states() {
         hipLaunchKernelGGL(gather_states_kernel, dim3((count() + 255) / 256), dim3(256), 0, stream,
                            d_fin[0], count(), d_states);
         SEM_HIP(hipMemcpyAsync(h_states, d_states, sizeof(StateRow) * count(), hipMemcpyDeviceToHost,
                                stream));
+    }
+    // ... and wait for it
+    void read_states() {
+        enqueue_read_states();
         SEM_HIP(hipStreamSynchronize(stream));
     }
 
@@ -526,27 +530,45 @@ void set_state(Mesh &m, bool active, double tol, int max_iter, int fixed, hipStr
     SEM_HIP(hipMemcpyAsync(ws.st, ws.h_st, sizeof(CgState), hipMemcpyHostToDevice, s));
 }
 
-// Batched FP32 iterations until every problem has stopped.
+// Batched FP32 iterations until every problem has stopped.  Problems that
+// have stopped leave the launches: once a quarter of the current members
+// have stopped, the tables are rebuilt for the running ones (a running
+// problem's blocks, partial slots and results stay those of its solo solve;
+// the caller restores the full member list afterwards).
 void iterate_all(BatchImpl &B, bool otf, int chunk, bool use_graph, int max_iter) {
     int64_t last_sum = -1;
     const int64_t guard = (int64_t)max_iter / std::max(chunk, 1) + 8;
     for (int64_t round = 0;; ++round) {
         B.read_states();
-        bool any = false;
+        int running = 0;
         int64_t sum = 0;
         for (int q = 0; q < B.count(); ++q) {
-            any |= B.h_states[q].stop == 0;
+            running += B.h_states[q].stop == 0;
             sum += B.h_states[q].iter;
         }
-        if (!any) break;
+        if (!running) break;
         if (sum <= last_sum || round > guard)
             fail(SEM_EDEVICE, "batched CG state did not advance");
         last_sum = sum;
+        if (4 * (B.count() - running) >= B.count()) {
+            std::vector<Mesh *> keep;
+            for (int q = 0; q < B.count(); ++q)
+                if (B.h_states[q].stop == 0) keep.push_back(B.meshes[q]);
+            B.rebuild(keep);
+            last_sum = -1;      // the sum now runs over fewer members
+        }
         B.run_chunk(otf, chunk, use_graph);
     }
 }
 
 }  // namespace
+
+struct ServerImpl;
+ServerImpl *server_new(const sem_cg_opts &o, int round_iters);
+void server_delete(ServerImpl *sv);
+void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag,
+                hipStream_t user_s);
+int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, int *n_done);
 
 sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_dev,
                        void *const *x_dev, sem_cg_result *res, hipStream_t user_s) {
@@ -570,9 +592,10 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
     const bool graph = o.use_graph != 0;
     bool breakdown = false;
 
+    const std::vector<Mesh *> all = B.meshes;   // iterate_all may drop stopped members
     if (o.prec == SEM_FP32) {
         for (int q = 0; q < P; ++q) {
-            Mesh &m = *B.meshes[q];
+            Mesh &m = *all[q];
             Workspace &ws = cg_workspace(m, false);
             set_state(m, true, o.tol, o.max_iter, o.fixed_iters, s);
             SEM_HIP(hipMemcpyAsync(ws.x, x_dev[q], sizeof(float) * m.n, hipMemcpyDeviceToDevice, s));
@@ -588,8 +611,9 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
                                   static_cast<float *>(ws.p), ws.st, ws.part_vec, s);
         }
         iterate_all(B, otf, chunk, graph, o.fixed_iters > 0 ? o.fixed_iters : o.max_iter);
+        if (B.meshes != all) B.rebuild(all);
         for (int q = 0; q < P; ++q) {
-            Mesh &m = *B.meshes[q];
+            Mesh &m = *all[q];
             Workspace &ws = cg_workspace(m, false);
             launch_x_flush<float>(m, static_cast<float *>(ws.x), static_cast<const float *>(ws.p),
                                   ws.st, s);
@@ -606,105 +630,27 @@ sem_status batch_solve(BatchImpl &B, const sem_cg_opts &o, const void *const *b_
             breakdown |= h.stop == 3;
         }
     } else if (o.prec == SEM_MIXED) {
-        const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
-        const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
-        const int inner_cap = o.max_iter > 0 ? o.max_iter : 100000;
-        std::vector<int> outer(P, 0), total(P, 0), done(P, 0), last_stop(P, 0);
-        std::vector<double> rel(P, 0.0), inner_rel(P, 0.0);
-        for (int q = 0; q < P; ++q) {
-            Mesh &m = *B.meshes[q];
-            Workspace &w64 = cg_workspace(m, true);
-            double *x64 = static_cast<double *>(w64.x);
-            SEM_HIP(hipMemcpyAsync(x64, x_dev[q], sizeof(double) * m.n, hipMemcpyDeviceToDevice, s));
-            launch_mask<double>(m, x64, s);
-            launch_dot<double>(m, static_cast<const double *>(b_dev[q]),
-                               static_cast<const double *>(b_dev[q]), w64.dval + 1, w64.part_vec, s);
-        }
-        for (;;) {
-            // outer FP64 residuals of the problems still running
-            for (int q = 0; q < P; ++q) {
-                if (done[q]) continue;
-                Mesh &m = *B.meshes[q];
-                Workspace &w64 = cg_workspace(m, true);
-                api_apply_A64(m, static_cast<const double *>(w64.x), static_cast<double *>(w64.w), s);
-                launch_residual64(m, static_cast<const double *>(b_dev[q]),
-                                  static_cast<const double *>(w64.w), static_cast<double *>(w64.r),
-                                  w64.dval + 0, w64.part_vec, s);
-                SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double),
-                                       hipMemcpyDeviceToHost, s));
-            }
-            SEM_HIP(hipStreamSynchronize(s));
-            std::vector<int> todo(P, 0);
-            int ntodo = 0;
-            for (int q = 0; q < P; ++q) {
-                if (done[q]) continue;
-                Workspace &w64 = cg_workspace(*B.meshes[q], true);
-                const double rr = w64.h_val[0], bb = w64.h_val[1];
-                rel[q] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
-                if (!std::isfinite(rel[q])) {
-                    done[q] = 3;
-                } else if (rel[q] <= o.tol || rr == 0.0) {
-                    done[q] = 1;
-                } else if (outer[q] >= max_outer) {
-                    done[q] = 2;
-                } else {
-                    todo[q] = 1;
-                    ++ntodo;
-                }
-            }
-            if (ntodo == 0) break;
-            for (int q = 0; q < P; ++q) {
-                Mesh &m = *B.meshes[q];
-                Workspace &w32 = cg_workspace(m, false);
-                if (!todo[q]) {
-                    set_state(m, false, inner_tol, inner_cap, 0, s);
-                    continue;
-                }
-                Workspace &w64 = cg_workspace(m, true);
-                float *b32 = static_cast<float *>(w32.b);
-                launch_scale_to_f32(m.n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
-                set_state(m, true, refine_inner_tol(inner_tol, o.tol, rel[q]), inner_cap, 0, s);
-                SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * m.n, s));
-                launch_cg_init<float>(m, b32, nullptr, static_cast<float *>(w32.r),
-                                      static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
-            }
-            iterate_all(B, otf, chunk, graph, inner_cap);
-            for (int q = 0; q < P; ++q) {
-                if (!todo[q]) continue;
-                Mesh &m = *B.meshes[q];
-                Workspace &w32 = cg_workspace(m, false);
-                Workspace &w64 = cg_workspace(m, true);
-                SEM_HIP(hipMemcpyAsync(w32.h_st, w32.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-                SEM_HIP(hipStreamSynchronize(s));
-                const CgState &h = *w32.h_st;
-                total[q] += h.iter;
-                last_stop[q] = h.stop;
-                inner_rel[q] = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;
-                if (h.stop == 3) {
-                    done[q] = 3;
-                    continue;
-                }
-                launch_x_flush<float>(m, static_cast<float *>(w32.x),
-                                      static_cast<const float *>(w32.p), w32.st, s);
-                launch_axpy_from_f32(m.n, static_cast<double *>(w64.x), w64.dval + 0,
-                                     static_cast<const float *>(w32.x), s);
-                ++outer[q];
+        // every problem runs the refinement of sem_cg_solve(SEM_MIXED) with
+        // outer steps of its own: the serving loop with all problems added
+        // at once.  The inner FP32 iterations of the problems in their inner
+        // solve advance together; a problem leaves the launches when its
+        // inner solve stops (its FP64 outer residual runs between rounds)
+        // and joins them again for its next inner solve.
+        std::unique_ptr<ServerImpl, void (*)(ServerImpl *)> sv(server_new(o, chunk),
+                                                                server_delete);
+        for (int q = 0; q < P; ++q)
+            server_add(*sv, all[q], static_cast<const double *>(b_dev[q]),
+                       static_cast<double *>(x_dev[q]), q, user_s);
+        std::vector<int64_t> tags(P);
+        std::vector<sem_cg_result> out(P);
+        for (int left = P; left > 0;) {
+            int nd = 0;
+            left = server_step(*sv, tags.data(), out.data(), P, &nd);
+            for (int k = 0; k < nd; ++k) {
+                res[tags[k]] = out[k];
+                breakdown |= out[k].status == 3;
             }
         }
-        for (int q = 0; q < P; ++q) {
-            Mesh &m = *B.meshes[q];
-            Workspace &w64 = cg_workspace(m, true);
-            SEM_HIP(hipMemcpyAsync(x_dev[q], w64.x, sizeof(double) * m.n, hipMemcpyDeviceToDevice, s));
-            res[q] = sem_cg_result{};
-            res[q].iters = total[q];
-            res[q].outer = outer[q];
-            res[q].converged = done[q] == 1;
-            res[q].status = done[q] == 1 ? 1 : (done[q] == 3 ? 3 : (last_stop[q] ? last_stop[q] : 2));
-            res[q].rel_res_recursive = inner_rel[q];
-            res[q].rel_res_true = rel[q];
-            breakdown |= done[q] == 3;
-        }
-        SEM_HIP(hipStreamSynchronize(s));
     } else {
         fail(SEM_EUNSUPPORTED, "batched solves run in SEM_FP32 or SEM_MIXED");
     }
@@ -726,6 +672,15 @@ void batch_delete(BatchImpl *b) { delete b; }
 // launches.  A request's arithmetic and reduction order do not depend on
 // which other requests share its launches, so its result is bitwise that of
 // its own sem_cg_solve.
+//
+// The loop is pipelined over two streams.  Each call of server_step ends by
+// launching the next round of inner iterations (main stream) and returns
+// while it runs; the next call first computes, on the side stream and
+// concurrently with that round, the FP64 outer residuals of the requests
+// that are between inner solves (new ones, and those whose inner solve
+// stopped), decides which are done, then waits for the round, reads the
+// state of every member in one copy, restarts the inner solves of the
+// requests that go on (they join the next round) and launches it.
 // ---------------------------------------------------------------------------
 namespace sem {
 
@@ -735,7 +690,8 @@ struct ServerReq {
     const double *b = nullptr;
     double *x = nullptr;
     int64_t tag = 0;
-    int phase = 0;          // 0: outer residual pending; 1: inner CG running
+    int phase = 0;          // 0: outer residual pending; 1: inner CG running (member of
+                            // the round in flight); 2: to restart its inner solve
     int outer = 0, total = 0, last_stop = 0;
     bool broken = false;    // the inner CG broke down
     double rel = 0.0, inner_rel = 0.0;
@@ -744,12 +700,23 @@ struct ServerReq {
 struct ServerImpl {
     sem_cg_opts o{};
     int round_iters = 16;
-    BatchImpl batch;
+    BatchImpl batch;                    // its stream is the main stream
+    hipStream_t side = nullptr;         // request set-up, outer residuals, result copies
+    hipEvent_t ev_side = nullptr, ev_round = nullptr;
+    bool round_in_flight = false;
     std::vector<ServerReq> reqs;
     uint64_t next_uid = 1;
     std::vector<uint64_t> batch_uids;   // requests the batch tables were built for
+    std::vector<uint64_t> round_uids;   // members of the round in flight, in table order
     double inner_tol = 1e-5;
     int max_outer = 20, inner_cap = 100000;
+
+    ~ServerImpl() {
+        (void)hipDeviceSynchronize();
+        if (ev_side) (void)hipEventDestroy(ev_side);
+        if (ev_round) (void)hipEventDestroy(ev_round);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 ServerImpl *server_new(const sem_cg_opts &o, int round_iters) {
@@ -766,6 +733,9 @@ ServerImpl *server_new(const sem_cg_opts &o, int round_iters) {
     SEM_HIP(hipGetDevice(&sv->batch.device));
     SEM_HIP(hipStreamCreateWithFlags(&sv->batch.stream, hipStreamNonBlocking));
     SEM_HIP(hipEventCreateWithFlags(&sv->batch.ev, hipEventDisableTiming));
+    SEM_HIP(hipStreamCreateWithFlags(&sv->side, hipStreamNonBlocking));
+    SEM_HIP(hipEventCreateWithFlags(&sv->ev_side, hipEventDisableTiming));
+    SEM_HIP(hipEventCreateWithFlags(&sv->ev_round, hipEventDisableTiming));
     sv->batch.rebuild({});
     return sv.release();
 }
@@ -780,9 +750,10 @@ void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag
     if (m->device != sv.batch.device) fail(SEM_EINVAL, "the mesh lives on another device");
     if (sv.o.geom == SEM_G_PRECOMPUTED && !m->G32)
         fail(SEM_EUNSUPPORTED, "precomputed FP32 G was not built for the mesh");
-    hipStream_t s = sv.batch.stream;
-    // b and x may still be in flight on the caller's stream: the server's
-    // stream waits for everything enqueued there so far.
+    // the request's set-up runs on the side stream (a round may be in
+    // flight on the main one); b and x may still be in flight on the
+    // caller's stream, which the side stream waits for
+    hipStream_t s = sv.side;
     SEM_HIP(hipEventRecord(sv.batch.ev, user_s));
     SEM_HIP(hipStreamWaitEvent(s, sv.batch.ev, 0));
     Workspace &w64 = cg_workspace(*m, true);
@@ -800,25 +771,32 @@ void server_add(ServerImpl &sv, Mesh *m, const double *b, double *x, int64_t tag
     sv.reqs.push_back(r);
 }
 
-// One round.  Returns the number of requests still in the server; finished
+// One step.  Returns the number of requests still in the server; finished
 // requests are written to (tags, results) up to cap (the rest stay queued
-// as finished and are returned by the next call).
+// as finished and are returned by the next call).  The round it launches
+// is still running when it returns.
 int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, int *n_done) {
-    hipStream_t s = sv.batch.stream;
+    hipStream_t s = sv.batch.stream, s2 = sv.side;
     const bool otf = sv.o.geom == SEM_G_ON_THE_FLY;
     *n_done = 0;
-    // 1. outer residuals of the requests whose inner solve finished (or new)
+    // 1. outer FP64 residuals of the requests between inner solves, on the
+    // side stream while the round launched by the previous step runs
     bool any_outer = false;
     for (ServerReq &r : sv.reqs) {
         if (r.phase != 0) continue;
         any_outer = true;
         Workspace &w64 = cg_workspace(*r.m, true);
-        api_apply_A64(*r.m, static_cast<const double *>(w64.x), static_cast<double *>(w64.w), s);
+        api_apply_A64(*r.m, static_cast<const double *>(w64.x), static_cast<double *>(w64.w), s2);
         launch_residual64(*r.m, r.b, static_cast<const double *>(w64.w),
-                          static_cast<double *>(w64.r), w64.dval + 0, w64.part_vec, s);
-        SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                          static_cast<double *>(w64.r), w64.dval + 0, w64.part_vec, s2);
+        SEM_HIP(hipMemcpyAsync(w64.h_val, w64.dval, 2 * sizeof(double), hipMemcpyDeviceToHost, s2));
     }
-    if (any_outer) SEM_HIP(hipStreamSynchronize(s));
+    if (any_outer) {
+        SEM_HIP(hipEventRecord(sv.ev_side, s2));
+        SEM_HIP(hipEventSynchronize(sv.ev_side));
+    }
+    // 2. the stopping test of those requests: finished ones copy their x
+    // out (side stream) and leave; the others will restart their inner solve
     std::vector<ServerReq> keep;
     for (ServerReq &r : sv.reqs) {
         if (r.phase == 0) {
@@ -831,7 +809,7 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
             else if (r.outer >= sv.max_outer) done = 2;
             if (done && *n_done < cap) {
                 SEM_HIP(hipMemcpyAsync(r.x, w64.x, sizeof(double) * r.m->n,
-                                       hipMemcpyDeviceToDevice, s));
+                                       hipMemcpyDeviceToDevice, s2));
                 sem_cg_result &o = results[*n_done];
                 o = sem_cg_result{};
                 o.iters = r.total;
@@ -844,27 +822,62 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
                 ++*n_done;
                 continue;
             }
-            if (done) {          // no room to report it: keep it for the next call
-                keep.push_back(r);
-                continue;
-            }
-            // start the inner FP32 solve of A d = r / ||r||_c
-            Workspace &w32 = cg_workspace(*r.m, false);
-            float *b32 = static_cast<float *>(w32.b);
-            launch_scale_to_f32(r.m->n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
-            // the stream was synchronised after the outer residuals, and
-            // this request's pinned state is not in use: no further sync
-            set_state(*r.m, true, refine_inner_tol(sv.inner_tol, sv.o.tol, r.rel), sv.inner_cap,
-                      0, s, true);
-            SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * r.m->n, s));
-            launch_cg_init<float>(*r.m, b32, nullptr, static_cast<float *>(w32.r),
-                                  static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
-            r.phase = 1;
+            if (!done) r.phase = 2;
+            // done but no room to report it: kept (phase 0) for the next call
         }
         keep.push_back(r);
     }
     sv.reqs.swap(keep);
-    // 2. a round of batched inner iterations
+    // 3. the round in flight: wait for it and read every member's state
+    // (gathered into one array at its end)
+    if (sv.round_in_flight) {
+        SEM_HIP(hipEventSynchronize(sv.ev_round));
+        sv.round_in_flight = false;
+        for (ServerReq &r : sv.reqs) {
+            if (r.phase != 1) continue;
+            const auto it = std::find(sv.round_uids.begin(), sv.round_uids.end(), r.uid);
+            if (it == sv.round_uids.end()) fail(SEM_EDEVICE, "a running request missed its round");
+            const StateRow h = sv.batch.h_states[it - sv.round_uids.begin()];
+            if (!h.stop) continue;
+            Workspace &w32 = cg_workspace(*r.m, false);
+            Workspace &w64 = cg_workspace(*r.m, true);
+            r.total += h.iter;
+            r.last_stop = h.stop;
+            r.inner_rel = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;
+            if (h.stop == 3) {
+                r.broken = true;
+            } else {
+                // the round is complete: x64 += ||r||_c d on the side
+                // stream, ahead of this request's next outer residual there
+                launch_x_flush<float>(*r.m, static_cast<float *>(w32.x),
+                                      static_cast<const float *>(w32.p), w32.st, s2);
+                launch_axpy_from_f32(r.m->n, static_cast<double *>(w64.x), w64.dval + 0,
+                                     static_cast<const float *>(w32.x), s2);
+                ++r.outer;
+            }
+            r.phase = 0;   // next step: outer residual and the stopping test
+        }
+    }
+    // 4. restart the inner FP32 solves of A d = r / ||r||_c that go on, on
+    // the main stream ahead of the next round (the residual they start from
+    // is complete: the side stream was waited for above; no round in
+    // flight touches their state)
+    for (ServerReq &r : sv.reqs) {
+        if (r.phase != 2) continue;
+        Workspace &w32 = cg_workspace(*r.m, false);
+        Workspace &w64 = cg_workspace(*r.m, true);
+        float *b32 = static_cast<float *>(w32.b);
+        launch_scale_to_f32(r.m->n, static_cast<const double *>(w64.r), w64.dval + 0, b32, s);
+        set_state(*r.m, true, refine_inner_tol(sv.inner_tol, sv.o.tol, r.rel), sv.inner_cap, 0,
+                  s, true);
+        SEM_HIP(hipMemsetAsync(w32.x, 0, sizeof(float) * r.m->n, s));
+        launch_cg_init<float>(*r.m, b32, nullptr, static_cast<float *>(w32.r),
+                              static_cast<float *>(w32.p), w32.st, w32.part_vec, s);
+        r.phase = 1;
+    }
+    // 5. launch the next round for every request in its inner solve (the
+    // tables rebuilt when the member set changed), with the gather of all
+    // members' states at its end; it runs while the caller goes on
     std::vector<Mesh *> inner;
     std::vector<uint64_t> inner_uids;
     for (ServerReq &r : sv.reqs)
@@ -878,30 +891,13 @@ int server_step(ServerImpl &sv, int64_t *tags, sem_cg_result *results, int cap, 
             sv.batch_uids = inner_uids;
         }
         for (int c = 0; c < sv.round_iters; ++c) sv.batch.enqueue_iteration(otf, s);
-        sv.batch.read_states();
-        int q = 0;
-        for (ServerReq &r : sv.reqs) {
-            if (r.phase != 1) continue;
-            const StateRow h = sv.batch.h_states[q++];   // read for every member at once
-            if (!h.stop) continue;
-            Workspace &w32 = cg_workspace(*r.m, false);
-            Workspace &w64 = cg_workspace(*r.m, true);
-            r.total += h.iter;
-            r.last_stop = h.stop;
-            r.inner_rel = h.rho0 > 0 ? std::sqrt(h.rr / h.rho0) : 0.0;
-            if (h.stop == 3) {
-                r.broken = true;
-            } else {
-                launch_x_flush<float>(*r.m, static_cast<float *>(w32.x),
-                                      static_cast<const float *>(w32.p), w32.st, s);
-                launch_axpy_from_f32(r.m->n, static_cast<double *>(w64.x), w64.dval + 0,
-                                     static_cast<const float *>(w32.x), s);
-                ++r.outer;
-            }
-            r.phase = 0;   // next round: outer residual and the stopping test
-        }
+        sv.batch.enqueue_read_states();
+        SEM_HIP(hipEventRecord(sv.ev_round, s));
+        sv.round_uids = inner_uids;
+        sv.round_in_flight = true;
     }
-    SEM_HIP(hipStreamSynchronize(s));
+    // the finished requests' x copies (and the set-up of new ones) are done
+    SEM_HIP(hipStreamSynchronize(s2));
     return (int)sv.reqs.size();
 }
 

@@ -84,10 +84,16 @@ def test_batch_fp32_tolerance_equals_solo_and_oracle():
     bs = [to_dev(v, torch.float32) for v in bh]
     batch = sem.Batch(gms)
     xs, res = batch.solve(bs, prec=sem.FP32, tol=1e-5, max_iter=5000)
+    # the problems stop at different iterations, so stopped ones leave the
+    # launches during the solve; a second solve on the same batch (its full
+    # member list restored) gives the same results
+    assert len({r["iters"] for r in res}) > 1
+    xs2, res2 = batch.solve(bs, prec=sem.FP32, tol=1e-5, max_iter=5000)
     for q, gm in enumerate(gms):
         xq, rq = gm.cg_solve(bs[q], prec=sem.FP32, tol=1e-5, max_iter=5000)
         assert res[q]["iters"] == rq["iters"] and res[q]["converged"] == 1
         assert torch.equal(xs[q], xq)
+        assert torch.equal(xs2[q], xq) and res2[q]["iters"] == rq["iters"]
     # one problem against the oracle's converged solution
     pr = oracle.Problem(boxes[1])
     xo, _, _ = pr.cg(bh[1], tol=1e-12, max_iter=20000)
@@ -111,7 +117,14 @@ def test_batch_mixed_equals_solo(geom):
         assert torch.equal(xs[q], xq), q
         assert res[q]["rel_res_true"] <= 1e-8
     pr = oracle.Problem(boxes[2])
-    assert pr.true_rel_residual(to_host(bs[2]), to_host(xs[2])) < 1.1e-8
+    bo, _ = pr.rhs_manufactured()           # the oracle's own right-hand side
+    assert pr.true_rel_residual(bo, to_host(xs[2])) < 1.1e-8
+    # an FP32 solve after the mixed one on the same batch still equals solo
+    b32 = [to_dev(random_global_rhs(b, seed=5 + q), torch.float32) for q, b in enumerate(boxes)]
+    x32, r32 = batch.solve(b32, prec=sem.FP32, geom=geom, fixed_iters=9)
+    for q, gm in enumerate(gms):
+        xq, _ = gm.cg_solve(b32[q], prec=sem.FP32, geom=geom, fixed_iters=9)
+        assert torch.equal(x32[q], xq), q
     batch.close()
 
 
