@@ -400,8 +400,29 @@ def main(argv=None):
         u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n).astype(np.float32),
                             device="cuda")
         ms = {g: time_ax(gm, u, g) for g in ("pre", "otf")}
-        return _emit({"metric": "local operator alone, median of 50 launches",
-                      "ax_pre_ms": ms["pre"], "ax_otf_ms": ms["otf"], "n_local": n,
+        # the stand-alone gather-scatter (in place, with the mask) in FP32
+        # and FP64, on a fresh copy of u before every timed launch
+        gs_ms = {}
+        for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+            src = u.to(dt)
+            w = torch.empty_like(src)
+            ts = []
+            for rep in range(55):
+                w.copy_(src)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                gm.gs(w, mask=True)
+                e1.record()
+                if rep >= 5:
+                    ts.append((e0, e1))
+            torch.cuda.synchronize()
+            gs_ms[name] = sorted(a.elapsed_time(b_) for a, b_ in ts)[len(ts) // 2]
+        info = gm.info()
+        return _emit({"metric": "local operator and gather-scatter alone, median of 50 launches",
+                      "ax_pre_ms": ms["pre"], "ax_otf_ms": ms["otf"],
+                      "gs_fp32_ms": gs_ms["fp32"], "gs_fp64_ms": gs_ms["fp64"],
+                      "n_local": n, "n_shared": info["n_shared"],
                       "config": {"workload": f"{nel}^3 N={N} +-10% deformed, FP32"}})
 
     log("bench: warmup")
@@ -1222,7 +1243,13 @@ def run_config9(args):
     dst = torch.empty_like(src)
     t_copy = timed(lambda: dst.copy_(src))
     copy_bps = 2 * src.numel() * 4 / t_copy
-    del src, dst
+    # one-direction context for the kernels' fractions of the 8 TB/s peak:
+    # torch's sum of the 1 GiB vector (reads) and torch's fill (writes); the
+    # sum is torch's reduction, not a read-ceiling measurement
+    acc = torch.empty((), dtype=torch.float32, device="cuda")
+    read_bps = src.numel() * 4 / timed(lambda: torch.sum(src, 0, out=acc))
+    write_bps = dst.numel() * 4 / timed(lambda: dst.fill_(1.0))
+    del src, dst, acc
     g = torch.Generator(device="cpu").manual_seed(RHS_SEED)
     perm = torch.randperm(n, generator=g).to("cuda")
     v = torch.rand(n, device="cuda")
@@ -1317,6 +1344,8 @@ def run_config9(args):
                   "unit": "words/cycle (beta_gs, FP32 remat, pass schedule)",
                   "higher_is_better": True, "rows": rows,
                   "machine": {"clock_hz": CLOCK_HZ, "copy_GBps": copy_bps / 1e9,
+                              "torch_sum_read_GBps": read_bps / 1e9,
+                              "torch_fill_write_GBps": write_bps / 1e9,
                               "random_gather_scatter_Gwords_per_s": rand_wps / 1e9,
                               "hbm_peak_words_per_cycle_fp32": HBM_PEAK_GBS * 1e9 / 4 / CLOCK_HZ},
                   "dtype": "f32/f64", "data": "synthetic",
