@@ -155,11 +155,14 @@ __device__ __forceinline__ void gs_sums_logical_block(const GsClasses &cls, int6
     }
 }
 
-// One logical block lb of a mesh's gather-scatter (uniform across the block).
+// The logical block at position lb of a gather-scatter launch (uniform
+// across the block), in the class-major block numbering after the mesh's
+// block order, if it has one.
 template <typename T>
 __device__ __forceinline__ void gs_logical_block(const GsClasses &cls, int64_t lb,
                                                  const int32_t *__restrict__ idx,
                                                  T *__restrict__ w) {
+    if (cls.lb_order) lb = cls.lb_order[lb];
     int c = 0;
     while (c + 1 < cls.ncls && lb >= cls.blk0[c + 1]) ++c;
     const int M = cls.M[c];

@@ -104,6 +104,13 @@ struct GsClasses {
     int64_t ng[kMaxGsClasses];     // groups in this class
     int64_t io[kMaxGsClasses];     // offset of the class in gs_idx
     int64_t blk0[kMaxGsClasses];   // first block of the class in a gs launch
+    // gather-scatter launches only (null: identity): DEVICE int32 [blocks],
+    // the class-major logical block that position b of a launch runs; the
+    // blocks sorted by the first local index of their first group, so the
+    // classes of one region of the mesh run together.  A permutation of all
+    // blocks: only launches that cover every block may apply it (the group
+    // sums over a sub-range of classes do not).
+    const int32_t *lb_order = nullptr;
 };
 void gs_classes_finish(GsClasses &c);
 int64_t gs_total_blocks(const GsClasses &c);   // logical blocks of a whole gather-scatter
@@ -149,6 +156,7 @@ struct Mesh {
     double *B64 = nullptr;        // [E][P3] mass w_q |J_q|
     uint8_t *mcode = nullptr;     // [n]: multiplicity | Dirichlet bit
     int32_t *gs_idx = nullptr;    // [n_shared], class-major, groups of M ascending indices
+    int32_t *gs_lb_order = nullptr;   // gs.lb_order's array
     int32_t *dir_idx = nullptr;   // [n_dir]
     // Shared sums inside the CG update (used when every shared point lies on
     // the surface of its element's P^3 block): gsrc[l] is the other copy of
@@ -218,6 +226,7 @@ struct HostTables {
     GsClasses gs{};
     std::vector<uint8_t> mcode;     // [n]
     std::vector<int32_t> gs_idx;    // class-major ascending member lists
+    std::vector<int32_t> gs_lb_order;  // see GsClasses::lb_order
     std::vector<int32_t> dir_idx;   // Dirichlet local points
     bool gs_in_update = false;      // every shared point on its element's surface
     int64_t n_groups_multi = 0;     // groups with more than two copies

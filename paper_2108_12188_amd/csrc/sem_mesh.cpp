@@ -30,9 +30,15 @@ void upload(T *dst, const T *src, size_t count, hipStream_t s) {
     if (count) SEM_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// The gather-scatter runs its blocks in the order of GsClasses::lb_order
+// (0: class-major order, for comparison).
+#ifndef SEM_GS_BLOCK_ORDER
+#define SEM_GS_BLOCK_ORDER 1
+#endif
+
 void free_mesh_arrays(Mesh *m) {
     void *ptrs[] = {m->vert64,     m->vert32,  m->G32,     m->G64,       m->B64,
-                    m->mcode,      m->gs_idx,  m->dir_idx, m->gsrc,
+                    m->mcode,      m->gs_idx,  m->gs_lb_order, m->dir_idx, m->gsrc,
                     m->wedge_idx,  m->basis_blob, m->scratch, m->state,   m->minv64,
                     m->minv32,     m->erec,    m->pos_tab, m->ewedge_idx};
     for (void *p : ptrs)
@@ -156,6 +162,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         if (flags & SEM_MESH_G_FP64) m->G64 = dev_alloc<double>(*m, (size_t)n * 6);
         m->mcode = dev_alloc<uint8_t>(*m, (size_t)n);
         m->gs_idx = dev_alloc<int32_t>(*m, t.gs_idx.size());
+        m->gs_lb_order = dev_alloc<int32_t>(*m, t.gs_lb_order.size());
         m->dir_idx = dev_alloc<int32_t>(*m, t.dir_idx.size());
         if (t.gs_in_update && !m->gs_struct) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
         if (t.gsum_wedge) m->wedge_idx = dev_alloc<int32_t>(*m, t.wedge_idx.size());
@@ -195,6 +202,8 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         upload(m->vert32, v32.data(), v32.size(), s);
         upload(m->mcode, t.mcode.data(), t.mcode.size(), s);
         upload(m->gs_idx, t.gs_idx.data(), t.gs_idx.size(), s);
+        upload(m->gs_lb_order, t.gs_lb_order.data(), t.gs_lb_order.size(), s);
+        if (SEM_GS_BLOCK_ORDER) m->gs.lb_order = m->gs_lb_order;
         upload(m->dir_idx, t.dir_idx.data(), t.dir_idx.size(), s);
         if (t.gs_in_update && !m->gs_struct) upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
         if (t.gsum_wedge) upload(m->wedge_idx, t.wedge_idx.data(), t.wedge_idx.size(), s);

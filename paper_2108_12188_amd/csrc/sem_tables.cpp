@@ -307,6 +307,24 @@ void build_tables(int64_t E, int N, const int64_t *gid, const uint8_t *dir, Host
     while (gs_idx.size() % 8) gs_idx.push_back(0);
     gs_classes_finish(cls);
     t.gs = cls;
+    // order of the gather-scatter's logical blocks: by the first local index
+    // of each block's first group (ties: class-major order), so that one
+    // launch position range, which one XCD runs, covers every class of one
+    // region of the mesh instead of each class sweeping the whole mesh
+    {
+        const int64_t nblk = gs_total_blocks(cls);
+        std::vector<int64_t> key((size_t)nblk);
+        for (int c = 0; c < cls.ncls; ++c) {
+            const int64_t gpb = gsb::gs_per_block(cls.M[c]);
+            const int64_t nb = (cls.ng[c] + gpb - 1) / gpb;
+            for (int64_t k = 0; k < nb; ++k)
+                key[(size_t)(cls.blk0[c] + k)] = gs_idx[(size_t)(cls.io[c] + k * gpb * cls.M[c])];
+        }
+        t.gs_lb_order.resize((size_t)nblk);
+        std::iota(t.gs_lb_order.begin(), t.gs_lb_order.end(), 0);
+        std::stable_sort(t.gs_lb_order.begin(), t.gs_lb_order.end(),
+                         [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
     // classes are in ascending m: the groups of more than two copies are the
     // gather-scatter blocks from the first class with M > 2 on
     t.n_groups_multi = n_multi;

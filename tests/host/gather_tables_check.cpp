@@ -10,7 +10,9 @@
 // than 1, 2, 4, 8> gsum_wedge=<0|1> table_free=<0|1> checked_tf=<points>"
 // and exits 0, or names the first failing point and exits 1.  The
 // table-free form (odd N) is checked the same way: every point's decoded
-// code and value against its copies' ascending-order sum, bitwise.
+// code and value against its copies' ascending-order sum, bitwise.  The
+// gather-scatter's block order must be a permutation of its logical blocks
+// sorted by each block's first local index ("gs_blocks=<blocks>").
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -20,6 +22,7 @@
 #include <string>
 #include <vector>
 
+#include "../../paper_2108_12188_amd/csrc/sem_gs_body.h"
 #include "../../paper_2108_12188_amd/csrc/sem_vec_body.h"
 
 namespace sem {
@@ -79,6 +82,32 @@ int main(int argc, char **argv) {
     for (l = 0; l < n; ++l) {
         w32[l] = U(rng);
         w64[l] = (double)U(rng) + 1e-9 * (double)U(rng);
+    }
+
+    // the gather-scatter's block order: a permutation of all logical blocks,
+    // whose blocks' first local indices never decrease along it
+    const int64_t nblk = sem::gs_total_blocks(t.gs);
+    {
+        l = -1;
+        CHECK((int64_t)t.gs_lb_order.size() == nblk, "block order holds %lld of %lld blocks",
+              (long long)t.gs_lb_order.size(), (long long)nblk);
+        std::vector<int64_t> first((size_t)nblk, -1);
+        for (int c = 0; c < t.gs.ncls; ++c) {
+            const int64_t gpb = sem::gsb::gs_per_block(t.gs.M[c]);
+            for (int64_t g = 0; g < t.gs.ng[c]; g += gpb)
+                first[(size_t)(t.gs.blk0[c] + g / gpb)] = t.gs_idx[t.gs.io[c] + g * t.gs.M[c]];
+        }
+        std::vector<char> seen((size_t)nblk, 0);
+        int64_t prev = -1;
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int32_t lb = t.gs_lb_order[(size_t)b];
+            CHECK(lb >= 0 && lb < nblk && !seen[(size_t)lb], "block order entry %lld = %d",
+                  (long long)b, lb);
+            seen[(size_t)lb] = 1;
+            CHECK(first[(size_t)lb] >= prev, "block order not by first index at %lld",
+                  (long long)b);
+            prev = first[(size_t)lb];
+        }
     }
 
     int64_t checked = 0, odd_m = 0;
@@ -265,8 +294,9 @@ int main(int argc, char **argv) {
         }
     }
     std::printf("gs_in_update=%d checked=%lld odd_m=%lld gsum_wedge=%d table_free=%d "
-                "checked_tf=%lld\n",
+                "checked_tf=%lld gs_blocks=%lld\n",
                 t.gs_in_update ? 1 : 0, (long long)checked, (long long)odd_m,
-                t.gsum_wedge ? 1 : 0, t.gs_struct ? 1 : 0, (long long)checked_tf);
+                t.gsum_wedge ? 1 : 0, t.gs_struct ? 1 : 0, (long long)checked_tf,
+                (long long)nblk);
     return 0;
 }

@@ -47,6 +47,7 @@ def test_conforming_meshes_gather_in_update(checker, tmp_path, shape, N):
     out = _run(checker, tmp_path, mesh)
     assert out["gs_in_update"] == "1"
     assert int(out["checked"]) == mesh.E * (N + 1) ** 3
+    assert int(out["gs_blocks"]) > 0     # block order checked over every block
     if min(shape) > 1:   # interior edges exist: groups with m > 2 on element edges
         assert out["gsum_wedge"] == "1"
     # odd orders also take the table-free form (P^3 a multiple of 4), checked
