@@ -48,6 +48,20 @@ constexpr bool prefetch_g() {
     return SEM_AX_PREFETCH_G && 6 * kP * sizeof(T) <= 6 * 8 * 4;
 }
 
+// The precomputed factors are read once per application and are the largest
+// stream (24 B of 32 per point in FP32): non-temporal loads keep them from
+// displacing the vectors (u, w and, in CG, r, p, x: 268 MB in FP32) that the
+// next kernels read again from the 256 MB Infinity Cache.  FP64 vectors
+// (537 MB) do not fit it either way, and there the hint costs a little.
+#ifndef SEM_AX_G_STREAM
+#define SEM_AX_G_STREAM 1
+#endif
+template <typename T>
+__device__ __forceinline__ T load_g(const T *p) {
+    if constexpr (SEM_AX_G_STREAM && sizeof(T) == 4) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Kernel-argument copy of the basis: indexed only with compile-time
 // constants, so every access is a scalar load.
 template <typename T>
@@ -170,8 +184,8 @@ __device__ __forceinline__ void point_flux(const ColumnGeom<T> &cg, const BasisK
             g22 = gq[3][k], g23 = gq[4][k], g33 = gq[5][k];
         } else {
             const T *G = Ge + k * P2;
-            g11 = G[0], g12 = G[P3], g13 = G[2 * P3];
-            g22 = G[3 * P3], g23 = G[4 * P3], g33 = G[5 * P3];
+            g11 = load_g(G), g12 = load_g(G + P3), g13 = load_g(G + 2 * P3);
+            g22 = load_g(G + 3 * P3), g23 = load_g(G + 4 * P3), g33 = load_g(G + 5 * P3);
         }
         // fused multiply-adds in a fixed order, so that every kernel (and
         // both engines) rounds this product the same way
@@ -404,7 +418,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
 #pragma unroll
-                    for (int k = 0; k < P; ++k) gq[c][k] = Ge[c * P3 + k * P2];
+                    for (int k = 0; k < P; ++k) gq[c][k] = load_g(Ge + c * P3 + k * P2);
             }
         }
         lds_barrier();
@@ -675,7 +689,7 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
 #pragma unroll
-                    for (int k = 0; k < P; ++k) gq[c][k] = Ge[c * P3 + k * P2];
+                    for (int k = 0; k < P; ++k) gq[c][k] = load_g(Ge + c * P3 + k * P2);
             }
 
             // gradient: k in the column's registers, i and j on pencils
@@ -908,7 +922,7 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
 #pragma unroll
                 for (int cc = 0; cc < 6; ++cc)
 #pragma unroll
-                    for (int k = 0; k < P; ++k) gq[cc][k] = Ge[cc * P3 + k * P2];
+                    for (int k = 0; k < P; ++k) gq[cc][k] = load_g(Ge + cc * P3 + k * P2);
             }
 
             // gradient: i- and j-pencils of sA into sB and sC
