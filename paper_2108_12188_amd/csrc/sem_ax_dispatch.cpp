@@ -25,8 +25,9 @@ SEM_DECL_ORDER(11)
 #undef SEM_DECL_ORDER
 
 #define SEM_DECL_BATCH(N)                                                                      \
-    void ax_batch_order_##N##_f32(bool, bool, const AxArgs<float> *, const int2 *, int64_t, int, \
-                                  const double *, const double *, const double *, hipStream_t);
+    void ax_batch_order_##N##_f32(bool, bool, bool, const AxArgs<float> *, const int2 *,       \
+                                  int64_t, int, const double *, const double *, const double *, \
+                                  hipStream_t);
 SEM_DECL_BATCH(1)
 SEM_DECL_BATCH(2)
 SEM_DECL_BATCH(3)
@@ -40,7 +41,7 @@ SEM_DECL_BATCH(10)
 SEM_DECL_BATCH(11)
 #undef SEM_DECL_BATCH
 
-using FnB = void (*)(bool, bool, const AxArgs<float> *, const int2 *, int64_t, int,
+using FnB = void (*)(bool, bool, bool, const AxArgs<float> *, const int2 *, int64_t, int,
                      const double *, const double *, const double *, hipStream_t);
 static const FnB kFnB[kMaxOrder + 1] = {
     nullptr,           ax_batch_order_1_f32, ax_batch_order_2_f32, ax_batch_order_3_f32,
@@ -211,12 +212,23 @@ void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
     a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma, sh.threads);
 }
 
-void launch_ax_batch(int N, bool otf, bool mfma, const AxArgs<float> *descs, const int2 *blk,
-                     int64_t nblk, int epb, const double *D, const double *xi, const double *w,
+void launch_ax_batch(int N, bool otf, bool mfma, bool stream, const AxArgs<float> *descs,
+                     const int2 *blk, int64_t nblk, int epb, const double *D, const double *xi,
+                     const double *w,
                      hipStream_t s) {
     if (nblk <= 0) return;
-    kFnB[N](otf, mfma, descs, blk, nblk, epb, D, xi, w, s);
+    kFnB[N](otf, mfma, stream, descs, blk, nblk, epb, D, xi, w, s);
     check_hip(hipGetLastError(), "batched ax kernel launch");
+}
+
+int64_t cg_footprint32(const Mesh &m) {
+    const int64_t es = edge_slots(m.N);
+    int64_t b = 16 * m.n;                                  // r, p, x, w
+    if (m.gs_struct) b += m.E * (6 + es) * 8 + 4 * m.n_egroups;   // records, edge sums
+    else if (m.gs_in_update) b += 4 * m.n + 4 * m.n_groups_multi; // table, group sums
+    if (m.gsum_wedge || m.gs_struct) b += m.E * es * 4;    // edge copy
+    b += m.E * 24 * 4 + m.n;                               // vertices, codes
+    return b;
 }
 
 int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override) {

@@ -244,12 +244,36 @@ __device__ __forceinline__ void lds_barrier() {
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 
+// In a CG iteration the search direction p and the solution x are read
+// and written by the CG-fused operator alone, once per iteration, one
+// iteration apart.  When the iteration's FP32 vectors, records and edge
+// copy exceed the 256 MB Infinity Cache (AxArgs::stream, set by the host),
+// those accesses are non-temporal (cache-policy bit NT on the loads,
+// non-temporal stores), so that p and x take no cache space from r, w,
+// the edge copy and the gather records, which the group sums and the
+// update read again within the iteration.  A smaller iteration fits the
+// cache as it is and keeps plain accesses, as do FP64 vectors.
+constexpr int kCpolNt = 2;       // NT bit of the load cache-policy operand
+// The choice is a template argument: a runtime flag lets the compiler merge
+// the two stores into one plain store before the flag is known.
+template <bool NT, typename T>
+__device__ __forceinline__ void store_nt(T *p, T v) {
+    if constexpr (NT && sizeof(T) == 4) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ T load_nt(const T *p) {
+    if constexpr (NT && sizeof(T) == 4) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // The block's nwave waves copy nf floats (a multiple of 4; src and dst
 // 16-byte aligned) from global memory to LDS: every wave moves 64 x 16
 // bytes per instruction, lane q of a wave landing at the wave's (uniform)
 // LDS base + 16 q.  Completion is tracked by vmcnt.  (The wave count is an
 // argument: the block size lives in memory, and loading it would make the
 // wave wait for all of its outstanding stores.)
+template <int kCpol = 0>
 __device__ __forceinline__ void dma_to_lds(const float *src, float *dst, int nf, int nwave) {
     const int pieces = nf >> 2;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -257,14 +281,18 @@ __device__ __forceinline__ void dma_to_lds(const float *src, float *dst, int nf,
     for (int q0 = wave * 64; q0 < pieces; q0 += nwave * 64) {
         if (q0 + lane < pieces)
             __builtin_amdgcn_global_load_lds((glb_void_t *)(src + 4 * (q0 + lane)),
-                                             (lds_void_t *)(dst + 4 * q0), 16, 0, 0);
+                                             (lds_void_t *)(dst + 4 * q0), 16, 0, kCpol);
     }
+}
+template <bool NT>
+__device__ __forceinline__ void dma_to_lds_nt(const float *src, float *dst, int nf, int nwave) {
+    dma_to_lds<NT ? kCpolNt : 0>(src, dst, nf, nwave);
 }
 
 // Tiles vb, vb + vgrid, vb + 2 vgrid, ... of one problem; in the fused mode
 // the block's partial goes to a.partial[vb].  Every thread of the block
 // calls it.
-template <typename T, bool OTF, bool FUSED>
+template <typename T, bool OTF, bool FUSED, bool NT = false>
 __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk, int64_t ntiles,
                                         int64_t vb, int64_t vgrid) {
     constexpr int P = kP, P2 = P * P, P3 = P2 * P;
@@ -305,6 +333,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
     // applied here where p_{i-1} is read anyway
     bool xlag = false;
     T aprev = T(0);
+    constexpr bool strm = FUSED && NT;   // p and x non-temporal
     if constexpr (FUSED) {
         beta = (T)a.st->beta;
         xlag = a.x != nullptr && a.st->x_lag != 0;
@@ -330,7 +359,8 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
             const int64_t e0 = tl * a.epb;
             const int nval = (int)(a.E - e0 < a.epb ? a.E - e0 : a.epb);
             dma_to_lds(reinterpret_cast<const float *>(a.u) + e0 * P3, sR, nval * P3, nwave);
-            dma_to_lds(reinterpret_cast<const float *>(a.p) + e0 * P3, sP, nval * P3, nwave);
+            dma_to_lds_nt<strm>(reinterpret_cast<const float *>(a.p) + e0 * P3, sP, nval * P3,
+                               nwave);
             if constexpr (OTF)
                 dma_to_lds(reinterpret_cast<const float *>(a.vert) + e0 * 24, sV, nval * 24,
                            nwave);
@@ -341,7 +371,8 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
             const int64_t e0 = tl * a.epb;
             const int nval = (int)(a.E - e0 < a.epb ? a.E - e0 : a.epb);
             if (xlag)
-                dma_to_lds(reinterpret_cast<const float *>(a.x) + e0 * P3, sX, nval * P3, nwave);
+                dma_to_lds_nt<strm>(reinterpret_cast<const float *>(a.x) + e0 * P3, sX, nval * P3,
+                                   nwave);
         }
     };
     if constexpr (kDma) {
@@ -374,24 +405,28 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
 #pragma unroll
                 for (int k = 0; k < P; ++k) uc[k] = rr[k * P2] + beta * pp[k * P2];
 #pragma unroll
-                for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                for (int k = 0; k < P; ++k) store_nt<strm>(a.p + base + k * P2, uc[k]);
                 if (xlag) {
                     // x was staged in this thread's own slots of the tile,
                     // which the p-update below overwrites
                     const float *const xx = sX + el * P3 + col;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) a.x[base + k * P2] = xx[k * P2] + aprev * pp[k * P2];
+                    for (int k = 0; k < P; ++k)
+                        store_nt<strm>(a.x + base + k * P2, xx[k * P2] + aprev * pp[k * P2]);
                 }
             } else if constexpr (FUSED) {
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     const T r = a.u[base + k * P2];
-                    const T pold = a.p[base + k * P2];
+                    const T pold = load_nt<strm>(a.p + base + k * P2);
                     uc[k] = r + beta * pold;
-                    if (xlag) a.x[base + k * P2] += aprev * pold;
+                    if (xlag)
+                        store_nt<strm>(a.x + base + k * P2,
+                                load_nt<strm>(a.x + base + k * P2) +
+                                    aprev * pold);
                 }
 #pragma unroll
-                for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                for (int k = 0; k < P; ++k) store_nt<strm>(a.p + base + k * P2, uc[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < P; ++k) uc[k] = a.u[base + k * P2];
@@ -506,6 +541,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // two 16-byte-per-lane direct loads, tracked by vmcnt.  The source base is
 // made wave-uniform (scalar base + the lane's constant offset), so the
 // loads hold no per-lane 64-bit address registers.
+template <int kCpol = 0>
 __device__ __forceinline__ void dma_elem_to_lds(const float *src, float *dst) {
     const int lane = (int)(threadIdx.x & 63);
     const uint64_t pa = reinterpret_cast<uint64_t>(src);
@@ -513,10 +549,17 @@ __device__ __forceinline__ void dma_elem_to_lds(const float *src, float *dst) {
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
     const float *su = reinterpret_cast<const float *>(((uint64_t)hi << 32) | lo);
     // the immediate offset (1024 bytes) applies to the global and the LDS
-    // address alike
-    __builtin_amdgcn_global_load_lds((glb_void_t *)(su + 4 * lane), (lds_void_t *)dst, 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((glb_void_t *)(su + 4 * lane), (lds_void_t *)dst, 16, 1024, 0);
+    // address alike; kCpol: the cache-policy bits of the loads
+    __builtin_amdgcn_global_load_lds((glb_void_t *)(su + 4 * lane), (lds_void_t *)dst, 16, 0,
+                                     kCpol);
+    __builtin_amdgcn_global_load_lds((glb_void_t *)(su + 4 * lane), (lds_void_t *)dst, 16, 1024,
+                                     kCpol);
 }
+template <bool NT>
+__device__ __forceinline__ void dma_elem_to_lds_nt(const float *src, float *dst) {
+    dma_elem_to_lds<NT ? kCpolNt : 0>(src, dst);
+}
+
 
 // Element tile in LDS (512 floats): point (i, j, k) at
 //   (i ^ 4 (j >> 2)) + 8 (j ^ (k & 3)) + 64 k.
@@ -582,7 +625,7 @@ __device__ __forceinline__ MfmaPencils mfma_pencils(int q) {
     return pc;
 }
 
-template <bool OTF, bool FUSED>
+template <bool OTF, bool FUSED, bool NT = false>
 __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const BasisK<float> &bk,
                                              int64_t ntiles, int64_t vb, int64_t vgrid) {
     if constexpr (kP == 8) {
@@ -616,6 +659,7 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
         T beta = T(0);
         bool xlag = false;
         T aprev = T(0);
+        constexpr bool strm = FUSED && NT;   // p and x non-temporal
         if constexpr (FUSED) {
             beta = (T)a.st->beta;
             xlag = a.x != nullptr && a.st->x_lag != 0;
@@ -637,8 +681,11 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
         auto stage = [&](int64_t e) {
             if constexpr (kDma) {
                 dma_elem_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR);
-                dma_elem_to_lds(reinterpret_cast<const float *>(a.p) + e * P3, sP);
-                if (xlag) dma_elem_to_lds(reinterpret_cast<const float *>(a.x) + e * P3, sX);
+                dma_elem_to_lds_nt<strm>(
+                    reinterpret_cast<const float *>(a.p) + e * P3, sP);
+                if (xlag)
+                    dma_elem_to_lds_nt<strm>(
+                        reinterpret_cast<const float *>(a.x) + e * P3, sX);
             }
         };
         float vnext = 0.f;
@@ -668,11 +715,12 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
 #pragma unroll
                 for (int k = 0; k < P; ++k) uc[k] = sR[q + k * P2] + beta * sP[q + k * P2];
 #pragma unroll
-                for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                for (int k = 0; k < P; ++k)
+                    store_nt<strm>(a.p + base + k * P2, uc[k]);
                 if (xlag) {
 #pragma unroll
                     for (int k = 0; k < P; ++k)
-                        a.x[base + k * P2] = sX[q + k * P2] + aprev * sP[q + k * P2];
+                        store_nt<strm>(a.x + base + k * P2, sX[q + k * P2] + aprev * sP[q + k * P2]);
                 }
             } else {
 #pragma unroll
@@ -811,7 +859,7 @@ __device__ __forceinline__ void mfma_apply10(const float (&m)[kP], const float (
     }
 }
 
-template <bool OTF, bool FUSED>
+template <bool OTF, bool FUSED, bool NT = false>
 __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const BasisK<float> &bk,
                                                int64_t ntiles, int64_t vb, int64_t vgrid) {
     if constexpr (kP == 10) {
@@ -848,6 +896,7 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
         T beta = T(0);
         bool xlag = false;
         T aprev = T(0);
+        constexpr bool strm = FUSED && NT;   // p and x non-temporal
         if constexpr (FUSED) {
             beta = (T)a.st->beta;
             xlag = a.x != nullptr && a.st->x_lag != 0;
@@ -864,8 +913,9 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
         auto stage = [&](int64_t e) {
             if constexpr (kDma) {
                 dma_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR, P3, 2);
-                dma_to_lds(reinterpret_cast<const float *>(a.p) + e * P3, sP, P3, 2);
-                if (xlag) dma_to_lds(reinterpret_cast<const float *>(a.x) + e * P3, sX, P3, 2);
+                dma_to_lds_nt<strm>(reinterpret_cast<const float *>(a.p) + e * P3, sP, P3, 2);
+                if (xlag)
+                    dma_to_lds_nt<strm>(reinterpret_cast<const float *>(a.x) + e * P3, sX, P3, 2);
             }
         };
         auto stage_vert = [&](int64_t e) {
@@ -895,11 +945,11 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
                 for (int k = 0; k < P; ++k) uc[k] = sR[c + k * P2] + beta * sP[c + k * P2];
                 if (active) {
 #pragma unroll
-                    for (int k = 0; k < P; ++k) a.p[base + k * P2] = uc[k];
+                    for (int k = 0; k < P; ++k) store_nt<strm>(a.p + base + k * P2, uc[k]);
                     if (xlag) {
 #pragma unroll
                         for (int k = 0; k < P; ++k)
-                            a.x[base + k * P2] = sX[c + k * P2] + aprev * sP[c + k * P2];
+                            store_nt<strm>(a.x + base + k * P2, sX[c + k * P2] + aprev * sP[c + k * P2]);
                     }
                 }
             } else {
@@ -1022,45 +1072,46 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
 constexpr int kMfmaThreads = kP == 10 ? 128 : 64;
 constexpr int kMfmaWaves = kP == 10 ? 3 : 4;
 
-template <bool OTF, bool FUSED>
+template <bool OTF, bool FUSED, bool NT>
 __device__ __forceinline__ void ax_mfma_any(const AxArgs<float> &a, const BasisK<float> &bk,
                                             int64_t ntiles, int64_t vb, int64_t vgrid) {
-    if constexpr (kP == 10) ax_mfma10_body<OTF, FUSED>(a, bk, ntiles, vb, vgrid);
-    else ax_mfma_body<OTF, FUSED>(a, bk, ntiles, vb, vgrid);
+    if constexpr (kP == 10) ax_mfma10_body<OTF, FUSED, NT>(a, bk, ntiles, vb, vgrid);
+    else ax_mfma_body<OTF, FUSED, NT>(a, bk, ntiles, vb, vgrid);
 }
 
-template <bool OTF, bool FUSED>
+// NT: the CG-fused form with p and x non-temporal (AxArgs::stream)
+template <bool OTF, bool FUSED, bool NT = false>
 __global__ void __launch_bounds__(kMfmaThreads, kMfmaWaves)
 ax_mfma_kernel(const AxArgs<float> a, const BasisK<float> bk, int64_t ntiles) {
-    ax_mfma_any<OTF, FUSED>(a, bk, ntiles, blockIdx.x, gridDim.x);
+    ax_mfma_any<OTF, FUSED, NT>(a, bk, ntiles, blockIdx.x, gridDim.x);
 }
 
-template <bool OTF>
+template <bool OTF, bool NT = false>
 __global__ void __launch_bounds__(kMfmaThreads, kMfmaWaves)
 ax_mfma_batch_kernel(const AxArgs<float> *__restrict__ descs, const int2 *__restrict__ blk,
                      const BasisK<float> bk) {
     const int2 pv = blk[blockIdx.x];
     const AxArgs<float> a = descs[pv.x];
-    ax_mfma_any<OTF, true>(a, bk, a.E, pv.y, a.vgrid);
+    ax_mfma_any<OTF, true, NT>(a, bk, a.E, pv.y, a.vgrid);
 }
 
-template <typename T, bool OTF, bool FUSED>
+template <typename T, bool OTF, bool FUSED, bool NT = false>
 __global__ void __launch_bounds__(512, ax_min_waves<T>())
 ax_kernel(const AxArgs<T> a, const BasisK<T> bk, int64_t ntiles) {
-    ax_body<T, OTF, FUSED>(a, bk, ntiles, blockIdx.x, gridDim.x);
+    ax_body<T, OTF, FUSED, NT>(a, bk, ntiles, blockIdx.x, gridDim.x);
 }
 
 // Many problems of this order in one launch: block b runs virtual block
 // blk[b].y of problem blk[b].x, exactly the block that problem's own launch
 // would run, so every problem's partials (and results) are bitwise those
 // of its solo solve.
-template <typename T, bool OTF>
+template <typename T, bool OTF, bool NT = false>
 __global__ void __launch_bounds__(512, ax_min_waves<T>())
 ax_batch_kernel(const AxArgs<T> *__restrict__ descs, const int2 *__restrict__ blk,
                 const BasisK<T> bk) {
     const int2 pv = blk[blockIdx.x];
     const AxArgs<T> a = descs[pv.x];
-    ax_body<T, OTF, true>(a, bk, (a.E + a.epb - 1) / a.epb, pv.y, a.vgrid);
+    ax_body<T, OTF, true, NT>(a, bk, (a.E + a.epb - 1) / a.epb, pv.y, a.vgrid);
 }
 
 template <typename T>
@@ -1076,19 +1127,29 @@ BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
 
 template <typename T, bool OTF, bool FUSED>
 void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s) {
+    constexpr bool kMayStream = FUSED && sizeof(T) == 4;
+    const bool nt = kMayStream && a.stream != 0;
     if constexpr (sizeof(T) == 4 && (kP == 8 || kP == 10)) {
         if (a.mfma) {
             // one element per block (one wave at N = 7, two at N = 9)
-            hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid),
-                               dim3(kMfmaThreads), 0, s, a, bk, a.E);
+            if (nt)
+                hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED, kMayStream>), dim3((unsigned)grid),
+                                   dim3(kMfmaThreads), 0, s, a, bk, a.E);
+            else
+                hipLaunchKernelGGL((ax_mfma_kernel<OTF, FUSED>), dim3((unsigned)grid),
+                                   dim3(kMfmaThreads), 0, s, a, bk, a.E);
             return;
         }
     }
     const int threads = ((a.epb * kP * kP + 63) / 64) * 64;
     const size_t lds = ax_lds_bytes<T, OTF, FUSED>(a.epb);
     const int64_t ntiles = (a.E + a.epb - 1) / a.epb;
-    hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED>), dim3((unsigned)grid), dim3(threads), lds, s, a,
-                       bk, ntiles);
+    if (nt)
+        hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED, kMayStream>), dim3((unsigned)grid),
+                           dim3(threads), lds, s, a, bk, ntiles);
+    else
+        hipLaunchKernelGGL((ax_kernel<T, OTF, FUSED>), dim3((unsigned)grid), dim3(threads), lds,
+                           s, a, bk, ntiles);
 }
 
 }  // namespace
@@ -1110,19 +1171,17 @@ static void ax_entry(bool otf, AxMode mode, const AxArgs<T> &a, const double *D,
     }
 }
 
-template <typename T>
-static void ax_batch_entry(bool otf, bool mfma, const AxArgs<T> *descs, const int2 *blk,
-                           int64_t nblk, int epb, const double *D, const double *xi,
-                           const double *w, hipStream_t s) {
-    const BasisK<T> bk = make_basis<T>(D, xi, w);
+template <typename T, bool NT>
+static void ax_batch_launch(bool otf, bool mfma, const AxArgs<T> *descs, const int2 *blk,
+                            int64_t nblk, int epb, const BasisK<T> &bk, hipStream_t s) {
     if constexpr (sizeof(T) == 4 && (kP == 8 || kP == 10)) {
         if (mfma) {
             // static LDS only
             if (otf)
-                hipLaunchKernelGGL((ax_mfma_batch_kernel<true>), dim3((unsigned)nblk),
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<true, NT>), dim3((unsigned)nblk),
                                    dim3(kMfmaThreads), 0, s, descs, blk, bk);
             else
-                hipLaunchKernelGGL((ax_mfma_batch_kernel<false>), dim3((unsigned)nblk),
+                hipLaunchKernelGGL((ax_mfma_batch_kernel<false, NT>), dim3((unsigned)nblk),
                                    dim3(kMfmaThreads), 0, s, descs, blk, bk);
             return;
         }
@@ -1131,18 +1190,28 @@ static void ax_batch_entry(bool otf, bool mfma, const AxArgs<T> *descs, const in
     const size_t lds_otf = ax_lds_bytes<T, true, true>(epb);
     const size_t lds_pre = ax_lds_bytes<T, false, true>(epb);
     if (otf)
-        hipLaunchKernelGGL((ax_batch_kernel<T, true>), dim3((unsigned)nblk), dim3(threads),
+        hipLaunchKernelGGL((ax_batch_kernel<T, true, NT>), dim3((unsigned)nblk), dim3(threads),
                            lds_otf, s, descs, blk, bk);
     else
-        hipLaunchKernelGGL((ax_batch_kernel<T, false>), dim3((unsigned)nblk), dim3(threads),
+        hipLaunchKernelGGL((ax_batch_kernel<T, false, NT>), dim3((unsigned)nblk), dim3(threads),
                            lds_pre, s, descs, blk, bk);
 }
 
-void SEM_CAT3(ax_batch_order_, SEM_ORDER, _f32)(bool otf, bool mfma, const AxArgs<float> *descs,
-                                                 const int2 *blk, int64_t nblk, int epb,
-                                                 const double *D, const double *xi,
-                                                 const double *w, hipStream_t s) {
-    ax_batch_entry<float>(otf, mfma, descs, blk, nblk, epb, D, xi, w, s);
+template <typename T>
+static void ax_batch_entry(bool otf, bool mfma, bool stream, const AxArgs<T> *descs,
+                           const int2 *blk, int64_t nblk, int epb, const double *D,
+                           const double *xi, const double *w, hipStream_t s) {
+    const BasisK<T> bk = make_basis<T>(D, xi, w);
+    if (stream) ax_batch_launch<T, true>(otf, mfma, descs, blk, nblk, epb, bk, s);
+    else ax_batch_launch<T, false>(otf, mfma, descs, blk, nblk, epb, bk, s);
+}
+
+void SEM_CAT3(ax_batch_order_, SEM_ORDER, _f32)(bool otf, bool mfma, bool stream,
+                                                 const AxArgs<float> *descs, const int2 *blk,
+                                                 int64_t nblk, int epb, const double *D,
+                                                 const double *xi, const double *w,
+                                                 hipStream_t s) {
+    ax_batch_entry<float>(otf, mfma, stream, descs, blk, nblk, epb, D, xi, w, s);
 }
 
 void SEM_CAT3(ax_order_, SEM_ORDER, _f32)(bool otf, AxMode mode, const AxArgs<float> &a,

@@ -186,6 +186,7 @@ struct BatchImpl {
         int64_t nblk = 0;
     };
     std::vector<OrderGroup> groups[2];              // [precomputed, on the fly]
+    bool stream_vectors = false;                    // p and x non-temporal (footprint)
     struct BlkTable {
         int2 *blk = nullptr;
         size_t cap = 0;
@@ -246,8 +247,8 @@ struct BatchImpl {
         if (count() == 0) return;
         const int f = otf ? 1 : 0;
         for (const auto &g : groups[f]) {
-            launch_ax_batch(g.N, otf, g.mfma, d_ax[f], g.blk, g.nblk, g.epb, order_D[g.N].data(),
-                            order_xi[g.N].data(), order_w[g.N].data(), s);
+            launch_ax_batch(g.N, otf, g.mfma, stream_vectors, d_ax[f], g.blk, g.nblk, g.epb,
+                            order_D[g.N].data(), order_xi[g.N].data(), order_w[g.N].data(), s);
         }
         if (n_gs_blk > 0)
             hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)n_gs_blk), dim3(gsb::kGsThreads), 0,
@@ -374,12 +375,18 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     std::map<int, int> order_epb[2];
     std::map<int, bool> order_mfma[2];
     ensure_cap(d_cls, cap_cls, count, bytes);
+    // one batched iteration touches every member's vectors
+    int64_t footprint = 0;
+    for (int q = 0; q < count; ++q) footprint += cg_footprint32(*ms[q]);
+    const int stream = cg_streams_vectors(footprint) ? 1 : 0;
+    stream_vectors = stream != 0;
     for (int q = 0; q < count; ++q) {
         Mesh &m = *ms[q];
         Workspace &ws = cg_workspace(m, false);
         for (int otf = 0; otf < 2; ++otf) {
             AxArgs<float> a{};
             ax_batch_desc(m, otf != 0, a);
+            a.stream = stream;
             a.u = static_cast<float *>(ws.r);
             a.p = static_cast<float *>(ws.p);
             a.w = static_cast<float *>(ws.w);

@@ -280,6 +280,8 @@ struct AxArgs {
                                 // x += alpha p_old (previous iteration's step)
     int mfma;                   // host side: launch the matrix-core form (FP32,
                                 // N = 7; one element per wave-sized block)
+    int stream;                 // CgFused FP32: p and x accesses non-temporal
+                                // (cg_streams_vectors of the iteration's footprint)
 };
 
 // Jacobi preconditioning in the CG update (preconditioned CG, Sec. 3.2;
@@ -314,12 +316,23 @@ int ax_shape_generation();
 template <typename T>
 void launch_ax(const Mesh &m, bool otf, AxMode mode, AxArgs<T> a, hipStream_t s);
 int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override);
+// Bytes an FP32 CG iteration of mesh m keeps touching: r, p, x, w, the
+// gather records or table, the operator's edge copy, vertices and codes.
+int64_t cg_footprint32(const Mesh &m);
+// The CG-fused operator reads and writes p and x non-temporally when the
+// iteration (of one mesh, or of a whole batch) exceeds the 256 MB Infinity
+// Cache, so that the cache keeps what the rest of the iteration reads again.
+constexpr int64_t kInfinityCacheBytes = int64_t(256) << 20;
+inline bool cg_streams_vectors(int64_t footprint) { return footprint > kInfinityCacheBytes; }
+
 // Fills `a` (basis, geometry, epb, vgrid) for a batched FP32 launch of mesh m.
 void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a);
 // One FP32 CG-fused operator launch over many problems of order N:
 // blk[b] = (descriptor index, virtual block).
-void launch_ax_batch(int N, bool otf, bool mfma, const AxArgs<float> *descs, const int2 *blk,
-                     int64_t nblk, int epb, const double *D, const double *xi, const double *w,
+// stream: p and x non-temporal (cg_streams_vectors of the batch's footprint)
+void launch_ax_batch(int N, bool otf, bool mfma, bool stream, const AxArgs<float> *descs,
+                     const int2 *blk, int64_t nblk, int epb, const double *D, const double *xi,
+                     const double *w,
                      hipStream_t s);
 
 // gather-scatter / mask / vector kernels (sem_gs.hip, sem_vec.hip)
