@@ -106,21 +106,30 @@ sem_status sem_mesh_create(int64_t n_elem, int order_N, const double *vert_xyz,
  * unstructured mesh guarantees no ordering or spatial locality of the
  * elements in the local vectors, which makes the gather-scatter's accesses
  * unaligned; Sec. 8.2 proposes partitioning or sorting the elements to
- * recover it.  This sorts the elements along a space-filling curve through
- * their centroids.  Host only (no device work).
+ * recover it.  This sorts the elements by their centroids, along a
+ * space-filling curve or in rows.  Host only (no device work).
  *   n_elem, vert_xyz  as in sem_mesh_create.
- *   kind      SEM_ORDER_HILBERT or SEM_ORDER_MORTON (Z-order); elements whose
+ *   kind      SEM_ORDER_HILBERT or SEM_ORDER_MORTON (Z-order): elements whose
  *             centroids fall in one cell of the curve's 2^21-per-axis grid
- *             keep their input order.
+ *             keep their input order; SEM_ORDER_ROWS: row-major order of the
+ *             centroids quantized per axis to the elements' median vertex
+ *             span along it, the axis with the most cells slowest (a structured box comes back in its
+ *             row-major numbering; elements in one cell keep their input
+ *             order; more than 2^21 cells along an axis is an error).
  *   perm      HOST int64 [n_elem], written: perm[k] is the input element
  *             placed at position k.
  * Applying perm to vert_xyz, glob_id and dirichlet (and to the element blocks
  * of every local vector) before sem_mesh_create gives the same operator with
  * the elements renumbered: every result equals that of the input order with
  * its element blocks permuted.
- * Errors: SEM_EINVAL (NULL, n_elem <= 0, non-finite coordinate, unknown kind).
+ * Errors: SEM_EINVAL (NULL, n_elem <= 0, non-finite coordinate, unknown kind,
+ * zero-extent elements or too many cells for SEM_ORDER_ROWS).
  */
-typedef enum { SEM_ORDER_HILBERT = 0, SEM_ORDER_MORTON = 1 } sem_element_order_kind;
+typedef enum {
+    SEM_ORDER_HILBERT = 0,
+    SEM_ORDER_MORTON = 1,
+    SEM_ORDER_ROWS = 2
+} sem_element_order_kind;
 sem_status sem_element_order(int64_t n_elem, const double *vert_xyz, int kind, int64_t *perm);
 
 /* Free every device array of the mesh (synchronises the device). NULL is a no-op. */

@@ -15,13 +15,13 @@ import numpy as np
 __all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_set",
            "ax_shape_get", "ax_engine_set", "ax_engine_get", "ENGINE_DEFAULT", "ENGINE_VALU",
            "ENGINE_MFMA", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
-           "PRECOND_NONE", "PRECOND_JACOBI", "ORDER_HILBERT", "ORDER_MORTON", "element_order",
+           "PRECOND_NONE", "PRECOND_JACOBI", "ORDER_HILBERT", "ORDER_MORTON", "ORDER_ROWS", "element_order",
            "permute_elements", "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
 PRECOMPUTED, ON_THE_FLY = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
-ORDER_HILBERT, ORDER_MORTON = 0, 1
+ORDER_HILBERT, ORDER_MORTON, ORDER_ROWS = 0, 1, 2
 G_FP32, G_FP64, GATHER_TABLE, GATHER_TABLE_FREE, GATHER_PASS = 0x1, 0x2, 0x4, 0x8, 0x10
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -397,9 +397,10 @@ def ax_engine_get(N: int, prec: int, geom: int) -> int:
 
 
 def element_order(vert, kind: int = ORDER_HILBERT) -> np.ndarray:
-    """Element permutation along a space-filling curve through the element
-    centroids (sem_element_order; host only): perm[k] is the input element
-    placed at position k."""
+    """Element permutation by the element centroids, along a space-filling
+    curve (ORDER_HILBERT, ORDER_MORTON) or in rows (ORDER_ROWS)
+    (sem_element_order; host only): perm[k] is the input element placed at
+    position k."""
     v = np.ascontiguousarray(vert, dtype=np.float64)
     if v.ndim != 3 or v.shape[1:] != (8, 3):
         raise ValueError("vert must be [E][8][3]")

@@ -65,10 +65,55 @@ uint64_t morton_key(uint32_t x, uint32_t y, uint32_t z) {
 
 }  // namespace
 
+namespace {
+
+// Row order: centroids quantized, axis by axis, to the median span of the
+// elements' vertices along that axis, then sorted lexicographically with
+// the axis that holds the most cells slowest and the one that holds the
+// fewest fastest, which keeps the largest distance between neighbours in
+// memory as small as a row-major numbering can.  On a quasi-uniform mesh
+// this recovers the row-major order of a structured grid.
+void row_keys(int64_t E, const double *vert, const std::vector<double> &c,
+              const double *lo, std::vector<uint64_t> &key) {
+    double h[3];
+    std::vector<double> span((size_t)E);
+    for (int d = 0; d < 3; ++d) {
+        for (int64_t e = 0; e < E; ++e) {
+            double mn = INFINITY, mx = -INFINITY;
+            for (int v = 0; v < 8; ++v) {
+                mn = std::min(mn, vert[(e * 8 + v) * 3 + d]);
+                mx = std::max(mx, vert[(e * 8 + v) * 3 + d]);
+            }
+            span[e] = mx - mn;
+        }
+        std::nth_element(span.begin(), span.begin() + E / 2, span.end());
+        h[d] = span[(size_t)E / 2];
+        if (!(h[d] > 0.0)) fail(SEM_EINVAL, "row order: elements of zero extent");
+    }
+    std::vector<int64_t> q(3 * (size_t)E);
+    int64_t cells[3] = {0, 0, 0};
+    for (int64_t e = 0; e < E; ++e)
+        for (int d = 0; d < 3; ++d) {
+            const int64_t v = (int64_t)std::floor((c[3 * e + d] - lo[d]) / h[d] + 0.5);
+            if (v < 0 || v >= (int64_t(1) << 21))
+                fail(SEM_EINVAL, "row order: more than 2^21 cells along an axis");
+            q[3 * e + d] = v;
+            cells[d] = std::max(cells[d], v + 1);
+        }
+    // axes by cell count, most cells first (ties: z before y before x)
+    int ax[3] = {2, 1, 0};
+    std::stable_sort(ax, ax + 3, [&](int a, int b) { return cells[a] > cells[b]; });
+    for (int64_t e = 0; e < E; ++e)
+        key[e] = ((uint64_t)q[3 * e + ax[0]] << 42) | ((uint64_t)q[3 * e + ax[1]] << 21) |
+                 (uint64_t)q[3 * e + ax[2]];
+}
+
+}  // namespace
+
 void element_order(int64_t E, const double *vert, int kind, int64_t *perm) {
     if (E <= 0) fail(SEM_EINVAL, "n_elem must be positive");
     if (!vert || !perm) fail(SEM_EINVAL, "vert_xyz and perm must not be NULL");
-    if (kind != SEM_ORDER_HILBERT && kind != SEM_ORDER_MORTON)
+    if (kind != SEM_ORDER_HILBERT && kind != SEM_ORDER_MORTON && kind != SEM_ORDER_ROWS)
         fail(SEM_EINVAL, "unknown element order");
     std::vector<double> c(3 * (size_t)E);
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -89,7 +134,8 @@ void element_order(int64_t E, const double *vert, int kind, int64_t *perm) {
     const double cells = (double)((1u << kBits) - 1);
     const double sc = ext > 0 ? cells / ext : 0.0;
     std::vector<uint64_t> key((size_t)E);
-    for (int64_t e = 0; e < E; ++e) {
+    if (kind == SEM_ORDER_ROWS) row_keys(E, vert, c, lo, key);
+    else for (int64_t e = 0; e < E; ++e) {
         uint32_t q[3];
         for (int d = 0; d < 3; ++d) {
             double v = std::floor((c[3 * e + d] - lo[d]) * sc + 0.5);

@@ -2,8 +2,10 @@
 host only): the result is a permutation; along the Hilbert order every two
 consecutive cells of a 2^k grid are face neighbours (the defining property of
 the curve); the Morton order equals the sort by interleaved coordinate bits
-computed here independently; the order does not depend on the input
-numbering of the elements; bad arguments are refused."""
+computed here independently; the row order gives a structured box back in
+its row-major numbering, deformed or not, with the axis of most cells
+slowest; the order does not depend on the input numbering of the elements;
+bad arguments are refused."""
 import numpy as np
 import pytest
 
@@ -44,7 +46,28 @@ def test_morton_is_the_interleaved_bit_sort():
     assert p.tolist() == want
 
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("perturb", [0.0, 0.1])
+def test_rows_order_restores_the_row_major_numbering(perturb):
+    import paper_2108_12188_amd as sem
+    a = box_mesh(6, 5, 4, 2, perturb=perturb, seed=7)
+    b = box_mesh(6, 5, 4, 2, perturb=perturb, seed=7, permute=True)
+    pb = sem.element_order(b.vert, sem.ORDER_ROWS)
+    # box_mesh numbers elements x fastest, then y, then z: the permuted
+    # copy reordered in rows is the unpermuted box (the axis with the most
+    # cells, x here, is the slowest of the row order, so compare by cells)
+    ca = np.rint((a.vert.mean(axis=1) - a.vert.mean(axis=1).min(axis=0)) * np.array([6, 5, 4]))
+    cb = np.rint((b.vert.mean(axis=1) - b.vert.mean(axis=1).min(axis=0)) * np.array([6, 5, 4]))
+    want = sorted(range(b.E), key=lambda e: (cb[e, 0], cb[e, 1], cb[e, 2]))
+    assert pb.tolist() == want
+    # on a cube the ties keep z slowest and x fastest: the box's own order
+    c = box_mesh(4, 4, 4, 1, perturb=perturb, seed=8)
+    d = box_mesh(4, 4, 4, 1, perturb=perturb, seed=8, permute=True)
+    pd = sem.element_order(d.vert, sem.ORDER_ROWS)
+    np.testing.assert_array_equal(d.vert[pd], c.vert)
+    assert len(ca) == a.E
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
 def test_order_is_independent_of_input_numbering(kind):
     import paper_2108_12188_amd as sem
     a = box_mesh(6, 5, 4, 2, perturb=0.1, seed=4)

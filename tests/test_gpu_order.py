@@ -1,4 +1,4 @@
-"""Element reordering along a space-filling curve (sem_element_order) on an
+"""Element reordering (sem_element_order: Hilbert, Morton, rows) on an
 unstructured-style mesh (shuffled elements, rotated local frames): the
 operator on the reordered mesh is bitwise the element-permuted operator of
 the input mesh; CG on the reordered mesh matches the oracle on the same
@@ -25,7 +25,7 @@ def _meshes(kind):
     return m, r, perm
 
 
-@pytest.mark.parametrize("kind", [0, 1], ids=["hilbert", "morton"])
+@pytest.mark.parametrize("kind", [0, 1, 2], ids=["hilbert", "morton", "rows"])
 def test_reordered_operator_is_permuted_operator(kind):
     import torch
     import paper_2108_12188_amd as sem
@@ -48,7 +48,7 @@ def test_reordered_operator_is_permuted_operator(kind):
     gb.close()
 
 
-@pytest.mark.parametrize("kind", [0, 1], ids=["hilbert", "morton"])
+@pytest.mark.parametrize("kind", [0, 1, 2], ids=["hilbert", "morton", "rows"])
 def test_reordered_cg_matches_oracle(kind):
     import torch
     import paper_2108_12188_amd as sem
