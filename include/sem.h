@@ -370,6 +370,20 @@ sem_status sem_ax_engine_set(int order_N, sem_precision prec, sem_geom geom, int
 /* The engine later launches use (SEM_AX_ENGINE_VALU or SEM_AX_ENGINE_MFMA). */
 sem_status sem_ax_engine_get(int order_N, sem_precision prec, sem_geom geom, int *engine);
 
+/*
+ * Cache size the CG drivers assume (process-wide).  MI355X holds a 256 MB
+ * Infinity Cache in front of HBM; a CG iteration whose vectors, gather
+ * records and edge copy (of one mesh, or of all members of a batch) exceed
+ * it runs the CG-fused operator with non-temporal accesses to p and x, the
+ * two vectors nothing else reads within an iteration, so that the cache
+ * keeps what the group sums and the update read again (FP32; FP64 with G on
+ * the fly).  The results are bitwise the same either way.
+ *   bytes   > 0: the size assumed; 0: back to 256 MiB.
+ * Applies to solves started afterwards (captured iteration graphs and batch
+ * tables are rebuilt).  Errors: SEM_EINVAL (bytes < 0).
+ */
+sem_status sem_set_cache_bytes(int64_t bytes);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *sem_last_error(void);
 

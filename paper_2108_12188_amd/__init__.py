@@ -16,6 +16,7 @@ __all__ = ["SemError", "Mesh", "Batch", "Server", "mesh_footprint", "ax_shape_se
            "ax_shape_get", "ax_engine_set", "ax_engine_get", "ENGINE_DEFAULT", "ENGINE_VALU",
            "ENGINE_MFMA", "FP64", "FP32", "MIXED", "PRECOMPUTED", "ON_THE_FLY",
            "PRECOND_NONE", "PRECOND_JACOBI", "ORDER_HILBERT", "ORDER_MORTON", "ORDER_ROWS", "element_order",
+           "set_cache_bytes",
            "permute_elements", "lib", "library_path", "version"]
 
 FP64, FP32, MIXED = 0, 1, 2
@@ -64,8 +65,8 @@ EXPORTS = ["sem_mesh_create", "sem_mesh_destroy", "sem_mesh_info", "sem_ax", "se
            "sem_dot", "sem_dot_noalloc", "sem_diag", "sem_element_order", "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create",
            "sem_batch_destroy", "sem_batch_solve", "sem_server_create", "sem_server_destroy",
            "sem_server_add", "sem_server_step", "sem_mesh_footprint", "sem_ax_shape_set",
-           "sem_ax_shape_get", "sem_ax_engine_set", "sem_ax_engine_get", "sem_last_error",
-           "sem_version"]
+           "sem_ax_shape_get", "sem_ax_engine_set", "sem_ax_engine_get", "sem_set_cache_bytes",
+           "sem_last_error", "sem_version"]
 
 
 def library_path() -> str:
@@ -110,6 +111,7 @@ def lib():
                                    C.POINTER(C.c_size_t)]
     L.sem_ax_engine_set.argtypes = [i32, i32, i32, i32]
     L.sem_ax_engine_get.argtypes = [i32, i32, i32, C.POINTER(C.c_int)]
+    L.sem_set_cache_bytes.argtypes = [C.c_int64]
     L.sem_last_error.restype = C.c_char_p
     L.sem_last_error.argtypes = []
     L.sem_version.restype = C.c_char_p
@@ -118,7 +120,7 @@ def lib():
                  "sem_coords", "sem_rhs", "sem_cg_solve", "sem_batch_create", "sem_batch_solve",
                  "sem_server_create", "sem_server_add", "sem_server_step", "sem_mesh_footprint",
                  "sem_ax_shape_set", "sem_ax_shape_get", "sem_ax_engine_set",
-                 "sem_ax_engine_get", "sem_diag", "sem_element_order"):
+                 "sem_ax_engine_get", "sem_diag", "sem_element_order", "sem_set_cache_bytes"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -388,6 +390,12 @@ ENGINE_DEFAULT, ENGINE_VALU, ENGINE_MFMA = 0, 1, 2
 def ax_engine_set(N: int, prec: int, geom: int, engine: int):
     """Contraction engine of the local operator (VALU FMA or matrix cores)."""
     _check(lib().sem_ax_engine_set(N, prec, geom, engine))
+
+
+def set_cache_bytes(nbytes: int = 0):
+    """Cache size the CG drivers assume when they choose non-temporal p and x
+    accesses (sem_set_cache_bytes; 0 = 256 MiB, the Infinity Cache)."""
+    _check(lib().sem_set_cache_bytes(int(nbytes)))
 
 
 def ax_engine_get(N: int, prec: int, geom: int) -> int:

@@ -416,6 +416,14 @@ sem_status sem_ax_shape_set(int order_N, sem_precision prec, sem_geom geom, int 
     });
 }
 
+sem_status sem_set_cache_bytes(int64_t bytes) {
+    return guarded([&]() -> sem_status {
+        if (bytes < 0) fail(SEM_EINVAL, "bytes must be >= 0");
+        cache_bytes_set(bytes);
+        return SEM_OK;
+    });
+}
+
 sem_status sem_ax_engine_set(int order_N, sem_precision prec, sem_geom geom, int engine) {
     return guarded([&]() -> sem_status {
         if (order_N < 1 || order_N > kMaxOrder) fail(SEM_EUNSUPPORTED, "order not built");

@@ -110,6 +110,15 @@ static std::atomic<int> g_shape_gen{0};
 
 int ax_shape_generation() { return g_shape_gen.load(); }
 
+static std::atomic<int64_t> g_cache_bytes{kInfinityCacheBytes};
+
+bool cg_streams_vectors(int64_t footprint) { return footprint > g_cache_bytes.load(); }
+
+void cache_bytes_set(int64_t bytes) {
+    g_cache_bytes.store(bytes > 0 ? bytes : kInfinityCacheBytes);
+    g_shape_gen.fetch_add(1);
+}
+
 void ax_shape_set(int N, bool fp64, bool otf, int epb) {
     g_epb[otf ? 1 : 0][fp64 ? 1 : 0][N].store(epb > 0 ? epb : 0);
     g_shape_gen.fetch_add(1);
@@ -221,12 +230,12 @@ void launch_ax_batch(int N, bool otf, bool mfma, bool stream, const AxArgs<float
     check_hip(hipGetLastError(), "batched ax kernel launch");
 }
 
-int64_t cg_footprint32(const Mesh &m) {
+int64_t cg_footprint(const Mesh &m, int tsz) {
     const int64_t es = edge_slots(m.N);
-    int64_t b = 16 * m.n;                                  // r, p, x, w
-    if (m.gs_struct) b += m.E * (6 + es) * 8 + 4 * m.n_egroups;   // records, edge sums
-    else if (m.gs_in_update) b += 4 * m.n + 4 * m.n_groups_multi; // table, group sums
-    if (m.gsum_wedge || m.gs_struct) b += m.E * es * 4;    // edge copy
+    int64_t b = 4 * tsz * m.n;                                          // r, p, x, w
+    if (m.gs_struct) b += m.E * (6 + es) * 8 + tsz * m.n_egroups;      // records, edge sums
+    else if (m.gs_in_update) b += 4 * m.n + tsz * m.n_groups_multi;    // table, group sums
+    if (m.gsum_wedge || m.gs_struct) b += m.E * es * tsz;               // edge copy
     b += m.E * 24 * 4 + m.n;                               // vertices, codes
     return b;
 }

@@ -246,24 +246,24 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 
 // In a CG iteration the search direction p and the solution x are read
 // and written by the CG-fused operator alone, once per iteration, one
-// iteration apart.  When the iteration's FP32 vectors, records and edge
-// copy exceed the 256 MB Infinity Cache (AxArgs::stream, set by the host),
-// those accesses are non-temporal (cache-policy bit NT on the loads,
-// non-temporal stores), so that p and x take no cache space from r, w,
-// the edge copy and the gather records, which the group sums and the
-// update read again within the iteration.  A smaller iteration fits the
-// cache as it is and keeps plain accesses, as do FP64 vectors.
+// iteration apart.  When the iteration's vectors, records and edge copy
+// exceed the 256 MB Infinity Cache (AxArgs::stream, set by the host; in
+// FP64 only with G on the fly), those accesses are non-temporal
+// (cache-policy bit NT on the loads, non-temporal stores), so that p and x
+// take no cache space from r, w, the edge copy and the gather records, which
+// the group sums and the update read again within the iteration.  A smaller
+// iteration fits the cache as it is and keeps plain accesses.
 constexpr int kCpolNt = 2;       // NT bit of the load cache-policy operand
 // The choice is a template argument: a runtime flag lets the compiler merge
 // the two stores into one plain store before the flag is known.
 template <bool NT, typename T>
 __device__ __forceinline__ void store_nt(T *p, T v) {
-    if constexpr (NT && sizeof(T) == 4) __builtin_nontemporal_store(v, p);
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
 template <bool NT, typename T>
 __device__ __forceinline__ T load_nt(const T *p) {
-    if constexpr (NT && sizeof(T) == 4) return __builtin_nontemporal_load(p);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
 
@@ -1127,7 +1127,7 @@ BasisK<T> make_basis(const double *D, const double *xi, const double *w) {
 
 template <typename T, bool OTF, bool FUSED>
 void launch(const AxArgs<T> &a, const BasisK<T> &bk, int64_t grid, hipStream_t s) {
-    constexpr bool kMayStream = FUSED && sizeof(T) == 4;
+    constexpr bool kMayStream = FUSED;
     const bool nt = kMayStream && a.stream != 0;
     if constexpr (sizeof(T) == 4 && (kP == 8 || kP == 10)) {
         if (a.mfma) {

@@ -188,7 +188,8 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, bool pc, hipStrea
     a.partial = ws.part_ax;
     a.wedge = (m.gsum_wedge || m.gs_struct) ? wedge : nullptr;
     a.x = x;
-    a.stream = (sizeof(T) == 4 && cg_streams_vectors(cg_footprint32(m))) ? 1 : 0;
+    a.stream =
+        ((sizeof(T) == 4 || otf) && cg_streams_vectors(cg_footprint(m, (int)sizeof(T)))) ? 1 : 0;
     if (ev) SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     if (ev) SEM_HIP(hipEventRecord(ev[1], s));

@@ -316,14 +316,22 @@ int ax_shape_generation();
 template <typename T>
 void launch_ax(const Mesh &m, bool otf, AxMode mode, AxArgs<T> a, hipStream_t s);
 int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override);
-// Bytes an FP32 CG iteration of mesh m keeps touching: r, p, x, w, the
-// gather records or table, the operator's edge copy, vertices and codes.
-int64_t cg_footprint32(const Mesh &m);
+// Bytes a CG iteration of mesh m with tsz-byte vectors keeps touching: r,
+// p, x, w, the gather records or table, the operator's edge copy, vertices
+// and codes.
+int64_t cg_footprint(const Mesh &m, int tsz);
+
 // The CG-fused operator reads and writes p and x non-temporally when the
 // iteration (of one mesh, or of a whole batch) exceeds the 256 MB Infinity
-// Cache, so that the cache keeps what the rest of the iteration reads again.
+// Cache, so that the cache keeps what the rest of the iteration reads again
+// (in FP64 only with G on the fly: the precomputed FP64 factors, read with
+// plain loads, fill the cache either way).
 constexpr int64_t kInfinityCacheBytes = int64_t(256) << 20;
-inline bool cg_streams_vectors(int64_t footprint) { return footprint > kInfinityCacheBytes; }
+bool cg_streams_vectors(int64_t footprint);
+// The cache size assumed by cg_streams_vectors (0: kInfinityCacheBytes);
+// changing it invalidates captured graphs and batch tables like a new tile
+// shape does.
+void cache_bytes_set(int64_t bytes);
 
 // Fills `a` (basis, geometry, epb, vgrid) for a batched FP32 launch of mesh m.
 void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a);
