@@ -74,9 +74,16 @@ def ax_flops_per_point(N: int, geom: str) -> float:
     return 12.0 * P + 15.0 if geom == "pre" else 30.0 * P + 96.0
 
 
+# the sources of every kernel the committed counter summary describes (the
+# operator, the gathered update and its group sums, the stand-alone
+# gather-scatter)
+COUNTER_SOURCES = ("sem_ax_order.hip", "sem_vec.hip", "sem_vec_body.h", "sem_gs.hip",
+                   "sem_gs_body.h")
+
+
 def src_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sem_ax_order.hip",):
+    for f in COUNTER_SOURCES:
         with open(os.path.join(ROOT, "paper_2108_12188_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
