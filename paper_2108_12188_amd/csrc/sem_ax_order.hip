@@ -254,6 +254,10 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 // the group sums and the update read again within the iteration.  A smaller
 // iteration fits the cache as it is and keeps plain accesses.
 constexpr int kCpolNt = 2;       // NT bit of the load cache-policy operand
+
+// read-only data that every lane of a wave reads at one address, loaded
+// into scalar registers (constant address space)
+typedef __attribute__((address_space(4))) const float kconst_float;
 // The choice is a template argument: a runtime flag lets the compiler merge
 // the two stores into one plain store before the flag is known.
 template <bool NT, typename T>
@@ -673,11 +677,6 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
             eta_j = a.xi[j];
             wij = a.wq[i] * a.wq[j];
         }
-        // vertices of an element: lane m < 24 loads coordinate m (one
-        // register), broadcast to the wave with readlane when used
-        auto load_vert = [&](int64_t e) -> float {
-            return q < 24 ? a.vert[e * 24 + q] : 0.f;
-        };
         auto stage = [&](int64_t e) {
             if constexpr (kDma) {
                 dma_elem_to_lds(reinterpret_cast<const float *>(a.u) + e * P3, sR);
@@ -688,10 +687,8 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
                         reinterpret_cast<const float *>(a.x) + e * P3, sX);
             }
         };
-        float vnext = 0.f;
         if (vb < ntiles) {
             if constexpr (kDma) stage(vb);
-            if constexpr (OTF) vnext = load_vert(vb);
         }
 
         double acc = 0.0;
@@ -708,7 +705,6 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
                 else __builtin_amdgcn_s_waitcnt(kWaitVmcnt8);
                 __asm__ volatile("" ::: "memory");
             }
-            const float vcur = vnext;
 
             T uc[P];
             if constexpr (kDma) {
@@ -762,17 +758,18 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
             if constexpr (kDma) {
                 if (e + vgrid < ntiles) stage(e + vgrid);
             }
-            if constexpr (OTF) {
-                if (e + vgrid < ntiles) vnext = load_vert(e + vgrid);
-            }
-
             // column geometry (after the gradient: fewer registers live)
             ColumnGeom<T> cg;
             if constexpr (OTF) {
+                // the element's 24 vertex coordinates in scalar registers:
+                // read through the constant address space (the vertices
+                // are read-only here; a C-style cast is the form clang
+                // accepts for the address-space conversion), so no VALU
+                // instruction broadcasts them
+                const kconst_float *vs = (const kconst_float *)(a.vert + e * 24);
                 T ve[24];
 #pragma unroll
-                for (int m = 0; m < 24; ++m)
-                    ve[m] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vcur), m));
+                for (int m = 0; m < 24; ++m) ve[m] = vs[m];
                 cg = column_geom<T>(ve, xi_i, eta_j, wij);
             }
 
