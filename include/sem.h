@@ -56,7 +56,9 @@ typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_MIXED = 2 } sem_precision;
 typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
 
 /* sem_mesh_create flags: which precomputed geometric-factor arrays to keep.
- * The on-the-fly form needs none of them (it reads the vertices). */
+ * The on-the-fly form needs none of them (it reads the vertices; at N = 7 the
+ * FP32 matrix-core operator reads 12 edge vectors per element, 144 B, that
+ * mesh creation derives from them). */
 #define SEM_MESH_G_FP32 0x1u   /* G as float [E][6][P3]  (24 B per point)  */
 #define SEM_MESH_G_FP64 0x2u   /* G as double [E][6][P3] (48 B per point)  */
 /* Form of the gather-scatter inside CG (the two give bitwise identical

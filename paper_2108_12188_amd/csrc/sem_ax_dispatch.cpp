@@ -182,6 +182,7 @@ void launch_ax<float>(const Mesh &m, bool otf, AxMode mode, AxArgs<float> a, hip
     a.xi = m.b32.xi;
     a.wq = m.b32.w;
     a.vert = m.vert32;
+    a.edge = m.edge32;
     if (!otf) a.G = m.G32;
     const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
     kFn32[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(),
@@ -200,6 +201,7 @@ void launch_ax<double>(const Mesh &m, bool otf, AxMode mode, AxArgs<double> a, h
     a.xi = m.b64.xi;
     a.wq = m.b64.w;
     a.vert = m.vert64;
+    a.edge = nullptr;
     if (!otf) a.G = m.G64;
     const int64_t ntiles = (m.E + sh.epb - 1) / sh.epb;
     kFn64[m.N](otf, mode, a, m.h_D.data(), m.h_xi.data(), m.h_w.data(),
@@ -217,6 +219,7 @@ void ax_batch_desc(const Mesh &m, bool otf, AxArgs<float> &a) {
     a.xi = m.b32.xi;
     a.wq = m.b32.w;
     a.vert = m.vert32;
+    a.edge = m.edge32;
     a.G = otf ? nullptr : m.G32;
     a.vgrid = ax_grid((m.E + sh.epb - 1) / sh.epb, AxMode::CgFused, sh.mfma, sh.threads);
 }
@@ -236,7 +239,9 @@ int64_t cg_footprint(const Mesh &m, int tsz) {
     if (m.gs_struct) b += m.E * (6 + es) * 8 + tsz * m.n_egroups;      // records, edge sums
     else if (m.gs_in_update) b += 4 * m.n + tsz * m.n_groups_multi;    // table, group sums
     if (m.gsum_wedge || m.gs_struct) b += m.E * es * tsz;               // edge copy
-    b += m.E * 24 * 4 + m.n;                               // vertices, codes
+    // vertices (the matrix-core operator at N = 7 reads the element edge
+    // vectors instead), point codes
+    b += (m.edge32 && tsz == 4 ? m.E * 36 * 4 : m.E * 24 * tsz) + m.n;
     return b;
 }
 

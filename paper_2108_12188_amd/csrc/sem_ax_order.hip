@@ -76,6 +76,13 @@ __device__ __forceinline__ T rcp(T x) { return T(1) / x; }
 template <>
 __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// a * b + c with one rounding.
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 template <typename T>
 struct Vec3 {
     T x, y, z;
@@ -108,28 +115,44 @@ struct ColumnGeom {
     T d0, d1, d2, wij;
 };
 
+// The 12 edge vectors of an element from its 8 vertices, in the order the
+// column geometry uses them: along xi (v1 - v0, v3 - v2, v5 - v4, v7 - v6),
+// along eta (v2 - v0, v3 - v1, v6 - v4, v7 - v5), along gamma (v4 - v0,
+// v5 - v1, v6 - v2, v7 - v3); ed[t * 3 + d].  The host builds the same
+// FP32 array per element (Mesh::vedge32) with the same subtractions.
 template <typename T>
-__device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T xi_i,
-                                                     T eta_j, T wij) {
+__device__ __forceinline__ void element_edges(const T *__restrict__ ve, T (&ed)[36]) {
+    constexpr int kA[12] = {1, 3, 5, 7, 2, 3, 6, 7, 4, 5, 6, 7};
+    constexpr int kB[12] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3};
+#pragma unroll
+    for (int t = 0; t < 12; ++t)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ed[t * 3 + d] = ve[kA[t] * 3 + d] - ve[kB[t] * 3 + d];
+}
+
+template <typename T, typename EdgePtr>
+__device__ __forceinline__ ColumnGeom<T> column_geom_edges(EdgePtr ed, T xi_i, T eta_j, T wij) {
     const T fi0 = T(0.5) * (T(1) - xi_i), fi1 = T(0.5) * (T(1) + xi_i);
     const T fj0 = T(0.5) * (T(1) - eta_j), fj1 = T(0.5) * (T(1) + eta_j);
     T A0[3], A1[3], B0[3], B1[3], Cc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const T v0 = ve[0 * 3 + d], v1 = ve[1 * 3 + d], v2 = ve[2 * 3 + d], v3 = ve[3 * 3 + d];
-        const T v4 = ve[4 * 3 + d], v5 = ve[5 * 3 + d], v6 = ve[6 * 3 + d], v7 = ve[7 * 3 + d];
+        // Every product-sum here is an explicit fused multiply-add: the
+        // edges may sit in scalar registers (matrix-core operator) or come
+        // out of subtractions (VALU operator), and both must round alike.
         // d/dxi at (eta_j, gamma corner c)
-        const T a0 = T(0.5) * ((v1 - v0) * fj0 + (v3 - v2) * fj1);
-        const T a1 = T(0.5) * ((v5 - v4) * fj0 + (v7 - v6) * fj1);
+        const T a0 = T(0.5) * fmadd(ed[0 * 3 + d], fj0, ed[1 * 3 + d] * fj1);
+        const T a1 = T(0.5) * fmadd(ed[2 * 3 + d], fj0, ed[3 * 3 + d] * fj1);
         // d/deta at (xi_i, gamma corner c)
-        const T b0 = T(0.5) * ((v2 - v0) * fi0 + (v3 - v1) * fi1);
-        const T b1 = T(0.5) * ((v6 - v4) * fi0 + (v7 - v5) * fi1);
+        const T b0 = T(0.5) * fmadd(ed[4 * 3 + d], fi0, ed[5 * 3 + d] * fi1);
+        const T b1 = T(0.5) * fmadd(ed[6 * 3 + d], fi0, ed[7 * 3 + d] * fi1);
         A0[d] = T(0.5) * (a0 + a1);
         A1[d] = T(0.5) * (a1 - a0);
         B0[d] = T(0.5) * (b0 + b1);
         B1[d] = T(0.5) * (b1 - b0);
-        Cc[d] = T(0.5) * ((v4 - v0) * fi0 * fj0 + (v5 - v1) * fi1 * fj0 +
-                          (v6 - v2) * fi0 * fj1 + (v7 - v3) * fi1 * fj1);
+        const T c4 = fmadd(ed[9 * 3 + d] * fi1, fj0, ed[8 * 3 + d] * fi0 * fj0);
+        const T c6 = fmadd(ed[10 * 3 + d] * fi0, fj1, c4);
+        Cc[d] = T(0.5) * fmadd(ed[11 * 3 + d] * fi1, fj1, c6);
     }
     const Vec3<T> a0{A0[0], A0[1], A0[2]}, a1{A1[0], A1[1], A1[2]};
     const Vec3<T> b0{B0[0], B0[1], B0[2]}, b1{B1[0], B1[1], B1[2]};
@@ -149,11 +172,12 @@ __device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T
     return g;
 }
 
-// a * b + c with one rounding.
 template <typename T>
-__device__ __forceinline__ T fmadd(T a, T b, T c) {
-    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
-    else return __builtin_fma(a, b, c);
+__device__ __forceinline__ ColumnGeom<T> column_geom(const T *__restrict__ ve, T xi_i, T eta_j,
+                                                     T wij) {
+    T ed[36];
+    element_edges<T>(ve, ed);
+    return column_geom_edges<T>(ed, xi_i, eta_j, wij);
 }
 
 // The pointwise step of A_L at level k of a column: (vr, vs, vt) = G (ur, us, ut)
@@ -761,16 +785,17 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
             // column geometry (after the gradient: fewer registers live)
             ColumnGeom<T> cg;
             if constexpr (OTF) {
-                // the element's 24 vertex coordinates in scalar registers:
-                // read through the constant address space (the vertices
+                // the element's 12 edge vectors (36 values, precomputed from
+                // the FP32 vertices with the same subtractions) in scalar
+                // registers: read through the constant address space (they
                 // are read-only here; a C-style cast is the form clang
                 // accepts for the address-space conversion), so no VALU
-                // instruction broadcasts them
-                const kconst_float *vs = (const kconst_float *)(a.vert + e * 24);
-                T ve[24];
+                // instruction forms or broadcasts them
+                const kconst_float *es = (const kconst_float *)(a.edge + e * 36);
+                T ed[36];
 #pragma unroll
-                for (int m = 0; m < 24; ++m) ve[m] = vs[m];
-                cg = column_geom<T>(ve, xi_i, eta_j, wij);
+                for (int m = 0; m < 36; ++m) ed[m] = es[m];
+                cg = column_geom_edges<T>(ed, xi_i, eta_j, wij);
             }
 
             // pointwise G, back in the column layout

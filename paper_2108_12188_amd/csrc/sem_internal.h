@@ -151,6 +151,7 @@ struct Mesh {
     // device arrays
     double *vert64 = nullptr;     // [E][8][3]
     float *vert32 = nullptr;      // [E][8][3]
+    float *edge32 = nullptr;      // N = 7: [E][12][3] element edge vectors from vert32
     float *G32 = nullptr;         // [E][6][P3]
     double *G64 = nullptr;        // [E][6][P3]
     double *B64 = nullptr;        // [E][P3] mass w_q |J_q|
@@ -267,6 +268,8 @@ struct AxArgs {
     T *w;                       // output
     const T *G;                 // precomputed factors [E][6][P3]
     const T *vert;              // vertices [E][8][3] (on-the-fly form)
+    const T *edge;              // FP32, N = 7, may be null: edge vectors [E][12][3]
+                                // (the matrix-core on-the-fly form reads these)
     const T *D;                 // [P][P]
     const T *Dt;                // [P][P]
     const T *xi;                // [P]

@@ -37,7 +37,7 @@ void upload(T *dst, const T *src, size_t count, hipStream_t s) {
 #endif
 
 void free_mesh_arrays(Mesh *m) {
-    void *ptrs[] = {m->vert64,     m->vert32,  m->G32,     m->G64,       m->B64,
+    void *ptrs[] = {m->vert64,     m->vert32,  m->edge32,  m->G32,     m->G64,       m->B64,
                     m->mcode,      m->gs_idx,  m->gs_lb_order, m->dir_idx, m->gsrc,
                     m->wedge_idx,  m->basis_blob, m->scratch, m->state,   m->minv64,
                     m->minv32,     m->erec,    m->pos_tab, m->ewedge_idx};
@@ -67,6 +67,7 @@ size_t mesh_footprint(int64_t E, int N, uint32_t flags, sem_precision prec) {
     const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
     const size_t n = (size_t)E * P3;
     size_t b = (size_t)E * 24 * (8 + 4);          // vertices, FP64 and FP32
+    if (N == 7) b += (size_t)E * 36 * 4;           // FP32 edge vectors
     b += n * 8;                                    // mass
     b += n * 1;                                    // point codes
     b += n * 4 * 2;                                // group index list and Dirichlet list (bounds)
@@ -157,6 +158,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     try {
         m->vert64 = dev_alloc<double>(*m, (size_t)E * 24);
         m->vert32 = dev_alloc<float>(*m, (size_t)E * 24);
+        if (N == 7) m->edge32 = dev_alloc<float>(*m, (size_t)E * 36);
         m->B64 = dev_alloc<double>(*m, (size_t)n);
         if (flags & SEM_MESH_G_FP32) m->G32 = dev_alloc<float>(*m, (size_t)n * 6);
         if (flags & SEM_MESH_G_FP64) m->G64 = dev_alloc<double>(*m, (size_t)n * 6);
@@ -200,6 +202,22 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         for (size_t q = 0; q < v32.size(); ++q) v32[q] = (float)vert[q];
         upload(m->vert64, vert, (size_t)E * 24, s);
         upload(m->vert32, v32.data(), v32.size(), s);
+        std::vector<float> ed32;
+        if (m->edge32) {
+            // the 12 edge vectors of each element, subtracted in FP32 from
+            // the FP32 vertices exactly as the on-the-fly geometry does: the
+            // matrix-core operator at N = 7 reads these instead of the
+            // vertices (same values, bit for bit)
+            static const int kHead[12] = {1, 3, 5, 7, 2, 3, 6, 7, 4, 5, 6, 7};
+            static const int kTail[12] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3};
+            ed32.resize((size_t)E * 36);
+            for (int64_t e = 0; e < E; ++e)
+                for (int t = 0; t < 12; ++t)
+                    for (int d = 0; d < 3; ++d)
+                        ed32[(size_t)e * 36 + t * 3 + d] = v32[(size_t)e * 24 + kHead[t] * 3 + d] -
+                                                           v32[(size_t)e * 24 + kTail[t] * 3 + d];
+            upload(m->edge32, ed32.data(), ed32.size(), s);
+        }
         upload(m->mcode, t.mcode.data(), t.mcode.size(), s);
         upload(m->gs_idx, t.gs_idx.data(), t.gs_idx.size(), s);
         upload(m->gs_lb_order, t.gs_lb_order.data(), t.gs_lb_order.size(), s);
