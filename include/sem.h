@@ -62,11 +62,13 @@ typedef enum { SEM_G_PRECOMPUTED = 0, SEM_G_ON_THE_FLY = 1 } sem_geom;
 #define SEM_MESH_G_FP32 0x1u   /* G as float [E][6][P3]  (24 B per point)  */
 #define SEM_MESH_G_FP64 0x2u   /* G as double [E][6][P3] (48 B per point)  */
 /* Form of the gather-scatter inside CG (the two give bitwise identical
- * results).  The table-free form applies to odd N on conforming meshes and
- * is used by default from 6 * 2^20 local points on (smaller meshes run
- * faster with the per-point table).  SEM_MESH_GATHER_TABLE keeps the table
- * form; SEM_MESH_GATHER_TABLE_FREE takes the table-free form wherever it
- * applies, whatever the size.  Not both. */
+ * results).  The table-free form applies to odd N on conforming meshes.
+ * sem_cg_solve uses it by default from 2^19 local points on (smaller meshes
+ * run faster alone with the per-point table, which such a mesh then holds
+ * as well); batched and served solves use it wherever it applies.
+ * SEM_MESH_GATHER_TABLE keeps the table form everywhere;
+ * SEM_MESH_GATHER_TABLE_FREE takes the table-free form wherever it applies,
+ * whatever the size.  Not both. */
 #define SEM_MESH_GATHER_TABLE 0x4u
 #define SEM_MESH_GATHER_TABLE_FREE 0x8u
 /* The paper's schedule instead (Algorithm 1 with the gather-scatter QQ^T as a
@@ -149,10 +151,10 @@ typedef struct {
     int32_t gs_in_update;  /* 1: every shared point lies on an element face, and sem_cg_solve
                               gathers the shared sums inside its vector update instead of a
                               separate gather-scatter pass (same results, bitwise) */
-    int32_t gs_table_free; /* 1: that gather derives each point's copies from its position in
-                              the element and per-element face and edge records (see
-                              SEM_MESH_GATHER_TABLE_FREE) instead of a per-point table (same
-                              results, bitwise) */
+    int32_t gs_table_free; /* 1: sem_cg_solve's gather derives each point's copies from its
+                              position in the element and per-element face and edge records
+                              (see SEM_MESH_GATHER_TABLE_FREE) instead of a per-point table
+                              (same results, bitwise) */
 } sem_mesh_info_t;
 
 sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info);

@@ -135,7 +135,7 @@ sem_status sem_mesh_info(sem_mesh_t mesh, sem_mesh_info_t *info) {
         info->n_dirichlet = m->n_dir;
         info->device_bytes = m->device_bytes + workspace_bytes(*m);
         info->gs_in_update = m->gs_in_update ? 1 : 0;
-        info->gs_table_free = m->gs_struct ? 1 : 0;
+        info->gs_table_free = m->gs_struct_solo ? 1 : 0;
         return SEM_OK;
     });
 }

@@ -233,12 +233,12 @@ void launch_ax_batch(int N, bool otf, bool mfma, bool stream, const AxArgs<float
     check_hip(hipGetLastError(), "batched ax kernel launch");
 }
 
-int64_t cg_footprint(const Mesh &m, int tsz) {
+int64_t cg_footprint(const Mesh &m, int tsz, bool table_free) {
     const int64_t es = edge_slots(m.N);
     int64_t b = 4 * tsz * m.n;                                          // r, p, x, w
-    if (m.gs_struct) b += m.E * (6 + es) * 8 + tsz * m.n_egroups;      // records, edge sums
+    if (table_free) b += m.E * (6 + es) * 8 + tsz * m.n_egroups;       // records, edge sums
     else if (m.gs_in_update) b += 4 * m.n + tsz * m.n_groups_multi;    // table, group sums
-    if (m.gsum_wedge || m.gs_struct) b += m.E * es * tsz;               // edge copy
+    if (m.gsum_wedge || table_free) b += m.E * es * tsz;                // edge copy
     // vertices (the matrix-core operator at N = 7 reads the element edge
     // vectors instead), point codes
     b += (m.edge32 && tsz == 4 ? m.E * 36 * 4 : m.E * 24 * tsz) + m.n;

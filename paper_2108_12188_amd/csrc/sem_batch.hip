@@ -377,7 +377,7 @@ void BatchImpl::rebuild(const std::vector<Mesh *> &ms) {
     ensure_cap(d_cls, cap_cls, count, bytes);
     // one batched iteration touches every member's vectors
     int64_t footprint = 0;
-    for (int q = 0; q < count; ++q) footprint += cg_footprint(*ms[q], 4);
+    for (int q = 0; q < count; ++q) footprint += cg_footprint(*ms[q], 4, ms[q]->gs_struct);
     const int stream = cg_streams_vectors(footprint) ? 1 : 0;
     stream_vectors = stream != 0;
     for (int q = 0; q < count; ++q) {

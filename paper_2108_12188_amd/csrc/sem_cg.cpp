@@ -186,20 +186,23 @@ void enqueue_iteration(const Mesh &m, Workspace &ws, bool otf, bool pc, hipStrea
     a.w = w;
     a.st = ws.st;
     a.partial = ws.part_ax;
-    a.wedge = (m.gsum_wedge || m.gs_struct) ? wedge : nullptr;
+    a.wedge = (m.gsum_wedge || m.gs_struct_solo) ? wedge : nullptr;
     a.x = x;
-    a.stream =
-        ((sizeof(T) == 4 || otf) && cg_streams_vectors(cg_footprint(m, (int)sizeof(T)))) ? 1 : 0;
+    a.stream = ((sizeof(T) == 4 || otf) &&
+                cg_streams_vectors(cg_footprint(m, (int)sizeof(T), m.gs_struct_solo)))
+                   ? 1
+                   : 0;
     if (ev) SEM_HIP(hipEventRecord(ev[0], s));
     launch_ax<T>(m, otf, AxMode::CgFused, a, s);
     if (ev) SEM_HIP(hipEventRecord(ev[1], s));
     const int64_t nax = ax_blocks(m, sizeof(T) == 8, otf, 0);
-    if (m.gs_struct) launch_edge_sums_cg<T>(m, wedge, w + m.n, ws.st, ws.part_ax, (int)nax, s);
+    if (m.gs_struct_solo)
+        launch_edge_sums_cg<T>(m, wedge, w + m.n, ws.st, ws.part_ax, (int)nax, s);
     else if (m.gs_in_update)
         launch_group_sums_cg<T>(m, w, wedge, gsum, ws.st, ws.part_ax, (int)nax, s);
     else launch_gs_cg<T>(m, w, ws.st, ws.part_ax, (int)nax, s);
     if (ev) SEM_HIP(hipEventRecord(ev[2], s));
-    if (m.gs_struct) launch_update_struct<T>(m, r, w, ws.st, ws.part_vec, s, pa);
+    if (m.gs_struct_solo) launch_update_struct<T>(m, r, w, ws.st, ws.part_vec, s, pa);
     else if (m.gs_in_update) launch_update_gather<T>(m, r, w, gsum, ws.st, ws.part_vec, s, pa);
     else launch_update<T>(m, r, w, ws.st, ws.part_vec, s, pa);
     if (ev) SEM_HIP(hipEventRecord(ev[3], s));

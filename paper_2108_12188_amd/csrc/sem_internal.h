@@ -19,7 +19,10 @@ constexpr uint8_t kDirichletBit = 0x80;
 constexpr uint8_t kMultMask = 0x7F;
 constexpr int kMaxP = kMaxOrder + 1;
 // local points from which a mesh takes the table-free gather by default
-constexpr int64_t kTableFreeMinPoints = int64_t(6) << 20;
+// (below it, where a CG iteration is mostly launch latency, the table form
+// measured up to 8% faster; from it on the table-free form is as fast or
+// faster, alone and in batches)
+constexpr int64_t kTableFreeMinPoints = int64_t(1) << 19;
 
 // Edge and corner nodes of an element's P^3 block (on two or three of its
 // faces): 12 N - 4 of them, numbered column by column (i, j on the border
@@ -182,8 +185,13 @@ struct Mesh {
     // n_egroups edge and corner groups of two or more copies (ecls /
     // ewedge_idx: positions in the compact edge array) follow w in class
     // order.  Division of a local index by P^3: (l * p3_magic) >> p3_shift
-    // (checked on the host for every l < n).
+    // (checked on the host for every l < n).  gs_struct: its tables are
+    // present (batched and served solves use it then); gs_struct_solo: a
+    // single-mesh solve uses it too (from kTableFreeMinPoints points on, or
+    // when forced), else the per-point table gsrc, which is then present.
+    // The two forms give bitwise identical results.
     bool gs_struct = false;
+    bool gs_struct_solo = false;
     ElemRec *erec = nullptr;       // [E][6 + edge_slots(N)]
     uint32_t *pos_tab = nullptr;   // [P3]
     GsClasses ecls{};
@@ -320,9 +328,9 @@ template <typename T>
 void launch_ax(const Mesh &m, bool otf, AxMode mode, AxArgs<T> a, hipStream_t s);
 int64_t ax_blocks(const Mesh &m, bool fp64, bool otf, int epb_override);
 // Bytes a CG iteration of mesh m with tsz-byte vectors keeps touching: r,
-// p, x, w, the gather records or table, the operator's edge copy, vertices
-// and codes.
-int64_t cg_footprint(const Mesh &m, int tsz);
+// p, x, w, the gather records (table_free) or table, the operator's edge
+// copy, vertices and codes.
+int64_t cg_footprint(const Mesh &m, int tsz, bool table_free);
 
 // The CG-fused operator reads and writes p and x non-temporally when the
 // iteration (of one mesh, or of a whole batch) exceeds the 256 MB Infinity

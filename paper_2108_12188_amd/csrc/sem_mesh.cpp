@@ -139,10 +139,13 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
     m->gs_blk_multi = t.gs_blk_multi;
     m->gsum_wedge = t.gsum_wedge;
     m->wedge_io0 = t.wedge_io0;
-    // the table-free gather where it applies: forced, or by size (below about
-    // 6 M points its fixed per-block set-up costs more than the table's bytes)
-    m->gs_struct = t.gs_struct && !(flags & SEM_MESH_GATHER_TABLE) &&
-                   ((flags & SEM_MESH_GATHER_TABLE_FREE) || n >= kTableFreeMinPoints);
+    // the table-free gather wherever it applies unless the table is asked
+    // for; single-mesh solves use it when forced or by size (below about half
+    // a million points its fixed per-block set-up costs more than the table's
+    // bytes there), batched launches always (their blocks span every member)
+    m->gs_struct = t.gs_struct && !(flags & SEM_MESH_GATHER_TABLE);
+    m->gs_struct_solo =
+        m->gs_struct && ((flags & SEM_MESH_GATHER_TABLE_FREE) || n >= kTableFreeMinPoints);
     if (m->gs_struct) {
         m->ecls = t.ecls;
         m->n_egroups = t.n_egroups;
@@ -166,7 +169,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         m->gs_idx = dev_alloc<int32_t>(*m, t.gs_idx.size());
         m->gs_lb_order = dev_alloc<int32_t>(*m, t.gs_lb_order.size());
         m->dir_idx = dev_alloc<int32_t>(*m, t.dir_idx.size());
-        if (t.gs_in_update && !m->gs_struct) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
+        if (t.gs_in_update && !m->gs_struct_solo) m->gsrc = dev_alloc<int32_t>(*m, t.gsrc.size());
         if (t.gsum_wedge) m->wedge_idx = dev_alloc<int32_t>(*m, t.wedge_idx.size());
         if (m->gs_struct) {
             m->erec = dev_alloc<ElemRec>(*m, t.erec.size());
@@ -223,7 +226,7 @@ Mesh *mesh_create(int64_t E, int N, const double *vert, const int64_t *gid, cons
         upload(m->gs_lb_order, t.gs_lb_order.data(), t.gs_lb_order.size(), s);
         if (SEM_GS_BLOCK_ORDER) m->gs.lb_order = m->gs_lb_order;
         upload(m->dir_idx, t.dir_idx.data(), t.dir_idx.size(), s);
-        if (t.gs_in_update && !m->gs_struct) upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
+        if (t.gs_in_update && !m->gs_struct_solo) upload(m->gsrc, t.gsrc.data(), t.gsrc.size(), s);
         if (t.gsum_wedge) upload(m->wedge_idx, t.wedge_idx.data(), t.wedge_idx.size(), s);
         if (m->gs_struct) {
             upload(m->erec, t.erec.data(), t.erec.size(), s);

@@ -283,14 +283,21 @@ def test_cg_table_free_gather_bitwise_equals_table(N):
 
 
 def test_gather_form_default_by_size_and_flags():
-    """The table-free gather is the default from 6 * 2^20 local points on
-    (24^3 N = 7: 7.1 M points), the table below (small meshes run faster
-    with it); asking for both forms is an error."""
+    """The table-free gather is the default from 2^19 local points on
+    (24^3 N = 7: 7.1 M points; 8^3 N = 7, 262144 points, keeps the table),
+    the table below (small meshes run faster with it); asking for both
+    forms is an error."""
     import paper_2108_12188_amd as sem
     small = box_mesh(3, 3, 3, 7, perturb=0.1, seed=93)
     gm = sem.Mesh.from_box(small)
     assert gm.info()["gs_table_free"] == 0
     gm.close()
+    # the boundary: 8 x 8 x 15 elements (491520 points) keep the table,
+    # 8 x 8 x 16 (524288 = 2^19 points) take the table-free form
+    for nz, want in ((15, 0), (16, 1)):
+        gm = sem.Mesh.from_box(box_mesh(8, 8, nz, 7, perturb=0.1, seed=96), g_fp32=False)
+        assert gm.info()["gs_table_free"] == want
+        gm.close()
     with pytest.raises(sem.SemError) as ei:
         sem.Mesh.from_box(small, gather_table=True, table_free=True)
     assert ei.value.code == -1
