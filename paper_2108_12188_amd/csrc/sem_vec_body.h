@@ -26,6 +26,18 @@ constexpr int kUpdPacks = SEM_UPD_PACKS;
 #endif
 constexpr int kUpdStructPacks = SEM_UPD_STRUCT_PACKS;
 
+// Blocks are dealt to the 8 XCDs round-robin (block b on XCD b mod 8): the
+// vector updates give each XCD a contiguous range of the logical blocks
+// instead (a bijection on [0, vgrid); the last vgrid mod 8 blocks keep
+// their place), so that the face partners a block reads in neighbouring
+// elements were mostly brought in through the same L2.  The ρ partial of a
+// block stays at its own index vb.
+__device__ __forceinline__ int64_t xcd_block(int64_t vb, int64_t vgrid) {
+    const int64_t full = vgrid & ~int64_t(7);
+    if (vb >= full) return vb;
+    return (vb & 7) * (full >> 3) + (vb >> 3);
+}
+
 template <typename T>
 struct alignas(4 * sizeof(T)) Pack4 {
     T v[4];
@@ -61,7 +73,7 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
     double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
-    const int64_t tid = vb * blockDim.x + threadIdx.x;
+    const int64_t tid = xcd_block(vb, vgrid) * blockDim.x + threadIdx.x;
     for (int64_t q = tid; q < n4; q += stride) {
         Pack4<T> rv = reinterpret_cast<const Pack4<T> *>(r)[q];
         const Pack4<T> wv = reinterpret_cast<const Pack4<T> *>(w)[q];
@@ -176,7 +188,7 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
     double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
-    const int64_t tid = vb * blockDim.x + threadIdx.x;
+    const int64_t tid = xcd_block(vb, vgrid) * blockDim.x + threadIdx.x;
     constexpr int K = kUpdPacks;
     for (int64_t q = tid; q < n4; q += K * stride) {
         int64_t qq[K];
@@ -339,7 +351,7 @@ __device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
     double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
-    const int64_t tid = vb * blockDim.x + threadIdx.x;
+    const int64_t tid = xcd_block(vb, vgrid) * blockDim.x + threadIdx.x;
     constexpr int K = kUpdStructPacks;
     for (int64_t q = tid; q < n4; q += K * stride) {
         int64_t qq[K];
