@@ -1189,9 +1189,12 @@ def run_config8(args):
     """The headline FP32 CG on unstructured element numberings, with and
     without reordering (see unstructured_rows)."""
     rows = unstructured_rows(args)
+    # the value: the best of the three reorderings of the shuffled mesh
+    best = max(("hilbert", "morton", "rows"), key=lambda k: rows[k]["gdof_iter_per_s"])
     return _emit({"metric": "FP32 CG GDOF·iter/s, 32^3 N=7: shuffled and rotated elements, "
-                            "Hilbert / Morton / row reordered, structured",
-                  "value": rows["rows"]["gdof_iter_per_s"], "unit": "GDOF·iter/s",
+                            "Hilbert / Morton / row reordered (value: the best), structured",
+                  "value": rows[best]["gdof_iter_per_s"], "best_reorder": best,
+                  "unit": "GDOF·iter/s",
                   "higher_is_better": True, "rows": rows, "dtype": "f32", "data": "synthetic",
                   "config": {"workload": "32^3 N=7 +-10% deformed, 500 FP32 CG iterations, "
                                          "element numbering varied"}})
