@@ -412,16 +412,19 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                                    nwave);
         }
     };
+    // the FP32 CG-fused form walks XCD-contiguously (measured faster: 24^3
+    // N = 5 +2.4%; FP64 CG 2.4% slower that way keeps launch order)
+    const int64_t tv0 = (FUSED && sizeof(T) == 4) ? xcd_first_tile(vb, vgrid) : vb;
     if constexpr (kDma) {
-        if (vb < ntiles) {
-            stage(vb);
-            stage_x(vb);
+        if (tv0 < ntiles) {
+            stage(tv0);
+            stage_x(tv0);
         }
     }
 
     double acc = 0.0;
     // a tile is `epb` consecutive elements; the grid strides over tiles
-    for (int64_t tile = vb; tile < ntiles; tile += vgrid) {
+    for (int64_t tile = tv0; tile < ntiles; tile += vgrid) {
         const int64_t e = tile * a.epb + el;
         const bool valid = (el < a.epb) && (e < a.E);
         const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
