@@ -343,8 +343,18 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
     float *const sV = sP + a.epb * P3;
     float *const sX = reinterpret_cast<float *>(sA);
 
+    // the CG state in one round of loads: stop, beta, the lagged x step
+    T beta = T(0);
+    // single-mesh CG: x += alpha_{i-1} p_{i-1} of the previous iteration,
+    // applied here where p_{i-1} is read anyway
+    bool xlag = false;
+    T aprev = T(0);
     if constexpr (FUSED) {
-        if (a.st->stop) return;          // uniform: the whole grid exits
+        const int stopped = a.st->stop;
+        beta = (T)a.st->beta;
+        xlag = a.x != nullptr && a.st->x_lag != 0;
+        aprev = (T)a.st->alpha;
+        if (stopped) return;             // uniform: the whole grid exits
     }
 
     const int t = threadIdx.x;
@@ -365,17 +375,7 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
         DiT[l] = a.Dt[i * P + l];
         DjT[l] = a.Dt[j * P + l];
     }
-    T beta = T(0);
-    // single-mesh CG: x += alpha_{i-1} p_{i-1} of the previous iteration,
-    // applied here where p_{i-1} is read anyway
-    bool xlag = false;
-    T aprev = T(0);
     constexpr bool strm = FUSED && NT;   // p and x non-temporal
-    if constexpr (FUSED) {
-        beta = (T)a.st->beta;
-        xlag = a.x != nullptr && a.st->x_lag != 0;
-        aprev = (T)a.st->alpha;
-    }
     // edge-array slots of the column (edge_slot): base ecb (-1 off the
     // border) holds k = 0, ecb + 1 holds k = N, and corner columns keep
     // k = 1 .. N-1 at ecb + 1 + k
@@ -682,8 +682,16 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
         __shared__ __align__(16) float sP[FUSED ? P3 : 4];   // next element's p
         __shared__ __align__(16) float sX[FUSED ? P3 : 4];   // next element's x
 
+        // the CG state in one round of loads: stop, beta, the lagged x step
+        T beta = T(0);
+        bool xlag = false;
+        T aprev = T(0);
         if constexpr (FUSED) {
-            if (a.st->stop) return;
+            const int stopped = a.st->stop;
+            beta = (T)a.st->beta;
+            xlag = a.x != nullptr && a.st->x_lag != 0;
+            aprev = (T)a.st->alpha;
+            if (stopped) return;
         }
         const int q = threadIdx.x;        // column (i, j) = (q & 7, q >> 3)
         const int i = q & 7, j = q >> 3;
@@ -696,15 +704,7 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
 #pragma unroll
         for (int l = 0; l < P; ++l)
             Dtab[l] = q < 8 ? a.D[q * P + l] : (q < 16 ? a.Dt[(q - 8) * P + l] : 0.f);
-        T beta = T(0);
-        bool xlag = false;
-        T aprev = T(0);
         constexpr bool strm = FUSED && NT;   // p and x non-temporal
-        if constexpr (FUSED) {
-            beta = (T)a.st->beta;
-            xlag = a.x != nullptr && a.st->x_lag != 0;
-            aprev = (T)a.st->alpha;
-        }
         const int ecb = edge_column_base(kOrder, i, j);
         const bool ecorner = (i == 0 || i == P - 1) && (j == 0 || j == P - 1);
         T xi_i = T(0), eta_j = T(0), wij = T(0);
@@ -911,8 +911,16 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
         __shared__ __align__(16) float sX[FUSED ? P3 : 4];   // next element's x
         __shared__ __align__(16) float sV[FUSED ? 32 : 4];   // next element's vertices
 
+        // the CG state in one round of loads: stop, beta, the lagged x step
+        T beta = T(0);
+        bool xlag = false;
+        T aprev = T(0);
         if constexpr (FUSED) {
-            if (a.st->stop) return;
+            const int stopped = a.st->stop;
+            beta = (T)a.st->beta;
+            xlag = a.x != nullptr && a.st->x_lag != 0;
+            aprev = (T)a.st->alpha;
+            if (stopped) return;
         }
         const int t = threadIdx.x;
         const bool active = t < P2;
@@ -930,15 +938,7 @@ __device__ __forceinline__ void ax_mfma10_body(const AxArgs<float> &a, const Bas
         // index c is (i, k) = (c % P, c / P)
         const int ipen = P * (c % P) + S * (c / P);     // + i
         const int jpen = (c % P) + S * (c / P);         // + P j
-        T beta = T(0);
-        bool xlag = false;
-        T aprev = T(0);
         constexpr bool strm = FUSED && NT;   // p and x non-temporal
-        if constexpr (FUSED) {
-            beta = (T)a.st->beta;
-            xlag = a.x != nullptr && a.st->x_lag != 0;
-            aprev = (T)a.st->alpha;
-        }
         const int ecb = edge_column_base(kOrder, i, j);
         const bool ecorner = (i == 0 || i == P - 1) && (j == 0 || j == P - 1);
         T xi_i = T(0), eta_j = T(0), wij = T(0);

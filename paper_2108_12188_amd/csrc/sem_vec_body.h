@@ -65,11 +65,14 @@ __device__ __forceinline__ void update_body(int64_t n, T *__restrict__ x, T *__r
                                             const uint8_t *__restrict__ mcode, CgState *st,
                                             double *partial, int64_t vb, int64_t vgrid,
                                             PcArgs<T> pc = PcArgs<T>{}) {
-    if (st->stop) return;
+    // the state's loads go out with the block's set-up; a stopped state
+    // returns before the first store to global memory (uniform)
+    const int stopped = st->stop;
+    const T a = (T)st->alpha;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
     weights_lds(cw);
-    const T a = (T)st->alpha;
+    if (stopped) return;
     double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
@@ -180,11 +183,14 @@ __device__ __forceinline__ void update_gather_body(int64_t n, T *__restrict__ r,
                                                    const GatherMap &gm, CgState *st,
                                                    double *partial, int64_t vb, int64_t vgrid,
                                                    PcArgs<T> pc = PcArgs<T>{}) {
-    if (st->stop) return;
+    // the state's loads go out with the block's set-up; a stopped state
+    // returns before the first store to global memory (uniform)
+    const int stopped = st->stop;
+    const T a = (T)st->alpha;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
     weights_lds(cw);
-    const T a = (T)st->alpha;
+    if (stopped) return;
     double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
@@ -341,13 +347,16 @@ __device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
                                                    const StructMap &sm, CgState *st,
                                                    double *partial, int64_t vb, int64_t vgrid,
                                                    PcArgs<T> pc = PcArgs<T>{}) {
-    if (st->stop) return;
+    // the state's loads go out with the block's set-up; a stopped state
+    // returns before the first store to global memory (uniform)
+    const int stopped = st->stop;
+    const T a = (T)st->alpha;
     __shared__ double cw[kVecThreads];
     __shared__ double red[16];
     __shared__ __align__(16) uint32_t pos[kMaxPosTab];
     for (int q = threadIdx.x; q < sm.p3; q += blockDim.x) pos[q] = sm.pos_tab[q];
     weights_lds(cw);
-    const T a = (T)st->alpha;
+    if (stopped) return;
     double acc = 0.0, acc2 = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = vgrid * blockDim.x;
@@ -435,22 +444,29 @@ __device__ __forceinline__ void update_struct_body(int64_t n, T *__restrict__ r,
 // preconditioned <r, z, c>; the stopping test and the history use <r, r, c>.
 __device__ __forceinline__ void finalize_rho_body(CgState *st, const double *partial, int cnt,
                                                   const double *partial2 = nullptr) {
-    if (st->stop) return;
+    // the state is read with the partials (one round of loads instead of
+    // three); a stopped state sums them and stores nothing
+    const int stopped = st->stop;
+    const double rho_prev = st->rho;
+    const int it = st->iter + 1;
+    const int fixed = st->fixed, max_iter = st->max_iter, hist_len = st->hist_len;
+    const double thresh = st->thresh;
+    double *const hist_rho = st->hist_rho;
     __shared__ double red[16];
     const double rho = sum_partials(partial, cnt, red);
     const double rr = partial2 ? sum_partials(partial2, cnt, red) : rho;
+    if (stopped) return;
     if (threadIdx.x == 0) {
-        const double beta = rho / st->rho;
+        const double beta = rho / rho_prev;
         st->beta = beta;
         st->rho = rho;
         st->rr = rr;
         st->x_lag = 1;
-        const int it = st->iter + 1;
         st->iter = it;
-        if (st->hist_rho && it < st->hist_len) st->hist_rho[it] = rr;
+        if (hist_rho && it < hist_len) hist_rho[it] = rr;
         if (!isfinite(rho) || !isfinite(rr)) st->stop = 3;
-        else if (!st->fixed && rr <= st->thresh) st->stop = 1;
-        else if (it >= st->max_iter) st->stop = 2;
+        else if (!fixed && rr <= thresh) st->stop = 1;
+        else if (it >= max_iter) st->stop = 2;
     }
 }
 
