@@ -60,12 +60,15 @@ using Fn64 = void (*)(bool, AxMode, const AxArgs<double> &, const double *, cons
 #endif
 constexpr int64_t kAxFusedMaxBlocks = SEM_AX_FUSED_MAX_BLOCKS;
 // the matrix-core form: blocks of one wave (N = 7; measured best of 8192,
-// 16384 and 32768) and of two waves (N = 9: 4096, ahead of 8192)
+// 16384 and 32768) and of two waves (N = 9: 1536, the blocks resident at
+// once at 3 waves per SIMD and 6 blocks per CU, ahead of 3072 and 4096 at
+// 10^3 ... 28^3 elements: every block walks its share of the elements
+// without a partial last round)
 #ifndef SEM_AX_MFMA_MAX_BLOCKS
 #define SEM_AX_MFMA_MAX_BLOCKS 16384
 #endif
 #ifndef SEM_AX_MFMA2_MAX_BLOCKS
-#define SEM_AX_MFMA2_MAX_BLOCKS 4096
+#define SEM_AX_MFMA2_MAX_BLOCKS 1536
 #endif
 constexpr int64_t kAxMfmaMaxBlocks = SEM_AX_MFMA_MAX_BLOCKS;
 constexpr int64_t kAxMfma2MaxBlocks = SEM_AX_MFMA2_MAX_BLOCKS;
