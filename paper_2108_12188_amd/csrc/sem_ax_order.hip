@@ -412,19 +412,18 @@ __device__ __forceinline__ void ax_body(const AxArgs<T> &a, const BasisK<T> &bk,
                                    nwave);
         }
     };
-    // the FP32 CG-fused form walks XCD-contiguously (measured faster: 24^3
-    // N = 5 +2.4%; FP64 CG 2.4% slower that way keeps launch order)
-    const int64_t tv0 = (FUSED && sizeof(T) == 4) ? xcd_first_tile(vb, vgrid) : vb;
     if constexpr (kDma) {
-        if (tv0 < ntiles) {
-            stage(tv0);
-            stage_x(tv0);
+        if (vb < ntiles) {
+            stage(vb);
+            stage_x(vb);
         }
     }
 
     double acc = 0.0;
-    // a tile is `epb` consecutive elements; the grid strides over tiles
-    for (int64_t tile = tv0; tile < ntiles; tile += vgrid) {
+    // a tile is `epb` consecutive elements; the grid strides over tiles (in
+    // launch order: the XCD-contiguous walk of the N = 7 matrix-core kernel
+    // measured slower here at every order)
+    for (int64_t tile = vb; tile < ntiles; tile += vgrid) {
         const int64_t e = tile * a.epb + el;
         const bool valid = (el < a.epb) && (e < a.E);
         const int64_t base = e * P3 + col;   // global index of (i, j, k=0)
@@ -723,9 +722,13 @@ __device__ __forceinline__ void ax_mfma_body(const AxArgs<float> &a, const Basis
                         reinterpret_cast<const float *>(a.x) + e * P3, sX);
             }
         };
-        // the CG-fused form walks XCD-contiguously (measured faster there;
-        // the plain operators, precomputed G most, keep launch order)
-        const int64_t ev0 = FUSED ? xcd_first_tile(vb, vgrid) : vb;
+        // the CG-fused form walks XCD-contiguously when every block takes
+        // the same number of elements (measured faster there; with a
+        // remainder, the contiguous ranges would leave the last round's
+        // elements to the first XCDs, and launch order spreads them); the
+        // plain operators, precomputed G most, keep launch order
+        const int64_t ev0 =
+            (FUSED && ntiles % vgrid == 0) ? xcd_first_tile(vb, vgrid) : vb;
         if (ev0 < ntiles) {
             if constexpr (kDma) stage(ev0);
         }

@@ -207,7 +207,14 @@ int elem_blocks(int64_t n) {
 
 int vec_blocks(int64_t n) {
     int64_t b = (n + 4 * kVecThreads - 1) / (4 * kVecThreads);
-    if (b > kVecMaxBlocks) b = kVecMaxBlocks;
+    if (b > kVecMaxBlocks) {
+        // as many blocks as give every block the same number of grid-stride
+        // steps (at most kVecMaxBlocks): the XCD-contiguous block ranges of
+        // the updates then end together (24^3 N = 9: 3375 blocks of four
+        // steps, update 42.1 against 45.5 us with 4096 of three or four)
+        const int64_t steps = (b + kVecMaxBlocks - 1) / kVecMaxBlocks;
+        b = (b + steps - 1) / steps;
+    }
     return (int)(b > 0 ? b : 1);
 }
 
