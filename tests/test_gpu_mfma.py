@@ -111,6 +111,36 @@ def test_mfma_operator_large_sampled():
     gm.close()
 
 
+def test_mfma_cg_large_uneven_grid():
+    """28^3 elements N = 7 (21952 elements: more than the fused operator's
+    16384 blocks and not a multiple of them, so its blocks walk in launch
+    order; the vector grid takes 3659 blocks of three equal grid-stride
+    steps): FP32 CG with G on the fly, 8 iterations, bitwise equal between
+    the matrix-core and VALU engines; the first rho is <r0, r0, c> of the
+    right-hand side in FP64 on the host."""
+    import torch
+    import paper_2108_12188_amd as sem
+    say("mfma cg 28^3 N=7")
+    mesh = box_mesh(28, 28, 28, 7, perturb=0.1, seed=2128)
+    gm = sem.Mesh.from_box(mesh, g_fp32=False)
+    bh = random_global_rhs(mesh, seed=79)
+    b = to_dev(bh, torch.float32)
+    out = {}
+    for eng in (sem.ENGINE_VALU, sem.ENGINE_MFMA):
+        with engine(sem, eng):
+            out[eng] = gm.cg_solve(b, prec=sem.FP32, geom=1, fixed_iters=8, history=9)
+    (xv, rv), (xm, rm) = out[sem.ENGINE_VALU], out[sem.ENGINE_MFMA]
+    assert rv["iters"] == rm["iters"] == 8
+    assert torch.equal(xv, xm)
+    assert np.array_equal(rv["hist_rho"], rm["hist_rho"])
+    # rho_0 = <r0, r0, c> for r0 = mask(b) and c = 1/multiplicity, by the
+    # oracle's mask, multiplicity and weighted dot (no geometric factors)
+    b32 = oracle.mask(mesh.dirichlet, bh.astype(np.float32).astype(np.float64))
+    m = oracle.multiplicity(mesh.glob_id, mesh.n_glob)
+    np.testing.assert_allclose(rm["hist_rho"][0], oracle.dot(b32, b32, m), rtol=1e-9)
+    gm.close()
+
+
 @pytest.mark.parametrize("N", [7, 9])
 @pytest.mark.parametrize("geom", [0, 1], ids=["pre", "otf"])
 @pytest.mark.parametrize("precond", [0, 1], ids=["cg", "jacobi"])
